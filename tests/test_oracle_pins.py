@@ -1,0 +1,473 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms
+(polynomial exactness), the stencils and 1D formulas printed in the paper, a LAPACK
+solve of the assembled system, the second-order accuracy the paper claims, and the
+convergence factors of its tables.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, default_grid, EDIVERGED, ENOCONV
+from workloads import geometry as geo, problems as pr
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _setup(dom, dim, n, nc, rule, **kw):
+    return Oracle(dom.nodal_phi(n), default_grid(dim, n, nc, **kw), rule)
+
+
+def _rhs(o, l, dom, sol, normal_override=None):
+    c, _ = o.cls(l)
+    G = o.ghosts(l)
+    n = o.info(l)["n"]
+    return pr.rhs_from_ghosts(o.dim, n, c, G["node"], G["B"], G["type"], sol, dom,
+                              normal_override=G["nB"] if normal_override == "discrete" else None)
+
+
+# ---------------------------------------------------------------------------------------
+# discretisation: Delta_h and the ghost rows (Sec. 2.3, Eq. (discrBC))
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [2, 3])
+def test_laplacian_exact_on_quadratics(dim):
+    rng = np.random.default_rng(3)
+    sol = pr.Polynomial(dim, rng)
+    dom = geo.Disk((0.05, -0.03), 0.6) if dim == 2 else geo.Torus(0.5, 0.25)
+    n = 32 if dim == 2 else 16
+    o = _setup(dom, dim, n, n // 2, pr.halfspace_rule([1.0] + [0.0] * (dim - 1)))
+    c, _ = o.cls(0)
+    P = geo.grid_points(dim, n)
+    u = sol.u(P)
+    rhs = np.where(c == 1, sol.f(P), 0.0)
+    r, _ = o.defect(0, u, rhs)
+    assert np.abs(r[c == 1]).max() < 1e-9 * np.abs(sol.f(P)).max() * n * n
+
+
+def _poly_family(dim, degree_kind, rng):
+    """Random polynomial in the family a rung must reproduce: 'tq' tensor-quadratic,
+    'tl' tensor-linear, 'lin' linear."""
+    if degree_kind == "tq":
+        C = rng.uniform(-1, 1, (3,) * dim)
+        powers = np.array(np.meshgrid(*([np.arange(3)] * dim), indexing="ij")).reshape(dim, -1).T
+    elif degree_kind == "tl":
+        C = rng.uniform(-1, 1, (2,) * dim)
+        powers = np.array(np.meshgrid(*([np.arange(2)] * dim), indexing="ij")).reshape(dim, -1).T
+    else:
+        C = rng.uniform(-1, 1, dim + 1)
+        powers = np.vstack([np.zeros(dim, int), np.eye(dim, dtype=int)])
+    coef = C.ravel()
+
+    def u(P):
+        return sum(cf * np.prod(P ** pw, axis=1) for cf, pw in zip(coef, powers))
+
+    def grad(P):
+        g = np.zeros_like(P)
+        for cf, pw in zip(coef, powers):
+            for a in range(dim):
+                if pw[a] == 0:
+                    continue
+                pa = pw.copy()
+                pa[a] -= 1
+                g[:, a] += cf * pw[a] * np.prod(P ** pa, axis=1)
+        return g
+
+    return u, grad
+
+
+RUNG_FAMILY = {1: "tq", 2: "tl", 3: "lin", 4: "lin"}
+
+
+@pytest.mark.parametrize("case", ["circle8", "circle16", "flower32", "disk64", "torus16"])
+def test_ghost_rows_polynomial_exactness(case):
+    """Rung 1 (3^d quadratic) is exact for tensor-quadratic u, rung 2 (2^d) for
+    tensor-linear, rungs 3-4 for linear u; Dirichlet rows reproduce u(B) and Neumann rows
+    grad u(B) . n_B.  Dirichlet weights sum to 1, Neumann weights to 0."""
+    if case == "circle8":
+        dom, dim, n = geo.paper_circle(), 2, 8
+    elif case == "circle16":
+        dom, dim, n = geo.paper_circle(), 2, 16
+    elif case == "flower32":
+        dom, dim, n = geo.Flower(0.5, 0.2, 5), 2, 32
+    elif case == "disk64":
+        dom, dim, n = geo.Disk((0.0, 0.0), 0.6), 2, 64
+    else:
+        dom, dim, n = geo.Torus(0.5, 0.25), 3, 16
+    o = _setup(dom, dim, n, n // 2, pr.paper_rule(dim))
+    G = o.ghosts(0)
+    P = geo.grid_points(dim, n)
+    rng = np.random.default_rng(7)
+    seen = set()
+    for rung, fam in RUNG_FAMILY.items():
+        m = G["rung"] == rung
+        if not m.any():
+            continue
+        seen.add(rung)
+        wn, w = G["wn"][m], G["w"][m]
+        B = G["B"][m][:, :dim]
+        nB = G["nB"][m][:, :dim]
+        if rung < 4:
+            u, grad = _poly_family(dim, fam, rng)
+            vals = np.where(wn >= 0, u(P[np.maximum(wn, 0)].reshape(-1, dim)).reshape(wn.shape),
+                            0.0)
+            Bu, Bg = u(B), grad(B)
+        else:
+            # the two-point rule interpolates along its own axis only: exact for
+            # u = c0 + c1 x_axis (value at the projection of B on that axis line)
+            used = np.sort(np.where(wn >= 0, wn, np.iinfo(np.int64).max), axis=1)[:, :2]
+            diff = np.abs(P[used[:, 1]] - P[used[:, 0]])
+            ax = np.argmax(diff, axis=1)
+            c0, c1 = rng.uniform(-1, 1, 2)
+            vals = np.where(wn >= 0, c0 + c1 * P[np.maximum(wn, 0)][..., 0] * 0 +
+                            c1 * np.take_along_axis(P[np.maximum(wn, 0)],
+                                                    ax[:, None, None].repeat(wn.shape[1], 1),
+                                                    axis=2)[..., 0], 0.0)
+            Bu = c0 + c1 * B[np.arange(len(B)), ax]
+            Bg = np.zeros_like(B)
+            Bg[np.arange(len(B)), ax] = c1
+        Lu = (w * vals).sum(axis=1)
+        target = np.where(G["type"][m] == 1, Bu, (Bg * nB).sum(axis=1))
+        scale = 1.0 + np.abs(w).sum(axis=1)
+        assert np.all(np.abs(Lu - target) < 1e-11 * scale), (case, rung)
+        sums = w.sum(axis=1)
+        D = G["type"][m] == 1
+        assert np.allclose(sums[D], 1.0, atol=1e-12)
+        assert np.allclose(sums[~D], 0.0, atol=1e-9 * n)
+    assert 1 in seen
+    if case == "circle8":
+        assert seen >= {1, 2}, "coarse circle exercises the reduced stencils"
+    if case == "flower32":
+        assert 4 in seen or 3 in seen or 2 in seen
+
+
+def test_neumann_normal_is_unit_and_outward():
+    o = _setup(geo.paper_circle(), 2, 64, 32, pr.paper_rule())
+    G = o.ghosts(0)
+    N = G["type"] == 0
+    nB = G["nB"][N][:, :2]
+    assert np.allclose((nB ** 2).sum(axis=1), 1.0, atol=1e-12)
+    exact = geo.paper_circle().normal(G["B"][N][:, :2])
+    assert np.all((nB * exact).sum(axis=1) > 0.999)
+
+
+def test_closest_point_on_exact_sdf():
+    """Eq. (clpt) on an exact SDF lands on the circle to second order."""
+    for n in (64, 128, 256):
+        o = _setup(geo.paper_circle(), 2, n, n // 2, pr.paper_rule())
+        G = o.ghosts(0)
+        dist = geo.paper_circle().phi(G["B"][:, :2])
+        assert np.abs(dist).max() < 2.0 * (2.0 / n) ** 2
+
+
+def test_1d_rows_match_left2_right2():
+    """Sec. 1.1: the Dirichlet row at a is the quadratic Lagrange interpolant,
+    Eq. (left2), with theta_l = (x_{l+1} - a)/h; the Neumann row at b is Eq. (right2) with
+    theta_r = (b - x_{r-1})/h."""
+    a, b, n = -0.743, 0.843, 64
+    o = _setup(geo.Interval(a, b), 1, n, 8, pr.halfspace_rule([-1.0], 0.0, False), lam=0)
+    G = o.ghosts(0)
+    h = 2.0 / n
+    x = -1.0 + h * np.arange(n + 1)
+    assert len(G["node"]) == 2
+    il, ir = sorted(range(2), key=lambda k: G["node"][k])
+    l = G["node"][il]
+    th = (x[l + 1] - a) / h
+    wl = dict(zip(G["wn"][il], G["w"][il]))
+    assert G["type"][il] == 1
+    assert np.isclose(wl[l], (1 + th) * th / 2, atol=1e-14)
+    assert np.isclose(wl[l + 1], (1 + th) * (1 - th), atol=1e-14)
+    assert np.isclose(wl[l + 2], -(1 - th) * th / 2, atol=1e-14)
+    r = G["node"][ir]
+    tr = (b - x[r - 1]) / h
+    wr = dict(zip(G["wn"][ir], G["w"][ir]))
+    assert G["type"][ir] == 0
+    assert np.isclose(wr[r], (0.5 + tr) / h, rtol=1e-12)
+    assert np.isclose(wr[r - 1], (-1 - (1 + 2 * tr) + 1) / h, rtol=1e-12) or \
+        np.isclose(wr[r - 1], -2 * tr / h, rtol=1e-12)
+    assert np.isclose(wr[r - 2], (tr - 0.5) / h, rtol=1e-12, atol=1e-12)
+    # constants mu_D dt = 0.9 and mu_N dt = 0.9 * 2h/3 (Sec. 1.1)
+    assert np.isclose(G["c"][il], 0.9) and np.isclose(G["c"][ir], 0.9 * 2 * h / 3)
+
+
+# ---------------------------------------------------------------------------------------
+# transfer operators (Sec. 2.5, 2.6)
+# ---------------------------------------------------------------------------------------
+def _load_golden_stencils():
+    out, cur, rows = {}, None, []
+    for line in open(os.path.join(GOLDEN, "restriction_stencils.txt")):
+        line = line.strip()
+        if line.startswith("# name:"):
+            cur = line.split()[2]
+            rows = []
+        elif line and not line.startswith("#"):
+            rows.append([float(v) for v in line.split()])
+            if len(rows) == 3:
+                out[cur] = np.array(rows) / 16.0
+    return out
+
+
+def _box_matrix(lo, hi):
+    """3x3 weight matrix (rows y = +1, 0, -1; columns x = -1, 0, +1) of a box."""
+    def w1(l, h):
+        if l == -1 and h == 1:
+            return {-1: 0.25, 0: 0.5, 1: 0.25}
+        if l == h:
+            return {0: 1.0}
+        return {l: 0.5, h: 0.5}
+    wx, wy = w1(lo[0], hi[0]), w1(lo[1], hi[1])
+    M = np.zeros((3, 3))
+    for ky, vy in wy.items():
+        for kx, vx in wx.items():
+            M[1 - ky, kx + 1] = vx * vy
+    return M
+
+
+def test_restriction_boxes_reproduce_printed_stencils():
+    gold = _load_golden_stencils()
+    variants = []
+    for name, S in gold.items():
+        for k in range(4):
+            R = np.rot90(S, k)
+            variants += [(name, R), (name, R[:, ::-1])]
+    o = _setup(geo.paper_circle(), 2, 64, 8, pr.paper_rule(), split=0)
+    lo, hi = o.boxes(0)
+    cc, _ = o.cls(1)
+    c, _ = o.cls(0)
+    kinds = set()
+    for X in np.where(cc == 1)[0]:
+        M = _box_matrix(lo[X], hi[X])
+        assert np.isclose(M.sum(), 1.0)
+        match = [nm for nm, V in variants if np.allclose(M, V)]
+        assert match, (X, M)
+        kinds.add(match[0])
+        # the full stencil exactly when the whole neighbourhood is interior
+        jx, jy = (X % 33) * 2, (X // 33) * 2
+        nb = [c[(jy + dy) * 65 + jx + dx] == 1 for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+        assert (match[0] == "full") == all(nb)
+    assert kinds == {"full", "3x2", "2x2"}
+
+
+def test_full_weighting_exact_on_bilinear():
+    o = _setup(geo.paper_circle(), 2, 64, 8, pr.paper_rule(), split=0)
+    P = geo.grid_points(2, 64)
+    r = 0.3 + 0.7 * P[:, 0] - 0.2 * P[:, 1] + 0.5 * P[:, 0] * P[:, 1]
+    rc = o.restrict(0, r)
+    Pc = geo.grid_points(2, 32)
+    cc, _ = o.cls(1)
+    lo, hi = o.boxes(0)
+    full = (cc == 1) & (lo[:, 0] == -1) & (hi[:, 0] == 1) & (lo[:, 1] == -1) & (hi[:, 1] == 1)
+    exact = 0.3 + 0.7 * Pc[:, 0] - 0.2 * Pc[:, 1] + 0.5 * Pc[:, 0] * Pc[:, 1]
+    assert np.abs(rc[full] - exact[full]).max() < 1e-14
+    # every partial stencil reproduces constants
+    rc1 = o.restrict(0, np.ones(len(P)))
+    assert np.allclose(rc1[cc > 0], 1.0, atol=1e-14)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_prolongation_exact_on_multilinear(dim):
+    dom = geo.paper_circle() if dim == 2 else geo.Torus(0.5, 0.25)
+    n = 32
+    o = _setup(dom, dim, n, n // 2, pr.paper_rule(dim))
+    c, _ = o.cls(0)
+    cc, _ = o.cls(1)
+    Pc = geo.grid_points(dim, n // 2)
+    P = geo.grid_points(dim, n)
+    coef = np.random.default_rng(2).uniform(-1, 1, 2 ** dim)
+
+    def ml(Q):
+        out = np.zeros(len(Q))
+        for m in range(2 ** dim):
+            t = np.ones(len(Q))
+            for a in range(dim):
+                if (m >> a) & 1:
+                    t = t * Q[:, a]
+            out += coef[m] * t
+        return out
+
+    ec = np.where(cc > 0, ml(Pc), 0.0)
+    u = np.zeros(len(P))
+    o.prolong(0, ec, u)
+    # fine unknowns whose coarse neighbours are all unknowns get the exact value
+    ok = np.zeros(len(P), bool)
+    J = np.array(np.unravel_index(np.arange(len(P)), (n + 1,) * dim, order="F")).T
+    for i in np.where(c > 0)[0]:
+        lists = [[J[i, a] // 2] if J[i, a] % 2 == 0 else [(J[i, a] - 1) // 2, (J[i, a] + 1) // 2]
+                 for a in range(dim)]
+        idx = np.array(np.meshgrid(*lists, indexing="ij")).reshape(dim, -1)
+        flat = sum(idx[a] * (n // 2 + 1) ** a for a in range(dim))
+        ok[i] = np.all(cc[flat] > 0)
+    assert ok.sum() > (0.9 if dim == 2 else 0.6) * (c > 0).sum()
+    assert np.abs(u[ok] - ml(P[ok])).max() < 1e-13
+    u1 = np.zeros(len(P))
+    o.prolong(0, np.where(cc > 0, 1.0, 0.0), u1)
+    assert np.allclose(u1[c > 0], 1.0, atol=1e-14)
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_extension_keeps_constants(split):
+    """The steady state of Eq. (exp) carries a constant ghost defect unchanged along the
+    normals to every node of the extension set."""
+    o = _setup(geo.Flower(0.5, 0.15, 5), 2, 128, 32, pr.flower().rule, split=split)
+    c, _ = o.cls(0)
+    E = o.extension(0)
+    assert len(E["node"]) > 0
+    r = np.where(c == 2, 2.5, 0.0)
+    o.extend(0, r)
+    has_src = (E["src"] >= 0).any(axis=1)
+    assert has_src.mean() > 0.99
+    assert np.allclose(r[E["node"][has_src]], 2.5, atol=1e-14)
+    # every outside node of the 3x3 neighbourhood of a coarse ghost is in the set
+    cc, _ = o.cls(1)
+    nb = set()
+    for X in np.where(cc == 2)[0]:
+        jx, jy = X % 65 * 2, X // 65 * 2
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                P = (jy + dy) * 129 + jx + dx
+                if c[P] == 0:
+                    nb.add(P)
+    assert nb == set(E["node"].tolist())
+    # processing order: increasing phi
+    phi = o.phi[E["node"]]
+    assert np.all(np.diff(phi) >= 0)
+
+
+# ---------------------------------------------------------------------------------------
+# the discrete system Eq. (discr) and its solution
+# ---------------------------------------------------------------------------------------
+def test_patch_test_quadratic_reproduced():
+    """Quadratic u with Neumann data from the discrete normal n_B: every row is exact, so
+    the unique discrete solution is u itself."""
+    rng = np.random.default_rng(11)
+    sol = pr.Polynomial(2, rng)
+    dom = geo.Disk((0.02, 0.01), 0.6)
+    o = _setup(dom, 2, 64, 8, pr.halfspace_rule([0.0, 1.0]))
+    G = o.ghosts(0)
+    assert np.all(G["rung"] == 1)
+    rhs = _rhs(o, 0, dom, sol, normal_override="discrete")
+    u = o.direct_solve(rhs)
+    c, _ = o.cls(0)
+    P = geo.grid_points(2, 64)
+    assert np.abs(u - sol.u(P))[c > 0].max() < 1e-10
+
+
+def test_dense_assembly_and_lapack_solve_match_multigrid():
+    dom = geo.Disk((0.0, 0.0), 0.6)
+    w = pr.disk64()
+    o = _setup(dom, 2, 16, 4, w.rule)
+    c, _ = o.cls(0)
+    rhs = _rhs(o, 0, dom, w.solution)
+    A, rowmap = o.assemble(0)
+    # the assembled rows are the residual operator applied to unit vectors
+    nn = len(c)
+    cols = []
+    for j in rowmap:
+        e = np.zeros(nn)
+        e[j] = 1.0
+        r, _ = o.defect(0, e, np.zeros(nn))
+        cols.append(-r[rowmap])
+    Adef = np.array(cols).T
+    assert np.allclose(Adef, A.toarray(), atol=1e-12 * np.abs(Adef).max())
+    x = np.linalg.solve(Adef, rhs[rowmap])
+    st, u, hist = o.solve(rhs, tol=1e-13, max_cycles=60)
+    assert st == 0
+    assert np.abs(u[rowmap] - x).max() < 1e-11 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("wname", ["disk", "flower"])
+def test_second_order_manufactured(wname):
+    errs = []
+    # the flower resolves its petals from N = 512 on (errors 1.4e-3, 6.3e-4, 2.2e-4, 5.8e-5
+    # at N = 128 ... 1024 with this oracle); the asymptotic ratio is measured there
+    ns = (64, 128, 256) if wname == "disk" else (512, 1024)
+    for n in ns:
+        w = pr.disk64() if wname == "disk" else pr.flower(n, 32)
+        o = _setup(w.domain, 2, n, 4 if wname == "disk" else 32, w.rule)
+        rhs = _rhs(o, 0, w.domain, w.solution)
+        st, u, _ = o.solve(rhs, tol=1e-9, max_cycles=80)
+        assert st == 0
+        c, _ = o.cls(0)
+        errs.append(np.abs(u - w.solution.u(geo.grid_points(2, n)))[c == 1].max())
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    order = np.log2(errs[0] / errs[-1]) / (len(errs) - 1)
+    assert order > 1.75, (errs, ratios)
+    assert all(2.5 < r < 6.0 for r in ratios), ratios
+
+
+def test_torus_second_order():
+    w = pr.torus(16, 8)
+    errs = []
+    for n in (16, 32):
+        o = _setup(w.domain, 3, n, 8, w.rule)
+        rhs = _rhs(o, 0, w.domain, w.solution)
+        st, u, _ = o.solve(rhs, tol=1e-11, max_cycles=80)
+        assert st == 0
+        c, _ = o.cls(0)
+        errs.append(np.abs(u - w.solution.u(geo.grid_points(3, n)))[c == 1].max())
+    assert errs[0] / errs[1] > 2.5, errs
+
+
+def test_solver_failure_codes():
+    w = pr.disk64()
+    o = _setup(w.domain, 2, 32, 4, w.rule)
+    rhs = _rhs(o, 0, w.domain, w.solution)
+    st, _, _ = o.solve(rhs, tol=1e-12, max_cycles=2)
+    assert st == ENOCONV
+    bad = rhs.copy()
+    bad[np.argmax(np.abs(bad))] = np.nan
+    st, _, _ = o.solve(bad, tol=1e-12, max_cycles=10)
+    assert st == EDIVERGED
+
+
+# ---------------------------------------------------------------------------------------
+# convergence factors of Sec. 3 (GS-LEX, paper composite restriction)
+# ---------------------------------------------------------------------------------------
+def _rho(dom, dim, n, nc, nu1, nu2, gamma, lam, rule):
+    o = _setup(dom, dim, n, nc, rule, nu1=nu1, nu2=nu2, gamma=gamma, lam=lam, ordering=0,
+               split=0)
+    c, _ = o.cls(0)
+    u0 = np.where(c > 0, np.random.default_rng(1).uniform(-1, 1, c.size), 0.0)
+    return o.rho(u0)[0]
+
+
+def test_rho_circle_without_extra_sweeps_w_cycle():
+    """Table badrho, W-cycle columns (lambda = 0): 0.71/0.68/0.70 (nu 1+1) and
+    0.58/0.59/0.60 (nu 2+1) at N = 64/128/256."""
+    dom, rule = geo.paper_circle(), pr.paper_rule()
+    paper = {(1, 1): (0.71, 0.68, 0.70), (2, 1): (0.58, 0.59, 0.60)}
+    for (a, b), vals in paper.items():
+        for n, p in zip((64, 128, 256), vals):
+            r = _rho(dom, 2, n, 8, a, b, 2, 0, rule)
+            assert abs(r - p) < 0.12, (a, b, n, r, p)
+
+
+def test_rho_circle_with_extra_sweeps():
+    """Table rhoC (lambda = 5, delta = 3h, W-cycle, Nc = 8): nu = 3 gives 0.09/0.08/0.08 at
+    N = 64/128/256, near the LFA value 0.119 of Table rholoc; lambda = 5 improves on the
+    lambda = 0 factors by a wide margin."""
+    dom, rule = geo.paper_circle(), pr.paper_rule()
+    for n, p in zip((64, 128, 256), (0.09, 0.08, 0.08)):
+        r = _rho(dom, 2, n, 8, 2, 1, 2, 5, rule)
+        assert abs(r - p) < 0.035, (n, r, p)
+    for n, p in zip((64, 128, 256), (0.11, 0.13, 0.14)):
+        r2 = _rho(dom, 2, n, 8, 1, 1, 2, 5, rule)
+        r0 = _rho(dom, 2, n, 8, 1, 1, 2, 0, rule)
+        assert r2 < p + 0.08 and r2 < 0.4 * r0, (n, r2, r0)
+
+
+def test_rho_flower_coarsest_8_does_not_converge():
+    """Table rhoSF3: the flower does not converge with Nc = 8."""
+    dom, rule = geo.Flower(0.5, 0.2, 5), pr.paper_rule()
+    for n in (32, 64):
+        assert _rho(dom, 2, n, 8, 2, 1, 2, 5, rule) > 1.0
+
+
+def test_rho_1d_matches_lfa_scale():
+    """Sec. 3.1: [a, b] = [-0.743, 0.843], N = 64, Nc = 8; the paper reports 0.185 (nu = 2)
+    and 0.122 (nu = 3), close to the LFA values.  The oracle's factors are no worse."""
+    dom, rule = geo.Interval(-0.743, 0.843), pr.halfspace_rule([-1.0], 0.0, False)
+    r2 = _rho(dom, 1, 64, 8, 1, 1, 2, 0, rule)
+    r3 = _rho(dom, 1, 64, 8, 2, 1, 2, 0, rule)
+    assert 0.02 < r2 < 0.185 + 0.03 and 0.02 < r3 < 0.122 + 0.03 and r3 < r2
