@@ -1,0 +1,158 @@
+"""Benchmark: unknowns/s to 1e-10 relative residual on one MI355X.
+
+Workload (the single-GPU headline configuration): 2D flower r < 0.5 + 0.15 sin(5 theta)
+on [-1, 1]^2 with 2048 x 2048 intervals, Dirichlet where x > 0 and Neumann elsewhere,
+manufactured u = sin(3x) cos(2y) + x y, V(2,1) cycles with lambda = 5 boundary sweeps down
+to a 32 x 32 coarsest grid, zero initial guess, until ||r||_inf / ||(f_h, g_h)||_inf <= 1e-10.
+One step = one complete solve (mg_solve) with inputs resident in HBM.
+
+Prints one JSON line on stdout.  Extra fields: the FP32-in-FP64 defect-correction solve of
+the same problem, the roofline of the dominant kernel (the fine-level red-black
+relaxation) and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "unknowns/s to 1e-10 rel. residual: plain FP64 vs FP32+learned guess; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dc", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the solver runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1111_0983_amd import ghostmg as gm
+    from workloads import geometry as geo, problems as pr
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    w = pr.flower(n, 32)
+    t0 = time.time()
+    phi = w.domain.nodal_phi(n)
+    log(f"[bench] phi {n}^2 in {time.time() - t0:.1f}s")
+    grid = gm.mg_grid_default(2, n, 32)
+    t0 = time.time()
+    s = gm.Solver(torch.from_numpy(phi).to(dev), [w.rule], grid)
+    setup_s = time.time() - t0
+    c = s.classes()
+    G = s.ghosts()
+    P = geo.grid_points(2, n)
+    f = torch.from_numpy(np.where(c == 1, w.solution.f(P), 0.0)).to(dev)
+    g = torch.from_numpy(pr.rhs_from_ghosts(2, n, c, G["node"], G["B"], G["type"],
+                                            w.solution, w.domain)).to(dev)
+    unknowns = int((c > 0).sum())
+    u = torch.zeros_like(f)
+    log(f"[bench] setup {setup_s:.2f}s, {unknowns} unknowns, {s.nlev} levels")
+
+    def step(solver, uu):
+        uu.zero_()
+        info = solver.solve(f, g, uu, tol=1e-10)
+        return info
+
+    for _ in range(args.warmup):
+        info = step(s, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = step(s, u)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = 1e3 * dt / args.steps
+    value = unknowns * args.steps / dt
+    err = float(np.abs(u.cpu().numpy() - w.solution.u(P))[c == 1].max())
+    log(f"[bench] FP64: {ms:.2f} ms/solve, {info['cycles']} cycles, rel {info['rel']:.2e}, "
+        f"error vs exact {err:.2e}")
+
+    # roofline of the dominant kernel: fine-level red-black relaxation
+    k_ms, k_bytes = s.time_kernel("smooth", 0, 50)
+    achieved = k_bytes / (k_ms * 1e-3) / 1e9
+    rd_ms, rd_bytes = s.time_kernel("defect", 0, 50)
+    band_ms, _ = s.time_kernel("band", 0, 20)
+    roof = {"bound": "hbm", "kernel": "k_smooth<2,double> (level 0)", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None, "avg_us": round(k_ms * 1e3, 2), "bytes_per_launch": k_bytes,
+            "defect_GBs": round(rd_bytes / (rd_ms * 1e-3) / 1e9, 1),
+            "band_kernel_us": round(band_ms * 1e3, 2)}
+
+    extra = {}
+    if not args.no_dc:
+        gdc = gm.mg_grid_default(2, n, 32, precision=gm.MG_FP32_DC, inner_cycles=2)
+        sdc = gm.Solver(torch.from_numpy(phi).to(dev), [w.rule], gdc)
+        udc = torch.zeros_like(f)
+        for _ in range(args.warmup):
+            idc = step(sdc, udc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            idc = step(sdc, udc)
+        torch.cuda.synchronize()
+        dtdc = time.perf_counter() - t0
+        diff = float((udc - u).abs().max().item() / u.abs().max().item())
+        extra = {"fp32dc_unknowns_per_s": unknowns * args.steps / dtdc,
+                 "fp32dc_ms_per_step": 1e3 * dtdc / args.steps,
+                 "fp32dc_cycles": idc["cycles"], "fp32dc_outer": idc["outer"],
+                 "fp32dc_rel_residual": idc["rel"], "fp32dc_vs_fp64_rel_diff": diff}
+        log(f"[bench] FP32-DC: {1e3 * dtdc / args.steps:.2f} ms/solve, {idc['cycles']} FP32 "
+            f"cycles in {idc['outer']} steps, diff vs FP64 {diff:.2e}")
+        sdc.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import Oracle, default_grid
+
+        t0 = time.perf_counter()
+        o = Oracle(phi, default_grid(2, n, 32), w.rule)
+        oc, _ = o.cls(0)
+        OG = o.ghosts(0)
+        rhs = pr.rhs_from_ghosts(2, n, oc, OG["node"], OG["B"], OG["type"], w.solution, w.domain)
+        t1 = time.perf_counter()
+        st, uo, hist = o.solve(rhs, tol=1e-10, max_cycles=60)
+        t2 = time.perf_counter()
+        cpu = {"value": unknowns / (t2 - t1), "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+               "sample": f"one complete FP64 red-black V(2,1) solve of the same {n}^2 flower "
+                         f"problem to 1e-10 ({len(hist) - 1} cycles, {t2 - t1:.1f} s, status "
+                         f"{st}; setup {t1 - t0:.1f} s not counted)"}
+        d = float(np.abs(uo - u.cpu().numpy()).max() / np.abs(uo).max())
+        cpu["gpu_vs_oracle_rel_diff"] = d
+        log(f"[bench] oracle: {t2 - t1:.1f}s, GPU vs oracle {d:.2e}")
+
+    out = {"metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"flower-{n} 2D FP64 V(2,1) lambda=5 Nc=32 tol=1e-10 zero guess",
+                      "n": n, "unknowns": unknowns, "cycles": info["cycles"],
+                      "rel_residual": info["rel"], "max_error_vs_exact": err,
+                      "setup_s": round(setup_s, 3), "parallelism": "single GPU"},
+           "roofline": roof, "cpu_baseline": cpu}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+/*
+ * ghostmg.h -- C ABI of the MI355X (gfx950) ghost-cell multigrid Poisson solver.
+ *
+ * The solver computes the unique solution of the discrete system of Coco and Russo,
+ * arXiv 1111.0983, Eq. (discr): the 5-point (2D) or 7-point (3D) Laplacian
+ * -Delta_h u = f at the interior nodes Omega_h = {phi < 0} and the boundary rows
+ * L_h u = g at the ghost nodes Gamma_h (Sec. 2.3, Eqs. (clpt), (St_G), (discrBC)),
+ * for a domain given by a signed distance function phi sampled at the nodes of the box
+ * [lo, hi]^dim (Sec. 2.2).  It iterates the multigrid cycle of Sec. 2.4 - 2.6 (red-black
+ * relaxation of Eqs. (jac2d), (dir2d), (neu2d), the lambda extra boundary sweeps of
+ * Sec. 3.2, defect extension Eq. (exp), partial full-weighting restriction
+ * Eqs. (Fstencil)-(Fstencil22), multilinear interpolation, exact coarsest solve) on the
+ * GPU until ||r||_inf / ||(f_h, g_h)||_inf <= tol.
+ *
+ * Layout of every node array: (n+1)^dim FP64 values per problem, x fastest, then y, then
+ * z; problems of a batch are consecutive.  Node j has coordinates lo + h j, h = (hi-lo)/n.
+ *
+ * Ownership: the caller owns every pointer it passes; the handle owns all level data and
+ * keeps no reference to caller memory after a call returns.  Calls on one handle are not
+ * thread-safe; work is ordered on the handle's stream (mg_set_stream, default the null
+ * stream).  Every call returns MG_OK (0) or a negative mg_status; no C++ exception
+ * crosses this interface.  mg_strerror() names a code.
+ */
+#ifndef GHOSTMG_H
+#define GHOSTMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_handle_s* mg_handle_t;
+
+enum mg_status {
+  MG_OK = 0,
+  MG_EINVAL = -1,     /* bad argument: grid sizes, NaN input, null pointer */
+  MG_ENOMEM = -2,     /* host or device allocation failed */
+  MG_EHIP = -3,       /* a HIP runtime call failed */
+  MG_EGEOM = -4,      /* unusable geometry: empty coarsest level, zero normal, singular
+                         coarsest matrix (e.g. a component with no Dirichlet ghost) */
+  MG_ENOCONV = -5,    /* max_cycles reached before the tolerance */
+  MG_EDIVERGED = -6   /* non-finite residual, or growth over five consecutive cycles */
+};
+
+enum mg_precision {
+  MG_FP64 = 0,        /* every cycle in FP64 */
+  MG_FP32_DC = 1      /* FP32 cycles on the correction inside an FP64 defect correction */
+};
+
+typedef struct {
+  int dim;            /* 2 or 3 */
+  int n;              /* intervals per axis on the finest grid */
+  double lo, hi;      /* the box [lo, hi]^dim; the domain must not touch its faces */
+  int n_coarse;       /* intervals on the coarsest grid; n = n_coarse * 2^L */
+  int nu1, nu2;       /* pre- and post-relaxations (V(2,1): 2, 1) */
+  int gamma;          /* 1 = V-cycle, 2 = W-cycle (Sec. 1.3, Remarks 1-2) */
+  int lambda;         /* extra boundary sweeps per relaxation (Sec. 3.2: 5) */
+  double delta_h;     /* band width in units of h (Sec. 3.2: 3) */
+  double cD;          /* mu_D dt of Eq. (dir2d) (0.9) */
+  double cN;          /* mu_N dt = cN h of Eq. (neu2d) (0.9 * 2 / (3 sqrt(dim))) */
+  int split;          /* 1: Dirichlet and Neumann defects are extended and restricted
+                         separately; 0: one outside pass over D_h - Omega_h */
+  int precision;      /* mg_precision */
+  int inner_cycles;   /* FP32 cycles per defect-correction step (MG_FP32_DC) */
+  int max_cycles;     /* cycle budget of mg_solve (FP64 cycles, or FP32 cycles in DC) */
+  int batch;          /* independent problems solved together (>= 1) */
+} mg_grid;
+
+/* Dirichlet at a ghost iff a . B + c > 0 (strict) or >= 0 (not strict), B its closest
+ * boundary point (Sec. 2.1: the partition of the boundary into Gamma_D and Gamma_N). */
+typedef struct {
+  double a[3];
+  double c;
+  int strict;
+} mg_bc_rule;
+
+typedef struct {
+  int status;           /* the call's return code */
+  int cycles;           /* multigrid cycles run (FP32 cycles in DC mode) */
+  int outer;            /* defect-correction steps (DC mode), else 0 */
+  double rel_residual;  /* final max over problems of ||r||_inf / ||(f_h, g_h)||_inf */
+  double solve_ms;      /* wall time of the call on its stream */
+  const double* history;/* per cycle (or DC step) relative residual, max over problems;
+                           owned by the handle, valid until the next solve or mg_free */
+  int history_len;
+} mg_stats;
+
+/* Fill *g with the paper's constants (lambda 5, delta 3h, mu dt 0.9 / 0.9 * 2h/(3 sqrt d)),
+ * V(2,1), FP64, batch 1, box [-1, 1]^dim. */
+int mg_grid_default(mg_grid* g, int dim, int n, int n_coarse);
+
+/* Build the level hierarchy (Sec. 2.4: each grid rediscretises the problem from phi at its
+ * nodes).  phi: batch * (n+1)^dim values, host or device memory, negative inside.
+ * bc: batch rules (host memory).  On success *out receives a new handle. */
+int mg_setup(const double* phi, const mg_bc_rule* bc, const mg_grid* grid, mg_handle_t* out);
+
+/* Order all later work of the handle on this hipStream_t (NULL = null stream). */
+int mg_set_stream(mg_handle_t h, void* hip_stream);
+
+/* Level sizes: info[0] n, [1] interior nodes, [2] ghost nodes, [3] interior band nodes,
+ * [4] extension nodes, [5] tiles, [6] coarsest unknowns (last level only), [7] levels;
+ * summed over the batch. */
+int mg_query_level(mg_handle_t h, int level, int64_t* info);
+
+/* Ghost points of one problem on one level, in increasing node index.  Two-call use: with
+ * node == NULL only *count is written.  node: node index within the problem; B, nB: 3
+ * values per ghost (closest point, unit normal at B used by Neumann rows); type: 1
+ * Dirichlet, 0 Neumann; rung: stencil rung 1..4.  Host memory. */
+int mg_query_ghosts(mg_handle_t h, int problem, int level, int64_t* count, int64_t* node,
+                    double* B, double* nB, int8_t* type, int8_t* rung);
+
+/* Node classes of one problem on one level: 0 outside, 1 interior, 2 ghost (host memory,
+ * (n_level+1)^dim bytes). */
+int mg_query_classes(mg_handle_t h, int problem, int level, int8_t* cls);
+
+/* Solve to ||r||_inf <= tol ||(f_h, g_h)||_inf.  f: read on Omega_h; g: read on Gamma_h
+ * (g(B) at ghost G); u: in/out initial guess, on return the solution on Omega_h u Gamma_h
+ * and 0 elsewhere.  Device memory, batch * (n+1)^dim FP64 each.  st may be NULL. */
+int mg_solve(mg_handle_t h, const double* f, const double* g, double* u, double tol,
+             mg_stats* st);
+
+/* Exactly ncycles cycles from u, no tolerance test (iterate-level checks). */
+int mg_cycles(mg_handle_t h, const double* f, const double* g, double* u, int ncycles);
+
+/* Defect r = (f + Delta_h u on Omega_h, g - L_h u on Gamma_h, 0 elsewhere) of the finest
+ * level (Sec. 2.4 step 3); r may be NULL.  norms (host, 2 * batch values): the infinity
+ * norms of the interior and ghost parts per problem. */
+int mg_residual(mg_handle_t h, const double* f, const double* g, const double* u, double* r,
+                double* norms);
+
+/* Time one kernel of the cycle at one level on the handle's stream with HIP events,
+ * launched reps times after one warm-up; kernel 0 = red-black interior relaxation,
+ * 1 = defect, 2 = restriction, 3 = interpolation + correction, 4 = boundary band sweeps.
+ * avg_ms: mean duration; bytes: the kernel's algorithmic HBM bytes per launch (every
+ * array element it must read or write once). */
+int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_ms,
+                   double* bytes);
+
+void mg_free(mg_handle_t h);
+
+const char* mg_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GHOSTMG_H */

@@ -447,6 +447,14 @@ static int build_level_geometry(ohandle* H, int l) {
     }
   }
   if (L->nint == 0) return ORC_EGEOM;
+  /* the domain must not touch the faces of the box (Sec. 2.1) */
+  for (int64_t i = 0; i < L->nn; ++i) {
+    if (L->cls[i] != ORC_IN) continue;
+    int j[3];
+    to_j(L, d, i, j);
+    for (int a = 0; a < d; ++a)
+      if (j[a] == 0 || j[a] == L->n) return ORC_EGEOM;
+  }
   int rc = build_ghosts(H, l);
   if (rc) return rc;
   L->lab = (int8_t*)malloc((size_t)L->nn);

@@ -1,0 +1,604 @@
+// C ABI of the ghost-cell multigrid solver: hierarchy upload, the cycle driver (captured
+// once into HIP graphs), the solve loop with its stopping test, and the query entry points.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "kernels.h"
+
+using namespace ghostmg;
+
+namespace {
+
+#define HIP_TRY(x)                       \
+  do {                                   \
+    if ((x) != hipSuccess) return MG_EHIP; \
+  } while (0)
+
+template <typename T>
+int upload(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  if (src.empty()) return MG_OK;
+  if (hipMalloc((void**)dst, src.size() * sizeof(T)) != hipSuccess) return MG_ENOMEM;
+  if (hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return MG_EHIP;
+  return MG_OK;
+}
+
+template <typename T>
+int alloc_zero(T** dst, size_t n) {
+  *dst = nullptr;
+  if (!n) return MG_OK;
+  if (hipMalloc((void**)dst, n * sizeof(T)) != hipSuccess) return MG_ENOMEM;
+  if (hipMemset(*dst, 0, n * sizeof(T)) != hipSuccess) return MG_EHIP;
+  return MG_OK;
+}
+
+int max_span(const std::vector<int32_t>& off) {
+  int m = 0;
+  for (size_t i = 0; i + 1 < off.size(); ++i) m = std::max(m, off[i + 1] - off[i]);
+  return m;
+}
+
+// Per-problem band + ghost work that one workgroup handles within its barriers; larger
+// boundary bands (3D) are swept by one launch per phase instead.
+constexpr int kSingleWgBand = 24576;
+constexpr int kSingleWgExt = 24576;
+constexpr int kMaxCoarse = 8192;
+
+int upload_level(mg_handle_s* H, int l) {
+  const HostLevel& S = H->host[l];
+  DevLevel& L = H->dev[l];
+  const size_t nn = (size_t)H->batch * S.g.npp;
+  const bool dc = H->grid.precision == MG_FP32_DC;
+  L.g = S.g;
+  L.ntiles = (int)S.tiles.size();
+  L.nghost = (int)S.ghosts.size();
+  L.nred = (int)S.red.size();
+  L.nblack = (int)S.black.size();
+  L.next = (int)S.ext.size();
+  L.gdag_off = S.gdag_off;
+  L.max_gp = max_span(S.ghost_off);
+  L.max_bandp = max_span(S.red_off) + max_span(S.black_off);
+  L.max_extp = max_span(S.ext_off);
+  int rc;
+  if ((rc = upload(&L.cls, S.cls))) return rc;
+  if ((rc = upload(&L.phi, S.phi))) return rc;
+  if ((rc = upload(&L.tiles, S.tiles))) return rc;
+  if ((rc = upload(&L.ghosts, S.ghosts))) return rc;
+  if ((rc = upload(&L.ghost_off, S.ghost_off))) return rc;
+  if ((rc = upload(&L.red, S.red))) return rc;
+  if ((rc = upload(&L.black, S.black))) return rc;
+  if ((rc = upload(&L.red_off, S.red_off))) return rc;
+  if ((rc = upload(&L.black_off, S.black_off))) return rc;
+  if ((rc = upload(&L.ext, S.ext))) return rc;
+  if ((rc = upload(&L.ext_merged, S.ext_merged))) return rc;
+  if ((rc = upload(&L.ext_off, S.ext_off))) return rc;
+  if ((rc = upload(&L.dag_off, S.dag_off))) return rc;
+  if ((rc = upload(&L.dag_start, S.dag_start))) return rc;
+  if ((rc = upload(&L.rcode, S.rcode))) return rc;
+  const bool need64 = !dc || l == 0;
+  if (need64) {
+    if ((rc = alloc_zero(&L.u64, nn))) return rc;
+    if ((rc = alloc_zero(&L.rhs64, nn))) return rc;
+    if ((rc = alloc_zero(&L.r64, nn))) return rc;
+    if ((rc = alloc_zero(&L.gtmp64, (size_t)L.nghost + 1))) return rc;
+  }
+  if (dc) {
+    if ((rc = alloc_zero(&L.u32, nn))) return rc;
+    if ((rc = alloc_zero(&L.rhs32, nn))) return rc;
+    if ((rc = alloc_zero(&L.r32, nn))) return rc;
+    if ((rc = alloc_zero(&L.gtmp32, (size_t)L.nghost + 1))) return rc;
+  }
+  if (l == H->L) {
+    L.nu_max = max_span(S.umap_off);
+    if ((rc = upload(&L.umap, S.umap))) return rc;
+    if ((rc = upload(&L.umap_off, S.umap_off))) return rc;
+    if ((rc = upload(&L.ainv_off, S.ainv_off))) return rc;
+    if ((rc = upload(&L.ainv, S.ainv))) return rc;
+  }
+  return MG_OK;
+}
+
+template <typename T>
+struct Arr;
+template <>
+struct Arr<double> {
+  static double* u(DevLevel& L) { return L.u64; }
+  static double* rhs(DevLevel& L) { return L.rhs64; }
+  static double* r(DevLevel& L) { return L.r64; }
+  static double* tmp(DevLevel& L) { return L.gtmp64; }
+};
+template <>
+struct Arr<float> {
+  static float* u(DevLevel& L) { return L.u32; }
+  static float* rhs(DevLevel& L) { return L.rhs32; }
+  static float* r(DevLevel& L) { return L.r32; }
+  static float* tmp(DevLevel& L) { return L.gtmp32; }
+};
+
+// One relaxation: red-black interior sweep, then ghost relaxation and lambda band sweeps.
+template <int D, typename T>
+void relax(mg_handle_s* H, int l, hipStream_t s) {
+  DevLevel& L = H->dev[l];
+  launch_smooth<D, T>(L, Arr<T>::u(L), Arr<T>::rhs(L), s);
+  const bool single = L.max_bandp + L.max_gp <= kSingleWgBand;
+  launch_band<D, T>(L, H->grid, Arr<T>::u(L), Arr<T>::rhs(L), Arr<T>::tmp(L), single, H->batch, s);
+}
+
+// The cycle of Sec. 2.4 from level l (TGCS recursion, gamma = 1 V, 2 W).
+template <int D, typename T>
+void cycle(mg_handle_s* H, int l, hipStream_t s) {
+  DevLevel& L = H->dev[l];
+  if (l == H->L) {
+    launch_coarse<T>(L, Arr<T>::rhs(L), Arr<T>::u(L), H->batch, s);
+    return;
+  }
+  for (int i = 0; i < H->grid.nu1; ++i) relax<D, T>(H, l, s);
+  launch_defect<D, T, T>(L, Arr<T>::u(L), Arr<T>::rhs(L), Arr<T>::r(L), nullptr, s);
+  launch_extend<T>(L, Arr<T>::r(L), L.max_extp <= kSingleWgExt, H->batch, s);
+  DevLevel& C = H->dev[l + 1];
+  launch_restrict<D, T>(L, C, Arr<T>::r(L), Arr<T>::rhs(C), Arr<T>::u(C), s);
+  for (int k = 0; k < H->grid.gamma; ++k) cycle<D, T>(H, l + 1, s);
+  launch_prolong<D, T>(L, C, Arr<T>::u(C), Arr<T>::u(L), s);
+  for (int i = 0; i < H->grid.nu2; ++i) relax<D, T>(H, l, s);
+}
+
+template <int D>
+void defect_norm64(mg_handle_s* H, hipStream_t s) {
+  DevLevel& L = H->dev[0];
+  launch_fill<uint64_t>(H->norms, 2 * H->batch, 0, s);
+  launch_defect<D, double, double>(L, L.u64, L.rhs64, L.r64, H->norms, s);
+}
+
+// FP64 defect of u64 written as the FP32 right-hand side of the correction problem
+template <int D>
+void dc_defect(mg_handle_s* H, hipStream_t s) {
+  DevLevel& L = H->dev[0];
+  launch_fill<uint64_t>(H->norms, 2 * H->batch, 0, s);
+  launch_defect<D, double, float>(L, L.u64, L.rhs64, L.rhs32, H->norms, s);
+}
+
+template <int D>
+void record_cycle(mg_handle_s* H, hipStream_t s) {
+  cycle<D, double>(H, 0, s);
+  defect_norm64<D>(H, s);
+}
+
+template <int D>
+void record_dc(mg_handle_s* H, hipStream_t s) {
+  for (int k = 0; k < H->grid.inner_cycles; ++k) cycle<D, float>(H, 0, s);
+  launch_dc_update<D>(H->dev[0], H->dev[0].u64, H->dev[0].u32, s);
+  dc_defect<D>(H, s);
+}
+
+hipStream_t stream_of(mg_handle_s* H) { return H->stream; }
+
+int capture(mg_handle_s* H, bool dc, hipGraphExec_t* out) {
+  if (*out) return MG_OK;
+  hipStream_t s = stream_of(H);
+  hipGraph_t graph;
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  if (H->dim == 2)
+    dc ? record_dc<2>(H, s) : record_cycle<2>(H, s);
+  else
+    dc ? record_dc<3>(H, s) : record_cycle<3>(H, s);
+  if (hipStreamEndCapture(s, &graph) != hipSuccess) return MG_EHIP;
+  const hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  return e == hipSuccess ? MG_OK : MG_EHIP;
+}
+
+// Read the per-problem norms; returns the max over problems of max(interior, ghost) / r0.
+int read_rel(mg_handle_s* H, double* rel) {
+  hipStream_t s = stream_of(H);
+  HIP_TRY(hipMemcpyAsync(H->norms_host, H->norms, 2 * H->batch * sizeof(uint64_t),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double m = 0.0;
+  for (int p = 0; p < H->batch; ++p) {
+    const double v = std::max(H->norms_host[2 * p], H->norms_host[2 * p + 1]) / H->r0[p];
+    if (!(v == v)) {
+      m = NAN;
+      break;
+    }
+    m = std::max(m, v);
+  }
+  *rel = m;
+  return MG_OK;
+}
+
+int check_ptrs(const void* a, const void* b, const void* c) {
+  return (!a || !b || !c) ? MG_EINVAL : MG_OK;
+}
+
+template <int D>
+int pack(mg_handle_s* H, const double* f, const double* g, const double* u) {
+  hipStream_t s = stream_of(H);
+  DevLevel& L = H->dev[0];
+  launch_pack<D>(L, f, g, u, L.rhs64, L.u64, s);
+  if (H->grid.precision == MG_FP32_DC) launch_fill<float>(L.u32, (int64_t)H->batch * L.g.npp, 0.f, s);
+  // r0 = ||(f_h, g_h)||_inf per problem
+  launch_fill<uint64_t>(H->norms, 2 * H->batch, 0, s);
+  launch_rhs_norm<D>(L, L.rhs64, H->norms, s);
+  HIP_TRY(hipMemcpyAsync(H->norms_host, H->norms, 2 * H->batch * sizeof(uint64_t),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int p = 0; p < H->batch; ++p) {
+    const double v = H->norms_host[2 * p];
+    if (!(v == v) || std::isinf(v)) return MG_EINVAL;
+    H->r0[p] = v > 0.0 ? v : 1.0;
+  }
+  return MG_OK;
+}
+
+int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, double tol,
+               int fixed_cycles, mg_stats* st) {
+  int rc = check_ptrs(f, g, u);
+  if (rc) return rc;
+  const bool dc = H->grid.precision == MG_FP32_DC;
+  hipStream_t s = stream_of(H);
+  auto t0 = std::chrono::steady_clock::now();
+  rc = H->dim == 2 ? pack<2>(H, f, g, u) : pack<3>(H, f, g, u);
+  if (rc) return rc;
+  if ((rc = capture(H, dc, dc ? &H->graph_dc : &H->graph_cycle))) return rc;
+  hipGraphExec_t exec = dc ? H->graph_dc : H->graph_cycle;
+  // defect of the initial guess
+  if (H->dim == 2)
+    dc ? dc_defect<2>(H, s) : defect_norm64<2>(H, s);
+  else
+    dc ? dc_defect<3>(H, s) : defect_norm64<3>(H, s);
+  double rel;
+  if ((rc = read_rel(H, &rel))) return rc;
+  H->history.clear();
+  H->history.push_back(rel);
+  int cycles = 0, steps = 0, grew = 0, status = MG_OK;
+  double prev = rel;
+  const int per = dc ? H->grid.inner_cycles : 1;
+  for (;;) {
+    if (fixed_cycles >= 0) {
+      if (steps >= fixed_cycles) break;
+    } else {
+      if (rel <= tol) break;
+      if (!(rel < INFINITY) || grew >= 5) {
+        status = MG_EDIVERGED;
+        break;
+      }
+      if (cycles + per > H->grid.max_cycles) {
+        status = MG_ENOCONV;
+        break;
+      }
+    }
+    HIP_TRY(hipGraphLaunch(exec, s));
+    cycles += per;
+    ++steps;
+    if ((rc = read_rel(H, &rel))) return rc;
+    H->history.push_back(rel);
+    grew = rel > prev ? grew + 1 : 0;
+    prev = rel;
+  }
+  if (H->dim == 2)
+    launch_unpack<2>(H->dev[0], H->batch, H->dev[0].u64, u, s);
+  else
+    launch_unpack<3>(H->dev[0], H->batch, H->dev[0].u64, u, s);
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hipGetLastError() != hipSuccess) return MG_EHIP;
+  auto t1 = std::chrono::steady_clock::now();
+  if (st) {
+    st->status = status;
+    st->cycles = cycles;
+    st->outer = dc ? steps : 0;
+    st->rel_residual = rel;
+    st->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    st->history = H->history.data();
+    st->history_len = (int)H->history.size();
+  }
+  return status;
+}
+
+void free_level(DevLevel& L) {
+  void* ptrs[] = {L.cls, L.phi, L.tiles, L.ghosts, L.ghost_off, L.red, L.black, L.red_off, L.black_off,
+                  L.ext, L.ext_merged, L.ext_off, L.dag_off, L.dag_start, L.rcode, L.u64, L.rhs64,
+                  L.r64, L.gtmp64, L.u32, L.rhs32, L.r32, L.gtmp32, L.umap, L.umap_off,
+                  L.ainv_off, L.ainv};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  L = DevLevel();
+}
+
+}  // namespace
+
+extern "C" {
+
+int mg_grid_default(mg_grid* g, int dim, int n, int n_coarse) {
+  if (!g) return MG_EINVAL;
+  std::memset(g, 0, sizeof(*g));
+  g->dim = dim;
+  g->n = n;
+  g->lo = -1.0;
+  g->hi = 1.0;
+  g->n_coarse = n_coarse;
+  g->nu1 = 2;
+  g->nu2 = 1;
+  g->gamma = 1;
+  g->lambda = 5;
+  g->delta_h = 3.0;
+  g->cD = 0.9;
+  g->cN = 0.9 * 2.0 / (3.0 * std::sqrt((double)dim));
+  g->split = 1;
+  g->precision = MG_FP64;
+  g->inner_cycles = 2;
+  g->max_cycles = 100;
+  g->batch = 1;
+  return MG_OK;
+}
+
+int mg_setup(const double* phi, const mg_bc_rule* bc, const mg_grid* grid, mg_handle_t* out) {
+  if (!phi || !bc || !grid || !out) return MG_EINVAL;
+  *out = nullptr;
+  const mg_grid& G = *grid;
+  if ((G.dim != 2 && G.dim != 3) || G.n < 4 || G.n_coarse < 2 || !(G.hi > G.lo) || G.batch < 1 ||
+      G.nu1 < 0 || G.nu2 < 0 || G.gamma < 1 || G.gamma > 2 || G.lambda < 0 || G.max_cycles < 0 ||
+      (G.precision != MG_FP64 && G.precision != MG_FP32_DC) ||
+      (G.precision == MG_FP32_DC && G.inner_cycles < 1))
+    return MG_EINVAL;
+  int L = 0, nn = G.n;
+  while (nn > G.n_coarse) {
+    if (nn % 2) return MG_EINVAL;
+    nn /= 2;
+    ++L;
+  }
+  if (nn != G.n_coarse || L >= kMaxLevels) return MG_EINVAL;
+  int64_t nodes = 1;
+  for (int a = 0; a < G.dim; ++a) nodes *= (int64_t)G.n + 1;
+  const int64_t padded = (int64_t)((G.n + 1 + 15) / 16 * 16) * nodes / (G.n + 1);
+  if (padded * G.batch >= ((int64_t)1 << 31)) return MG_EINVAL;
+
+  mg_handle_s* H = new (std::nothrow) mg_handle_s();
+  if (!H) return MG_ENOMEM;
+  H->grid = G;
+  H->bc.assign(bc, bc + G.batch);
+  H->L = L;
+  H->batch = G.batch;
+  H->dim = G.dim;
+  // phi may live in device memory
+  std::vector<double> phi_h((size_t)nodes * G.batch);
+  hipPointerAttribute_t attr;
+  bool on_device = false;
+  if (hipPointerGetAttributes(&attr, phi) == hipSuccess && attr.type == hipMemoryTypeDevice)
+    on_device = true;
+  (void)hipGetLastError();
+  if (on_device) {
+    if (hipMemcpy(phi_h.data(), phi, phi_h.size() * sizeof(double), hipMemcpyDeviceToHost) !=
+        hipSuccess) {
+      delete H;
+      return MG_EHIP;
+    }
+  } else {
+    std::memcpy(phi_h.data(), phi, phi_h.size() * sizeof(double));
+  }
+  int rc = build_hierarchy(H, phi_h.data());
+  // the coarsest right-hand side of one problem is staged in 64 KB of LDS
+  if (!rc && max_span(H->host[L].umap_off) > kMaxCoarse) rc = MG_EINVAL;
+  if (!rc) {
+    H->dev.assign(L + 1, DevLevel());
+    for (int l = 0; l <= L && !rc; ++l) rc = upload_level(H, l);
+  }
+  if (!rc && hipMalloc((void**)&H->norms, 2 * G.batch * sizeof(uint64_t)) != hipSuccess) rc = MG_ENOMEM;
+  if (!rc && hipHostMalloc((void**)&H->norms_host, 2 * G.batch * sizeof(double)) != hipSuccess)
+    rc = MG_ENOMEM;
+  if (!rc && hipStreamCreate(&H->own_stream) != hipSuccess) rc = MG_EHIP;
+  H->stream = H->own_stream;
+  if (!rc && (hipEventCreate(&H->ev0) != hipSuccess || hipEventCreate(&H->ev1) != hipSuccess))
+    rc = MG_EHIP;
+  if (!rc && hipDeviceSynchronize() != hipSuccess) rc = MG_EHIP;
+  H->r0 = new (std::nothrow) double[G.batch];
+  if (!rc && !H->r0) rc = MG_ENOMEM;
+  if (rc) {
+    mg_free(H);
+    return rc;
+  }
+  *out = H;
+  return MG_OK;
+}
+
+int mg_set_stream(mg_handle_t h, void* hip_stream) {
+  if (!h) return MG_EINVAL;
+  // captured graphs are stream independent: only the stream they are launched on changes
+  h->stream = hip_stream ? (hipStream_t)hip_stream : h->own_stream;
+  return MG_OK;
+}
+
+int mg_query_level(mg_handle_t h, int level, int64_t* info) {
+  if (!h || !info || level < 0 || level > h->L) return MG_EINVAL;
+  const HostLevel& S = h->host[level];
+  info[0] = S.g.n;
+  info[1] = S.nint;
+  info[2] = S.nghost;
+  info[3] = S.nband;
+  info[4] = (int64_t)S.ext.size();
+  info[5] = (int64_t)S.tiles.size();
+  info[6] = level == h->L ? (int64_t)S.umap.size() : 0;
+  info[7] = h->L + 1;
+  return MG_OK;
+}
+
+int mg_query_ghosts(mg_handle_t h, int problem, int level, int64_t* count, int64_t* node,
+                    double* B, double* nB, int8_t* type, int8_t* rung) {
+  if (!h || !count || problem < 0 || problem >= h->batch || level < 0 || level > h->L)
+    return MG_EINVAL;
+  const HostLevel& S = h->host[level];
+  const int a = S.ghost_off[problem], b = S.ghost_off[problem + 1];
+  *count = b - a;
+  if (!node) return MG_OK;
+  const Geo& g = S.g;
+  for (int i = a; i < b; ++i) {
+    const GhostRec& r = S.ghosts[i];
+    int64_t loc = r.node - (int64_t)problem * g.npp;
+    const int64_t z = h->dim == 3 ? loc / g.st[2] : 0;
+    loc -= z * g.st[2];
+    const int64_t y = loc / g.st[1], x = loc - y * g.st[1];
+    node[i - a] = x + (int64_t)g.np * (y + (int64_t)g.np * z);
+    for (int c = 0; c < 3; ++c) {
+      if (B) B[3 * (i - a) + c] = S.gB[3 * i + c];
+      if (nB) nB[3 * (i - a) + c] = r.type ? 0.0 : r.nb[c];
+    }
+    if (type) type[i - a] = r.type;
+    if (rung) rung[i - a] = r.rung;
+  }
+  return MG_OK;
+}
+
+int mg_query_classes(mg_handle_t h, int problem, int level, int8_t* cls) {
+  if (!h || !cls || problem < 0 || problem >= h->batch || level < 0 || level > h->L)
+    return MG_EINVAL;
+  const HostLevel& S = h->host[level];
+  const Geo& g = S.g;
+  const int nz = h->dim == 3 ? g.np : 1;
+  int64_t q = 0;
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < g.np; ++y)
+      for (int x = 0; x < g.np; ++x)
+        cls[q++] = S.cls[(size_t)problem * g.npp + x + g.st[1] * y + g.st[2] * z];
+  return MG_OK;
+}
+
+int mg_solve(mg_handle_t h, const double* f, const double* g, double* u, double tol,
+             mg_stats* st) {
+  if (!h || !(tol >= 0.0)) return MG_EINVAL;
+  return solve_impl(h, f, g, u, tol, -1, st);
+}
+
+int mg_cycles(mg_handle_t h, const double* f, const double* g, double* u, int ncycles) {
+  if (!h || ncycles < 0) return MG_EINVAL;
+  return solve_impl(h, f, g, u, 0.0, ncycles, nullptr);
+}
+
+int mg_residual(mg_handle_t h, const double* f, const double* g, const double* u, double* r,
+                double* norms) {
+  if (!h || !f || !g || !u) return MG_EINVAL;
+  hipStream_t s = stream_of(h);
+  int rc = h->dim == 2 ? pack<2>(h, f, g, u) : pack<3>(h, f, g, u);
+  if (rc) return rc;
+  DevLevel& L = h->dev[0];
+  launch_fill<double>(L.r64, (int64_t)h->batch * L.g.npp, 0.0, s);
+  if (h->dim == 2)
+    defect_norm64<2>(h, s);
+  else
+    defect_norm64<3>(h, s);
+  HIP_TRY(hipMemcpyAsync(h->norms_host, h->norms, 2 * h->batch * sizeof(uint64_t),
+                         hipMemcpyDeviceToHost, s));
+  if (r) {
+    if (h->dim == 2)
+      launch_unpack<2>(L, h->batch, L.r64, r, s);
+    else
+      launch_unpack<3>(L, h->batch, L.r64, r, s);
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (norms)
+    for (int i = 0; i < 2 * h->batch; ++i) norms[i] = h->norms_host[i];
+  return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
+}
+
+int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_ms, double* bytes) {
+  if (!h || level < 0 || level > h->L || reps < 1 || kernel < 0 || kernel > 4) return MG_EINVAL;
+  if ((kernel == 2 || kernel == 3) && level >= h->L) return MG_EINVAL;
+  hipStream_t s = stream_of(h);
+  DevLevel& L = h->dev[level];
+  const HostLevel& S = h->host[level];
+  const bool dc = h->grid.precision == MG_FP32_DC;
+  const double sz = dc ? 4.0 : 8.0;
+  auto run = [&]() {
+    if (h->dim == 2) {
+      if (dc) {
+        if (kernel == 0) launch_smooth<2, float>(L, L.u32, L.rhs32, s);
+        if (kernel == 1) launch_defect<2, float, float>(L, L.u32, L.rhs32, L.r32, nullptr, s);
+        if (kernel == 2) launch_restrict<2, float>(L, h->dev[level + 1], L.r32, h->dev[level + 1].rhs32, h->dev[level + 1].u32, s);
+        if (kernel == 3) launch_prolong<2, float>(L, h->dev[level + 1], h->dev[level + 1].u32, L.u32, s);
+        if (kernel == 4) launch_band<2, float>(L, h->grid, L.u32, L.rhs32, L.gtmp32, L.max_bandp + L.max_gp <= kSingleWgBand, h->batch, s);
+      } else {
+        if (kernel == 0) launch_smooth<2, double>(L, L.u64, L.rhs64, s);
+        if (kernel == 1) launch_defect<2, double, double>(L, L.u64, L.rhs64, L.r64, nullptr, s);
+        if (kernel == 2) launch_restrict<2, double>(L, h->dev[level + 1], L.r64, h->dev[level + 1].rhs64, h->dev[level + 1].u64, s);
+        if (kernel == 3) launch_prolong<2, double>(L, h->dev[level + 1], h->dev[level + 1].u64, L.u64, s);
+        if (kernel == 4) launch_band<2, double>(L, h->grid, L.u64, L.rhs64, L.gtmp64, L.max_bandp + L.max_gp <= kSingleWgBand, h->batch, s);
+      }
+    } else {
+      if (dc) {
+        if (kernel == 0) launch_smooth<3, float>(L, L.u32, L.rhs32, s);
+        if (kernel == 1) launch_defect<3, float, float>(L, L.u32, L.rhs32, L.r32, nullptr, s);
+        if (kernel == 2) launch_restrict<3, float>(L, h->dev[level + 1], L.r32, h->dev[level + 1].rhs32, h->dev[level + 1].u32, s);
+        if (kernel == 3) launch_prolong<3, float>(L, h->dev[level + 1], h->dev[level + 1].u32, L.u32, s);
+        if (kernel == 4) launch_band<3, float>(L, h->grid, L.u32, L.rhs32, L.gtmp32, L.max_bandp + L.max_gp <= kSingleWgBand, h->batch, s);
+      } else {
+        if (kernel == 0) launch_smooth<3, double>(L, L.u64, L.rhs64, s);
+        if (kernel == 1) launch_defect<3, double, double>(L, L.u64, L.rhs64, L.r64, nullptr, s);
+        if (kernel == 2) launch_restrict<3, double>(L, h->dev[level + 1], L.r64, h->dev[level + 1].rhs64, h->dev[level + 1].u64, s);
+        if (kernel == 3) launch_prolong<3, double>(L, h->dev[level + 1], h->dev[level + 1].u64, L.u64, s);
+        if (kernel == 4) launch_band<3, double>(L, h->grid, L.u64, L.rhs64, L.gtmp64, L.max_bandp + L.max_gp <= kSingleWgBand, h->batch, s);
+      }
+    }
+  };
+  if (dc && level > 0 && !L.u32) return MG_EINVAL;
+  if (!dc && !L.u64) return MG_EINVAL;
+  run();
+  HIP_TRY(hipEventRecord(h->ev0, s));
+  for (int i = 0; i < reps; ++i) run();
+  HIP_TRY(hipEventRecord(h->ev1, s));
+  HIP_TRY(hipEventSynchronize(h->ev1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  if (avg_ms) *avg_ms = ms / reps;
+  if (bytes) {
+    // algorithmic bytes: each array element the kernel must touch, once
+    const double nint = (double)S.nint, ng = (double)S.nghost;
+    double b = 0.0;
+    if (kernel == 0) b = nint * (3.0 * sz + 1.0);
+    if (kernel == 1) b = nint * (3.0 * sz + 1.0) + ng * (2.0 * sz + sizeof(GhostRec));
+    if (kernel == 2) {
+      const HostLevel& C = h->host[level + 1];
+      b = (nint + ng + (double)S.ext.size()) * sz + (double)(C.nint + C.nghost) * (2.0 * sz + 1.0);
+    }
+    if (kernel == 3) {
+      const HostLevel& C = h->host[level + 1];
+      b = (nint + ng) * (2.0 * sz + 1.0) + (double)(C.nint + C.nghost) * (sz + 1.0);
+    }
+    if (kernel == 4)
+      b = h->grid.lambda * (double)S.nband * 3.0 * sz +
+          (h->grid.lambda + 1) * ng * (3.0 * sz + sizeof(GhostRec));
+    *bytes = b;
+  }
+  return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
+}
+
+void mg_free(mg_handle_t h) {
+  if (!h) return;
+  if (h->graph_cycle) (void)hipGraphExecDestroy(h->graph_cycle);
+  if (h->graph_dc) (void)hipGraphExecDestroy(h->graph_dc);
+  for (DevLevel& L : h->dev) free_level(L);
+  if (h->norms) (void)hipFree(h->norms);
+  if (h->norms_host) (void)hipHostFree(h->norms_host);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  delete[] h->r0;
+  if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+  delete h;
+}
+
+const char* mg_strerror(int code) {
+  switch (code) {
+    case MG_OK: return "ok";
+    case MG_EINVAL: return "invalid argument";
+    case MG_ENOMEM: return "out of memory";
+    case MG_EHIP: return "HIP runtime error";
+    case MG_EGEOM: return "unusable geometry";
+    case MG_ENOCONV: return "cycle budget exhausted before the tolerance";
+    case MG_EDIVERGED: return "iteration diverged";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

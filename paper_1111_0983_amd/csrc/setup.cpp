@@ -1,0 +1,695 @@
+// Host construction of the multigrid hierarchy: node classes, ghost records, boundary
+// bands, defect-extension lists, restriction codes, active tiles and the coarsest-grid
+// inverse.  FP64 throughout; built with -ffp-contract=off so every geometric decision
+// (interior / ghost, boundary-condition type, upwind signs, processing order) is an exact
+// function of phi.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "ghostmg_impl.h"
+
+namespace ghostmg {
+namespace {
+
+enum { OUT = 0, IN = 1, GHOST = 2 };
+
+// One level of one problem in unpadded node order (x fastest).
+struct PL {
+  int D = 2, n = 0, np = 0;
+  double h = 0.0, lo = -1.0;
+  int64_t nn = 0, st[3] = {0, 0, 0};
+  std::vector<double> phi;
+  std::vector<int8_t> cls;
+  std::vector<int32_t> gid;   // node -> ghost index, -1 otherwise
+  std::vector<int8_t> lab;    // boundary-condition label of outside nodes, -1 otherwise
+  std::vector<GhostRec> gh;   // node field holds the local unpadded index here
+  std::vector<double> B;      // 3 per ghost
+};
+
+inline void jof(const PL& L, int64_t idx, int j[3]) {
+  j[0] = j[1] = j[2] = 0;
+  for (int a = 0; a < L.D; ++a) {
+    j[a] = (int)(idx % L.np);
+    idx /= L.np;
+  }
+}
+inline int64_t iof(const PL& L, const int j[3]) {
+  int64_t idx = 0;
+  for (int a = L.D - 1; a >= 0; --a) idx = idx * L.np + j[a];
+  return idx;
+}
+inline bool inbox(const PL& L, const int j[3]) {
+  for (int a = 0; a < L.D; ++a)
+    if (j[a] < 0 || j[a] > L.n) return false;
+  return true;
+}
+
+// Gradient of phi: central differences, one-sided second order on the box faces.
+void gradient(const PL& L, const int j[3], double g[3]) {
+  g[0] = g[1] = g[2] = 0.0;
+  const int64_t c = iof(L, j);
+  for (int a = 0; a < L.D; ++a) {
+    const int64_t s = L.st[a];
+    if (j[a] > 0 && j[a] < L.n)
+      g[a] = (L.phi[c + s] - L.phi[c - s]) / (2.0 * L.h);
+    else if (j[a] == 0)
+      g[a] = (-3.0 * L.phi[c] + 4.0 * L.phi[c + s] - L.phi[c + 2 * s]) / (2.0 * L.h);
+    else
+      g[a] = (3.0 * L.phi[c] - 4.0 * L.phi[c - s] + L.phi[c - 2 * s]) / (2.0 * L.h);
+  }
+}
+
+bool is_dirichlet(const mg_bc_rule& r, int D, const double* B) {
+  double v = r.c;
+  for (int a = 0; a < D; ++a) v += r.a[a] * B[a];
+  return r.strict ? (v > 0.0) : (v >= 0.0);
+}
+
+// Does the stencil of the rung (signs s) stay inside the box and on unknowns?
+bool contained(const PL& L, const int jG[3], const int8_t* s, int rung) {
+  int K = 1;
+  for (int a = 0; a < L.D; ++a) K *= 3;
+  for (int t = 0; t < K; ++t) {
+    int k[3] = {0, 0, 0}, tt = t;
+    for (int a = L.D - 1; a >= 0; --a) {
+      k[a] = tt % 3;
+      tt /= 3;
+    }
+    bool need;
+    if (rung == 1) {
+      need = true;
+    } else if (rung == 2) {
+      need = true;
+      for (int a = 0; a < L.D; ++a)
+        if (k[a] == 2) need = false;
+    } else {
+      int nz = 0, big = 0;
+      for (int a = 0; a < L.D; ++a) {
+        nz += k[a] != 0;
+        big += k[a] > 1;
+      }
+      need = nz <= 1 && big == 0;
+    }
+    if (!need) continue;
+    int j[3] = {jG[0], jG[1], jG[2]};
+    for (int a = 0; a < L.D; ++a) j[a] += s[a] * k[a];
+    if (!inbox(L, j)) return false;
+    const int8_t c = L.cls[iof(L, j)];
+    if (c != IN && c != GHOST) return false;
+  }
+  return true;
+}
+
+template <int D>
+void row_weights(const GhostRec& g, double inv_h, double* w) {
+  ghost_row<D>(g, inv_h, w);
+}
+
+int classify(PL& L, const mg_grid& G, const mg_bc_rule& rule) {
+  const int D = L.D;
+  L.cls.assign(L.nn, OUT);
+  int64_t nin = 0;
+  for (int64_t i = 0; i < L.nn; ++i)
+    if (L.phi[i] < 0.0) {
+      L.cls[i] = IN;
+      ++nin;
+    }
+  if (nin == 0) return MG_EGEOM;
+  for (int64_t i = 0; i < L.nn; ++i) {
+    if (L.cls[i] != IN) continue;
+    int j[3];
+    jof(L, i, j);
+    for (int a = 0; a < D; ++a)
+      if (j[a] == 0 || j[a] == L.n) return MG_EGEOM;  // the domain must not touch the box
+  }
+  for (int64_t i = 0; i < L.nn; ++i) {
+    if (L.cls[i] == IN) continue;
+    int j[3];
+    jof(L, i, j);
+    for (int a = 0; a < D && L.cls[i] != GHOST; ++a)
+      for (int dir = -1; dir <= 1; dir += 2) {
+        int q[3] = {j[0], j[1], j[2]};
+        q[a] += dir;
+        if (inbox(L, q) && L.phi[iof(L, q)] < 0.0) L.cls[i] = GHOST;
+      }
+  }
+  L.gid.assign(L.nn, -1);
+  L.lab.assign(L.nn, -1);
+  L.gh.clear();
+  L.B.clear();
+  const double inv_h = 1.0 / L.h;
+  for (int64_t Gi = 0; Gi < L.nn; ++Gi) {
+    if (L.cls[Gi] != GHOST) continue;
+    int jG[3];
+    jof(L, Gi, jG);
+    double gr[3];
+    gradient(L, jG, gr);
+    double n2 = 0.0;
+    for (int a = 0; a < D; ++a) n2 += gr[a] * gr[a];
+    const double nrm = std::sqrt(n2);
+    if (!(nrm > 0.0)) return MG_EGEOM;
+    double B[3] = {0, 0, 0}, xG[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+      const double na = gr[a] / nrm;
+      xG[a] = L.lo + L.h * (double)jG[a];
+      B[a] = xG[a] - na * L.phi[Gi];  // closest boundary point, Eq. (clpt)
+    }
+    GhostRec r;
+    std::memset(&r, 0, sizeof(r));
+    r.node = (int32_t)Gi;
+    r.type = is_dirichlet(rule, D, B) ? 1 : 0;
+    // upwind signs of Eq. (St_G); a tie goes to the side of the smaller-phi neighbour
+    int8_t pref[3] = {1, 1, 1};
+    int tiedax[3], ntied = 0;
+    for (int a = 0; a < D; ++a) {
+      const double df = B[a] - xG[a];
+      if (std::fabs(df) > 1e-12 * L.h) {
+        pref[a] = df > 0.0 ? 1 : -1;
+      } else {
+        tiedax[ntied++] = a;
+        const double pm = jG[a] > 0 ? L.phi[Gi - L.st[a]] : INFINITY;
+        const double pp = jG[a] < L.n ? L.phi[Gi + L.st[a]] : INFINITY;
+        pref[a] = pm < pp ? -1 : 1;
+      }
+    }
+    // reduced-stencil ladder (Remark 3 of Sec. 2.3)
+    int rung = 0, axis = 0;
+    int8_t s[3] = {1, 1, 1};
+    for (int rg = 1; rg <= 3 && !rung; ++rg)
+      for (int m = 0; m < (1 << ntied) && !rung; ++m) {
+        for (int a = 0; a < 3; ++a) s[a] = pref[a];
+        for (int b = 0; b < ntied; ++b)
+          if (m & (1 << b)) s[tiedax[b]] = (int8_t)-pref[tiedax[b]];
+        if (contained(L, jG, s, rg)) rung = rg;
+      }
+    if (!rung) {
+      double best = INFINITY;
+      int ba = -1, bs = 0;
+      for (int a = 0; a < D; ++a)
+        for (int dir = -1; dir <= 1; dir += 2) {
+          int q[3] = {jG[0], jG[1], jG[2]};
+          q[a] += dir;
+          if (!inbox(L, q)) continue;
+          const int64_t Q = iof(L, q);
+          if (L.cls[Q] != IN) continue;
+          if (L.phi[Q] < best) {
+            best = L.phi[Q];
+            ba = a;
+            bs = dir;
+          }
+        }
+      if (ba < 0) return MG_EGEOM;
+      for (int a = 0; a < 3; ++a) s[a] = pref[a];
+      s[ba] = (int8_t)bs;
+      axis = ba;
+      rung = 4;
+    }
+    r.rung = (int8_t)rung;
+    r.axis = (int8_t)axis;
+    for (int a = 0; a < 3; ++a) r.s[a] = a < D ? s[a] : 0;
+    for (int a = 0; a < D; ++a) r.xi[a] = (double)s[a] * (B[a] - xG[a]) / L.h;
+    if (!r.type) {
+      // unit normal at B from the same interpolant of phi (Eq. (neu2d))
+      double gp[3] = {0, 0, 0};
+      for (int a = 0; a < D; ++a) {
+        double e[3] = {0, 0, 0};
+        e[a] = 1.0;
+        double w[27];
+        uint32_t used = D == 2 ? stencil_weights<2>(rung, axis, s, r.xi, inv_h, 0, e, w)
+                               : stencil_weights<3>(rung, axis, s, r.xi, inv_h, 0, e, w);
+        int K = D == 2 ? 9 : 27;
+        for (int t = 0; t < K; ++t) {
+          if (!(used >> t & 1u)) continue;
+          int64_t off = 0, tt = t;
+          for (int c = D - 1; c >= 0; --c) {
+            off += (int64_t)s[c] * (tt % 3) * L.st[c];
+            tt /= 3;
+          }
+          gp[a] += w[t] * L.phi[Gi + off];
+        }
+      }
+      double g2 = 0.0;
+      for (int a = 0; a < D; ++a) g2 += gp[a] * gp[a];
+      const double gn = std::sqrt(g2);
+      if (!(gn > 0.0)) return MG_EGEOM;
+      for (int a = 0; a < D; ++a) r.nb[a] = gp[a] / gn;
+    }
+    L.gid[Gi] = (int32_t)L.gh.size();
+    L.lab[Gi] = r.type;
+    L.gh.push_back(r);
+    for (int a = 0; a < 3; ++a) L.B.push_back(a < D ? B[a] : 0.0);
+  }
+  (void)G;
+  return MG_OK;
+}
+
+struct Ext {
+  int64_t node;
+  int64_t src[3];
+  double wt[3];
+  int dag;
+};
+
+// Nodes of the defect extension for the transfer from F to the next coarser level C
+// (Sec. 2.6): every outside non-ghost node of F in the 3^D neighbourhood of a ghost of C,
+// processed once in increasing phi, each averaging its available upwind neighbours
+// Q_a = P - sgn(n_a) e_a with weights |n_a| (the steady state of Eq. (exp)).
+int extension(PL& F, const PL& C, const mg_grid& G, const mg_bc_rule& rule,
+              std::vector<Ext>& out) {
+  const int D = F.D;
+  std::vector<int64_t> rank(F.nn, -1);
+  std::vector<int64_t> nodes;
+  int nnb = 1;
+  for (int a = 0; a < D; ++a) nnb *= 3;
+  for (int64_t X = 0; X < C.nn; ++X) {
+    if (C.cls[X] != GHOST) continue;
+    int jc[3];
+    jof(C, X, jc);
+    for (int o = 0; o < nnb; ++o) {
+      int j[3] = {0, 0, 0}, oo = o;
+      for (int a = 0; a < D; ++a) {
+        j[a] = 2 * jc[a] + oo % 3 - 1;
+        oo /= 3;
+      }
+      if (!inbox(F, j)) continue;
+      const int64_t P = iof(F, j);
+      if (F.cls[P] == OUT && rank[P] < 0) {
+        rank[P] = 0;
+        nodes.push_back(P);
+      }
+    }
+  }
+  std::sort(nodes.begin(), nodes.end(), [&](int64_t a, int64_t b) {
+    if (F.phi[a] != F.phi[b]) return F.phi[a] < F.phi[b];
+    return a < b;
+  });
+  for (size_t e = 0; e < nodes.size(); ++e) rank[nodes[e]] = (int64_t)e;
+  std::vector<int> dag(F.nn, 0);
+  out.clear();
+  out.reserve(nodes.size());
+  for (size_t e = 0; e < nodes.size(); ++e) {
+    const int64_t P = nodes[e];
+    Ext x;
+    x.node = P;
+    x.dag = 1;
+    for (int a = 0; a < 3; ++a) {
+      x.src[a] = -1;
+      x.wt[a] = 0.0;
+    }
+    int j[3];
+    jof(F, P, j);
+    double gr[3];
+    gradient(F, j, gr);
+    double n2 = 0.0;
+    for (int a = 0; a < D; ++a) n2 += gr[a] * gr[a];
+    const double nrm = std::sqrt(n2);
+    if (!(nrm > 0.0)) {
+      F.lab[P] = 1;
+      dag[P] = 1;
+      out.push_back(x);
+      continue;
+    }
+    double Bp[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) Bp[a] = (F.lo + F.h * (double)j[a]) - gr[a] / nrm * F.phi[P];
+    F.lab[P] = is_dirichlet(rule, D, Bp) ? 1 : 0;
+    int nsame = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1 && (!G.split || nsame > 0)) break;
+      for (int a = 0; a < D; ++a) {
+        const double na = gr[a] / nrm;
+        if (na == 0.0) continue;
+        int q[3] = {j[0], j[1], j[2]};
+        q[a] -= na > 0.0 ? 1 : -1;
+        if (!inbox(F, q)) continue;
+        const int64_t Q = iof(F, q);
+        const bool avail = F.cls[Q] == GHOST || (rank[Q] >= 0 && rank[Q] < (int64_t)e);
+        if (!avail) continue;
+        if (G.split && pass == 0 && F.lab[Q] != F.lab[P]) continue;
+        if (pass == 0) ++nsame;
+        x.src[a] = Q;
+        x.wt[a] = std::fabs(na);
+      }
+    }
+    int lvl = 1;
+    for (int a = 0; a < 3; ++a)
+      if (x.src[a] >= 0 && F.cls[x.src[a]] == OUT) lvl = std::max(lvl, dag[x.src[a]] + 1);
+    dag[P] = lvl;
+    x.dag = lvl;
+    out.push_back(x);
+  }
+  return MG_OK;
+}
+
+// Box of the partial full-weighting transfer at coarse node X (Sec. 2.5): the largest box
+// [lo_a, hi_a], lo in {-1, 0}, hi in {0, 1}, whose fine nodes all lie in I_h; ties go to
+// the larger x, then y, then z extent, then to a box starting at -1 in x, then y, then z.
+uint8_t box_code(const PL& F, const int jf[3], bool inside, int lab) {
+  const int D = F.D;
+  int best[7] = {0, 0, 0, 0, 0, 0, 0};
+  bool have = false;
+  uint8_t code = 0;
+  int ncand = 1;
+  for (int a = 0; a < D; ++a) ncand *= 4;
+  for (int c = 0; c < ncand; ++c) {
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, cc = c;
+    for (int a = 0; a < D; ++a) {
+      lo[a] = (cc & 1) ? -1 : 0;
+      hi[a] = (cc & 2) ? 1 : 0;
+      cc >>= 2;
+    }
+    int ext[3] = {1, 1, 1}, cnt = 1;
+    for (int a = 0; a < D; ++a) {
+      ext[a] = hi[a] - lo[a] + 1;
+      cnt *= ext[a];
+    }
+    bool ok = true;
+    for (int t = 0; t < cnt && ok; ++t) {
+      int j[3] = {jf[0], jf[1], jf[2]}, tt = t;
+      for (int a = 0; a < D; ++a) {
+        j[a] = jf[a] + lo[a] + tt % ext[a];
+        tt /= ext[a];
+      }
+      if (!inbox(F, j)) {
+        ok = false;
+        break;
+      }
+      const int64_t P = iof(F, j);
+      if (inside)
+        ok = F.cls[P] == IN;
+      else
+        ok = F.cls[P] != IN && (lab < 0 || F.lab[P] == lab);
+    }
+    if (!ok) continue;
+    int key[7] = {cnt, 0, 0, 0, 0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+      key[1 + a] = ext[a];
+      key[4 + a] = lo[a] == -1;
+    }
+    bool better = !have;
+    for (int m = 0; m < 7 && have; ++m)
+      if (key[m] != best[m]) {
+        better = key[m] > best[m];
+        break;
+      }
+    if (better) {
+      have = true;
+      std::memcpy(best, key, sizeof(key));
+      code = 0;
+      for (int a = 0; a < D; ++a) code |= (uint8_t)(((lo[a] == -1) << (2 * a)) | ((hi[a] == 1) << (2 * a + 1)));
+    }
+  }
+  return code;
+}
+
+// Explicit inverse of the coarsest system by LU with partial pivoting (FP64).
+int invert(std::vector<double>& A, int n, std::vector<double>& inv) {
+  std::vector<int> piv(n);
+  double amax = 0.0;
+  for (double v : A) amax = std::max(amax, std::fabs(v));
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double pv = std::fabs(A[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[(size_t)i * n + k]) > pv) {
+        pv = std::fabs(A[(size_t)i * n + k]);
+        p = i;
+      }
+    piv[k] = p;
+    if (!(pv > 1e-13 * amax)) return MG_EGEOM;
+    if (p != k)
+      for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
+    const double d = A[(size_t)k * n + k];
+    for (int i = k + 1; i < n; ++i) {
+      const double m = A[(size_t)i * n + k] / d;
+      A[(size_t)i * n + k] = m;
+      if (m != 0.0)
+        for (int j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= m * A[(size_t)k * n + j];
+    }
+  }
+  inv.assign((size_t)n * n, 0.0);
+  std::vector<double> x(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) x[i] = 0.0;
+    x[c] = 1.0;
+    for (int k = 0; k < n; ++k)
+      if (piv[k] != k) std::swap(x[k], x[piv[k]]);
+    for (int i = 0; i < n; ++i) {
+      double s = x[i];
+      for (int j = 0; j < i; ++j) s -= A[(size_t)i * n + j] * x[j];
+      x[i] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = x[i];
+      for (int j = i + 1; j < n; ++j) s -= A[(size_t)i * n + j] * x[j];
+      x[i] = s / A[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = x[i];
+  }
+  return MG_OK;
+}
+
+}  // namespace
+
+// Build every level of every problem; phi is host memory, batch * (n+1)^D values.
+int build_hierarchy(mg_handle_s* H, const double* phi) {
+  const mg_grid& G = H->grid;
+  const int D = G.dim, batch = G.batch, L = H->L;
+  H->host.assign(L + 1, HostLevel());
+  for (int l = 0; l <= L; ++l) {
+    Geo& g = H->host[l].g;
+    g.n = G.n >> l;
+    g.np = g.n + 1;
+    g.pitch = (g.np + 15) / 16 * 16;
+    g.h = (G.hi - G.lo) / (double)g.n;
+    g.st[0] = 1;
+    g.st[1] = g.pitch;
+    g.st[2] = D == 3 ? (int64_t)g.pitch * g.np : 0;
+    g.npp = D == 3 ? (int64_t)g.pitch * g.np * g.np : (int64_t)g.pitch * g.np;
+    H->host[l].cls.assign((size_t)batch * g.npp, 0);
+    H->host[l].rcode.assign((size_t)batch * g.npp, kNoUnknown);
+    H->host[l].ghost_off.assign(1, 0);
+    H->host[l].red_off.assign(1, 0);
+    H->host[l].black_off.assign(1, 0);
+    H->host[l].ext_off.assign(1, 0);
+    H->host[l].dag_start.assign(1, 0);
+    H->host[l].umap_off.assign(1, 0);
+    H->host[l].ainv_off.assign(1, 0);
+  }
+  const int64_t np0 = (int64_t)G.n + 1;
+  int64_t nn0 = 1;
+  for (int a = 0; a < D; ++a) nn0 *= np0;
+  for (int p = 0; p < batch; ++p) {
+    std::vector<PL> lev(L + 1);
+    for (int l = 0; l <= L; ++l) {
+      PL& V = lev[l];
+      V.D = D;
+      V.n = G.n >> l;
+      V.np = V.n + 1;
+      V.h = (G.hi - G.lo) / (double)V.n;
+      V.lo = G.lo;
+      V.nn = 1;
+      for (int a = 0; a < D; ++a) {
+        V.st[a] = V.nn;
+        V.nn *= V.np;
+      }
+      V.phi.resize(V.nn);
+      const int64_t stride = (int64_t)1 << l;
+      for (int64_t i = 0; i < V.nn; ++i) {
+        int j[3];
+        jof(V, i, j);
+        int64_t fi = 0;
+        for (int a = D - 1; a >= 0; --a) fi = fi * np0 + (int64_t)j[a] * stride;
+        const double v = phi[(size_t)p * nn0 + fi];
+        if (!std::isfinite(v)) return MG_EINVAL;
+        V.phi[i] = v;
+      }
+      int rc = classify(V, G, H->bc[p]);
+      if (rc) return rc;
+    }
+    for (int l = 0; l <= L; ++l) {
+      PL& V = lev[l];
+      HostLevel& HL = H->host[l];
+      const Geo& g = HL.g;
+      const int64_t base = (int64_t)p * g.npp;
+      auto pad = [&](int64_t local) {
+        int j[3];
+        jof(V, local, j);
+        return base + j[0] + g.st[1] * j[1] + g.st[2] * j[2];
+      };
+      if (l > 0 && HL.phi.empty()) HL.phi.assign((size_t)batch * g.npp, 0.0);
+      for (int64_t i = 0; i < V.nn; ++i) {
+        HL.cls[pad(i)] = V.cls[i];
+        if (l > 0) HL.phi[pad(i)] = V.phi[i];
+        if (V.cls[i] == IN) ++HL.nint;
+      }
+      // ghosts
+      for (size_t q = 0; q < V.gh.size(); ++q) {
+        GhostRec r = V.gh[q];
+        r.node = (int32_t)pad(r.node);
+        HL.ghosts.push_back(r);
+        for (int a = 0; a < 3; ++a) HL.gB.push_back(V.B[3 * q + a]);
+      }
+      HL.nghost += (int64_t)V.gh.size();
+      HL.ghost_off.push_back((int32_t)HL.ghosts.size());
+      // boundary band: interior nodes within delta = delta_h h of the boundary (Sec. 3.2)
+      const double delta = G.delta_h * V.h;
+      for (int64_t i = 0; i < V.nn; ++i) {
+        if (V.cls[i] != IN || !(V.phi[i] >= -delta)) continue;
+        int j[3];
+        jof(V, i, j);
+        ((j[0] + j[1] + j[2]) & 1 ? HL.black : HL.red).push_back((int32_t)pad(i));
+        ++HL.nband;
+      }
+      HL.red_off.push_back((int32_t)HL.red.size());
+      HL.black_off.push_back((int32_t)HL.black.size());
+      // tiles holding unknowns
+      const int TX = D == 2 ? Tile<2>::X : Tile<3>::X;
+      const int TY = D == 2 ? Tile<2>::Y : Tile<3>::Y;
+      const int TZ = D == 2 ? 1 : Tile<3>::Z;
+      const int ntx = (V.np + TX - 1) / TX, nty = (V.np + TY - 1) / TY;
+      const int ntz = D == 2 ? 1 : (V.np + TZ - 1) / TZ;
+      for (int tz = 0; tz < ntz; ++tz)
+        for (int ty = 0; ty < nty; ++ty)
+          for (int tx = 0; tx < ntx; ++tx) {
+            bool any = false;
+            for (int z = tz * TZ; z < std::min((tz + 1) * TZ, D == 2 ? 1 : V.np) && !any; ++z)
+              for (int y = ty * TY; y < std::min((ty + 1) * TY, V.np) && !any; ++y)
+                for (int x = tx * TX; x < std::min((tx + 1) * TX, V.np); ++x) {
+                  const int64_t i = x + (int64_t)V.np * (y + (int64_t)V.np * z);
+                  if (V.cls[i] != OUT) {
+                    any = true;
+                    break;
+                  }
+                }
+            if (any) HL.tiles.push_back(make_int4(p, tx, ty, tz));
+          }
+    }
+    // extension lists and restriction codes between consecutive levels
+    for (int l = 0; l < L; ++l) {
+      PL& F = lev[l];
+      PL& C = lev[l + 1];
+      HostLevel& HF = H->host[l];
+      HostLevel& HC = H->host[l + 1];
+      std::vector<Ext> ext;
+      int rc = extension(F, C, G, H->bc[p], ext);
+      if (rc) return rc;
+      const Geo& gf = HF.g;
+      const int64_t basef = (int64_t)p * gf.npp;
+      auto padf = [&](int64_t local) -> int32_t {
+        if (local < 0) return -1;
+        int j[3];
+        jof(F, local, j);
+        return (int32_t)(basef + j[0] + gf.st[1] * j[1] + gf.st[2] * j[2]);
+      };
+      std::stable_sort(ext.begin(), ext.end(), [](const Ext& a, const Ext& b) { return a.dag < b.dag; });
+      int maxdag = 0;
+      for (const Ext& x : ext) maxdag = std::max(maxdag, x.dag);
+      // problem p's DAG levels: HF.ext[dag_off[dag_start[p] + d - 1], dag_off[... + d])
+      const int32_t ebase = (int32_t)HF.ext.size();
+      size_t k = 0;
+      for (int d = 1; d <= maxdag; ++d) {
+        HF.dag_off.push_back(ebase + (int32_t)k);
+        while (k < ext.size() && ext[k].dag == d) ++k;
+      }
+      HF.dag_off.push_back(ebase + (int32_t)ext.size());
+      HF.dag_start.push_back((int32_t)HF.dag_off.size());
+      for (const Ext& x : ext) {
+        ExtRec r;
+        r.node = padf(x.node);
+        for (int a = 0; a < 3; ++a) {
+          r.src[a] = padf(x.src[a]);
+          r.wt[a] = x.wt[a];
+        }
+        HF.ext.push_back(r);
+      }
+      HF.ext_off.push_back((int32_t)HF.ext.size());
+      // restriction codes of the coarse nodes
+      const Geo& gc = HC.g;
+      const int64_t basec = (int64_t)p * gc.npp;
+      for (int64_t X = 0; X < C.nn; ++X) {
+        if (C.cls[X] == OUT) continue;
+        int jc[3], jf[3] = {0, 0, 0};
+        jof(C, X, jc);
+        for (int a = 0; a < D; ++a) jf[a] = 2 * jc[a];
+        const bool inside = C.cls[X] == IN;
+        const int lab = (!inside && G.split) ? F.lab[iof(F, jf)] : -1;
+        HC.rcode[basec + jc[0] + gc.st[1] * jc[1] + gc.st[2] * jc[2]] = box_code(F, jf, inside, lab);
+      }
+    }
+    // the coarsest system and its inverse
+    {
+      PL& C = lev[L];
+      HostLevel& HC = H->host[L];
+      const Geo& gc = HC.g;
+      const int64_t basec = (int64_t)p * gc.npp;
+      std::vector<int64_t> col(C.nn, -1);
+      std::vector<int64_t> um;
+      for (int64_t i = 0; i < C.nn; ++i)
+        if (C.cls[i] != OUT) {
+          col[i] = (int64_t)um.size();
+          um.push_back(i);
+        }
+      const int nu = (int)um.size();
+      std::vector<double> A((size_t)nu * nu, 0.0);
+      const double ih2 = 1.0 / (C.h * C.h);
+      const double inv_h = 1.0 / C.h;
+      for (int r = 0; r < nu; ++r) {
+        const int64_t P = um[r];
+        if (C.cls[P] == IN) {
+          A[(size_t)r * nu + r] += 2.0 * D * ih2;
+          for (int a = 0; a < D; ++a) {
+            A[(size_t)r * nu + col[P - C.st[a]]] -= ih2;
+            A[(size_t)r * nu + col[P + C.st[a]]] -= ih2;
+          }
+        } else {
+          const GhostRec& gr = C.gh[C.gid[P]];
+          double w[27];
+          uint32_t used = D == 2 ? ghost_row<2>(gr, inv_h, w) : ghost_row<3>(gr, inv_h, w);
+          const int K = D == 2 ? 9 : 27;
+          for (int t = 0; t < K; ++t) {
+            if (!(used >> t & 1u)) continue;
+            int64_t off = 0, tt = t;
+            for (int c = D - 1; c >= 0; --c) {
+              off += (int64_t)gr.s[c] * (tt % 3) * C.st[c];
+              tt /= 3;
+            }
+            A[(size_t)r * nu + col[P + off]] += w[t];
+          }
+        }
+      }
+      std::vector<double> inv;
+      int rc = invert(A, nu, inv);
+      if (rc) return rc;
+      for (int r = 0; r < nu; ++r) {
+        int j[3];
+        jof(C, um[r], j);
+        HC.umap.push_back((int32_t)(basec + j[0] + gc.st[1] * j[1] + gc.st[2] * j[2]));
+      }
+      HC.umap_off.push_back((int32_t)HC.umap.size());
+      HC.ainv.insert(HC.ainv.end(), inv.begin(), inv.end());
+      HC.ainv_off.push_back((int64_t)HC.ainv.size());
+    }
+  }
+  // extension lists merged over problems by DAG level (for launches per DAG level)
+  for (int l = 0; l < L; ++l) {
+    HostLevel& HF = H->host[l];
+    int maxdag = 0;
+    for (int p = 0; p < batch; ++p) maxdag = std::max(maxdag, HF.dag_start[p + 1] - HF.dag_start[p] - 1);
+    HF.gdag_off.clear();
+    HF.ext_merged.clear();
+    for (int d = 1; d <= maxdag; ++d) {
+      HF.gdag_off.push_back((int32_t)HF.ext_merged.size());
+      for (int p = 0; p < batch; ++p) {
+        const int nd = HF.dag_start[p + 1] - HF.dag_start[p] - 1;
+        if (d > nd) continue;
+        const int32_t a = HF.dag_off[HF.dag_start[p] + d - 1], b = HF.dag_off[HF.dag_start[p] + d];
+        HF.ext_merged.insert(HF.ext_merged.end(), HF.ext.begin() + a, HF.ext.begin() + b);
+      }
+    }
+    HF.gdag_off.push_back((int32_t)HF.ext_merged.size());
+  }
+  return MG_OK;
+}
+
+}  // namespace ghostmg

@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Setup lists must be identical; defects agree to rounding; the iterates of the red-black
+cycle agree after every cycle (a race or a wrong index changes them); solutions match the
+oracle's discrete solution (a direct solve of the assembled system, or the oracle's own
+multigrid at sizes where no direct solve fits) to 1e-10 in the relative max norm.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import Oracle, default_grid  # noqa: E402
+from workloads import geometry as geo, problems as pr  # noqa: E402
+
+
+def _gm():
+    from paper_1111_0983_amd import ghostmg as gm
+    return gm
+
+
+DEV = "cuda:0"
+
+
+def _case(name):
+    if name == "disk64":
+        w = pr.disk64()
+        return w.domain, 2, 64, 4, w.rule, w.solution
+    if name == "flower256":
+        w = pr.flower(256, 32)
+        return w.domain, 2, 256, 32, w.rule, w.solution
+    if name == "flower200ish":
+        # n = 320 = 5 * 64: many 64-wide tiles with a ragged last column of tiles
+        w = pr.flower(320, 40)
+        return w.domain, 2, 320, 40, w.rule, w.solution
+    if name == "circle_paper":
+        return geo.paper_circle(), 2, 128, 8, pr.paper_rule(), pr.SinCosXY()
+    if name == "torus32":
+        w = pr.torus(32, 8)
+        return w.domain, 3, 32, 8, w.rule, w.solution
+    if name == "torus48":
+        w = pr.torus(48, 12)
+        return w.domain, 3, 48, 12, w.rule, w.solution
+    raise KeyError(name)
+
+
+def _build(name, **kw):
+    gm = _gm()
+    dom, dim, n, nc, rule, sol = _case(name)
+    phi = dom.nodal_phi(n)
+    grid = gm.mg_grid_default(dim, n, nc, **kw)
+    s = gm.Solver(torch.from_numpy(phi).to(DEV), [rule], grid)
+    okw = {}
+    for k in ("nu1", "nu2", "gamma", "split"):
+        if k in kw:
+            okw[k] = kw[k]
+    if "lam" in kw:
+        okw["lam"] = kw["lam"]
+    o = Oracle(phi, default_grid(dim, n, nc, ordering=1, **okw), rule)
+    return s, o, dom, dim, n, rule, sol
+
+
+def _rhs_gpu(s, dom, dim, n, sol):
+    c = s.classes()
+    G = s.ghosts()
+    P = geo.grid_points(dim, n)
+    f = np.where(c == 1, sol.f(P), 0.0)
+    g = pr.rhs_from_ghosts(dim, n, c, G["node"], G["B"], G["type"], sol, dom)
+    return f, g
+
+
+def _rhs_oracle(o, dom, dim, n, sol):
+    c, _ = o.cls(0)
+    G = o.ghosts(0)
+    return pr.rhs_from_ghosts(dim, n, c, G["node"], G["B"], G["type"], sol, dom)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.mark.parametrize("name", ["disk64", "flower256", "torus32"])
+def test_setup_lists_match_oracle(name):
+    s, o, *_ = _build(name)
+    assert s.nlev == o.nlev
+    for l in range(o.nlev):
+        c = s.classes(0, l)
+        oc, ob = o.cls(l)
+        assert np.array_equal(c, oc)
+        G = s.ghosts(0, l)
+        OG = o.ghosts(l)
+        assert np.array_equal(G["node"], OG["node"])
+        assert np.array_equal(G["type"], OG["type"])
+        assert np.array_equal(G["rung"], OG["rung"])
+        assert np.abs(G["B"] - OG["B"]).max() <= 1e-14
+        N = G["type"] == 0
+        if N.any():
+            assert np.abs(G["nB"][N] - OG["nB"][N]).max() <= 1e-13
+        info = s.level(l)
+        oi = o.info(l)
+        assert info["nint"] == oi["nint"] and info["nghost"] == oi["ng"]
+        assert info["nband"] == oi["nband"]
+        if l < o.nlev - 1:
+            assert info["next"] == oi["ne"]
+
+
+@pytest.mark.parametrize("name", ["disk64", "flower256", "torus32"])
+def test_defect_matches_oracle(name):
+    s, o, dom, dim, n, rule, sol = _build(name)
+    rhs = _rhs_oracle(o, dom, dim, n, sol)
+    c, _ = o.cls(0)
+    rng = np.random.default_rng(5)
+    u = np.where(c > 0, rng.uniform(-1, 1, c.size), 0.0)
+    r_ref, (ni, ng) = o.defect(0, u, rhs)
+    r = torch.zeros(c.size, dtype=torch.float64, device=DEV)
+    norms = s.residual(_t(rhs), _t(rhs), _t(u), r)
+    got = r.cpu().numpy()
+    scale = np.abs(r_ref).max()
+    assert np.abs(got - r_ref).max() <= 1e-13 * scale
+    assert abs(norms[0, 0] - ni) <= 1e-13 * scale and abs(norms[0, 1] - ng) <= 1e-13 * max(ng, 1)
+
+
+@pytest.mark.parametrize("name,kw", [("disk64", {}), ("flower256", {}), ("flower200ish", {}),
+                                     ("circle_paper", dict(gamma=2)), ("torus32", {}),
+                                     ("flower256", dict(split=0))])
+def test_cycle_iterates_match_oracle(name, kw):
+    """Red-black V(2,1) (or W) iterates after each of the first five cycles."""
+    s, o, dom, dim, n, rule, sol = _build(name, **kw)
+    rhs = _rhs_oracle(o, dom, dim, n, sol)
+    c, _ = o.cls(0)
+    rng = np.random.default_rng(9)
+    u0 = np.where(c > 0, rng.uniform(-1, 1, c.size), 0.0)
+    uo = u0.copy()
+    ug = _t(u0)
+    for k in range(5):
+        o.cycle(uo, rhs)
+        s.cycles(_t(rhs), _t(rhs), ug, 1)
+        got = ug.cpu().numpy()
+        err = np.abs(got - uo).max() / np.abs(uo).max()
+        assert err <= 1e-12, (k, err)
+
+
+@pytest.mark.parametrize("name", ["disk64", "flower256", "flower200ish", "torus32"])
+def test_fp64_solution_matches_oracle(name):
+    s, o, dom, dim, n, rule, sol = _build(name)
+    f, g = _rhs_gpu(s, dom, dim, n, sol)
+    u = torch.zeros(f.size, dtype=torch.float64, device=DEV)
+    info = s.solve(_t(f), _t(g), u, tol=1e-12)
+    assert info["status"] == 0
+    ref = o.direct_solve(_rhs_oracle(o, dom, dim, n, sol))
+    got = u.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+    c = s.classes()
+    assert np.all(got[c == 0] == 0.0)
+
+
+@pytest.mark.parametrize("name", ["disk64", "flower256", "torus32"])
+def test_fp32_defect_correction_matches_oracle(name):
+    gm = _gm()
+    s, o, dom, dim, n, rule, sol = _build(name, precision=gm.MG_FP32_DC, inner_cycles=2)
+    f, g = _rhs_gpu(s, dom, dim, n, sol)
+    u = torch.zeros(f.size, dtype=torch.float64, device=DEV)
+    info = s.solve(_t(f), _t(g), u, tol=1e-12)
+    assert info["status"] == 0 and info["outer"] > 1
+    ref = o.direct_solve(_rhs_oracle(o, dom, dim, n, sol))
+    assert np.abs(u.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_batch_of_problems_matches_single_solves():
+    gm = _gm()
+    n, nc = 128, 16
+    doms = [geo.Disk((0.05, -0.1), 0.55), geo.Flower(0.5, 0.15, 5),
+            geo.UnionOfEllipses([geo.Ellipse((-0.2, 0.1), 0.4, 0.25, 0.3),
+                                 geo.Ellipse((0.25, -0.1), 0.35, 0.3, 1.1)])]
+    rules = [pr.halfspace_rule([0.0, 1.0]), pr.halfspace_rule([1.0, 0.0]),
+             pr.halfspace_rule([0.6, 0.8], 0.1)]
+    sol = pr.SinCosXY()
+    phis = np.concatenate([d.nodal_phi(n) for d in doms])
+    grid = gm.mg_grid_default(2, n, nc, batch=len(doms))
+    s = gm.Solver(_t(phis), rules, grid)
+    nn = (n + 1) ** 2
+    P = geo.grid_points(2, n)
+    fs, gs = [], []
+    for p, d in enumerate(doms):
+        c = s.classes(p)
+        G = s.ghosts(p)
+        fs.append(np.where(c == 1, sol.f(P), 0.0))
+        gs.append(pr.rhs_from_ghosts(2, n, c, G["node"], G["B"], G["type"], sol, d))
+    u = torch.zeros(len(doms) * nn, dtype=torch.float64, device=DEV)
+    info = s.solve(_t(np.concatenate(fs)), _t(np.concatenate(gs)), u, tol=1e-12)
+    assert info["status"] == 0
+    got = u.cpu().numpy().reshape(len(doms), nn)
+    for p, d in enumerate(doms):
+        o = Oracle(d.nodal_phi(n), default_grid(2, n, nc), rules[p])
+        ref = o.direct_solve(_rhs_oracle(o, d, 2, n, sol))
+        assert np.abs(got[p] - ref).max() <= 1e-10 * np.abs(ref).max(), p
+
+
+def test_error_paths():
+    gm = _gm()
+    s, o, dom, dim, n, rule, sol = _build("disk64")
+    f, g = _rhs_gpu(s, dom, dim, n, sol)
+    u = torch.zeros(f.size, dtype=torch.float64, device=DEV)
+    bad = f.copy()
+    bad[np.argmax(np.abs(g))] = np.nan
+    gb = g.copy()
+    gb[np.argmax(np.abs(g))] = np.nan
+    info = s.solve(_t(f), _t(gb), u, tol=1e-10, check=False)
+    assert info["status"] == gm.MG_EINVAL
+    s2 = gm.Solver(_t(dom.nodal_phi(n)), [rule], gm.mg_grid_default(2, n, 4, max_cycles=3))
+    info = s2.solve(_t(f), _t(g), torch.zeros_like(u), tol=1e-14, check=False)
+    assert info["status"] == gm.MG_ENOCONV and info["cycles"] == 3
+    with pytest.raises(gm.GhostMGError) as e:
+        gm.Solver(_t(np.ones((n + 1) ** 2)), [rule], gm.mg_grid_default(2, n, 4))
+    assert e.value.code == gm.MG_EGEOM
+    with pytest.raises(gm.GhostMGError) as e:
+        gm.Solver(_t(dom.nodal_phi(n)), [rule], gm.mg_grid_default(2, n, 5))
+    assert e.value.code == gm.MG_EINVAL
+
+
+def test_repeat_solves_are_bitwise_identical():
+    s, o, dom, dim, n, rule, sol = _build("flower256")
+    f, g = _rhs_gpu(s, dom, dim, n, sol)
+    outs = []
+    for _ in range(2):
+        u = torch.zeros(f.size, dtype=torch.float64, device=DEV)
+        info = s.solve(_t(f), _t(g), u, tol=1e-10)
+        outs.append((u.cpu().numpy(), info["history"]))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
