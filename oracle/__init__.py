@@ -252,16 +252,24 @@ class Oracle:
         A = sp.csr_matrix((dat, ind, indptr), shape=(nr.value, nr.value))
         return A, rowmap
 
-    def direct_solve(self, rhs, l: int = 0, dense: bool = False):
+    def direct_solve(self, rhs, l: int = 0, dense: bool = False, refine: int = 2):
         """The unique solution of Eq. (discr): a library direct solve of the assembled
-        rows (LAPACK for dense, SuperLU for sparse)."""
+        rows (LAPACK for dense, SuperLU for sparse), followed by `refine` steps of iterative
+        refinement with the same factorisation (the Neumann rows make the system's
+        condition number ~1e6, so a plain FP64 factor solve is accurate to ~1e-10 only)."""
         A, rowmap = self.assemble(l)
         b = self._arr(rhs, l)[rowmap]
         if dense:
-            x = np.linalg.solve(A.toarray(), b)
+            import scipy.linalg as sla
+            fac = sla.lu_factor(A.toarray())
+            solve = lambda v: sla.lu_solve(fac, v)
         else:
             import scipy.sparse.linalg as spla
-            x = spla.spsolve(A.tocsc(), b)
+            fac = spla.splu(A.tocsc())
+            solve = fac.solve
+        x = solve(b)
+        for _ in range(refine):
+            x = x + solve(b - A @ x)
         u = np.zeros(self.info(l)["nn"])
         u[rowmap] = x
         return u
