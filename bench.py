@@ -29,6 +29,61 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def bench_torus(args, gm, pr, geo, np, torch, dev, step):
+    """3D torus (R, r) = (0.5, 0.25) on [-1, 1]^3, Neumann where z < 0, Dirichlet where
+    z >= 0, u = exp(x + y) cos(z), coarsest grid 16: FP64 cycles against FP32 cycles inside
+    FP64 defect correction, both to 1e-10."""
+    n = args.n3d
+    w = pr.torus(n, 16)
+    phi = w.domain.nodal_phi(n)
+    out = {}
+    ref = None
+    for name, prec in (("fp64", gm.MG_FP64), ("fp32dc", gm.MG_FP32_DC)):
+        grid = gm.mg_grid_default(3, n, 16, precision=prec, inner_cycles=2)
+        t0 = time.time()
+        s = gm.Solver(torch.from_numpy(phi).to(dev), [w.rule], grid)
+        setup = time.time() - t0
+        if ref is None:
+            c = s.classes()
+            G = s.ghosts()
+            P = geo.grid_points(3, n)
+            f = torch.from_numpy(np.where(c == 1, w.solution.f(P), 0.0)).to(dev)
+            g = torch.from_numpy(pr.rhs_from_ghosts(3, n, c, G["node"], G["B"], G["type"],
+                                                    w.solution, w.domain)).to(dev)
+            unknowns = int((c > 0).sum())
+        u = torch.zeros_like(f)
+        for _ in range(args.warmup):
+            info = step_fg(s, u, f, g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            info = step_fg(s, u, f, g)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        if ref is None:
+            ref = u.clone()
+            err = float(np.abs(u.cpu().numpy() - w.solution.u(P))[c == 1].max())
+            out["torus_max_error_vs_exact"] = err
+        else:
+            out["torus_fp32dc_vs_fp64_rel_diff"] = float((u - ref).abs().max() / ref.abs().max())
+        out[f"torus_{name}_unknowns_per_s"] = unknowns / dt
+        out[f"torus_{name}_ms"] = 1e3 * dt
+        out[f"torus_{name}_cycles"] = info["cycles"]
+        out[f"torus_{name}_rel_residual"] = info["rel"]
+        out[f"torus_{name}_setup_s"] = setup
+        log(f"[bench] torus {n}^3 {name}: {1e3 * dt:.1f} ms, {info['cycles']} cycles, "
+            f"rel {info['rel']:.2e}, setup {setup:.1f}s")
+        s.close()
+    out["torus_unknowns"] = unknowns
+    out["torus_workload"] = f"torus-{n}^3 3D V(2,1) lambda=5 Nc=16 tol=1e-10"
+    return out
+
+
+def step_fg(solver, uu, f, g):
+    uu.zero_()
+    return solver.solve(f, g, uu, tol=1e-10)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -37,6 +92,8 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dc", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--n3d", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -120,6 +177,9 @@ def main():
         log(f"[bench] FP32-DC: {1e3 * dtdc / args.steps:.2f} ms/solve, {idc['cycles']} FP32 "
             f"cycles in {idc['outer']} steps, diff vs FP64 {diff:.2e}")
         sdc.close()
+
+    if not args.no_3d:
+        extra.update(bench_torus(args, gm, pr, geo, np, torch, dev, step))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -48,6 +48,8 @@ int max_span(const std::vector<int32_t>& off) {
 constexpr int kSingleWgBand = 24576;
 constexpr int kSingleWgExt = 24576;
 constexpr int kMaxCoarse = 8192;
+constexpr int kChunkOwn = 512;   // owned band nodes per LDS chunk
+constexpr int kChunkLds = 64 * 1024;  // LDS bytes per chunk
 
 int upload_level(mg_handle_s* H, int l) {
   const HostLevel& S = H->host[l];
@@ -93,6 +95,41 @@ int upload_level(mg_handle_s* H, int l) {
     if ((rc = alloc_zero(&L.r32, nn))) return rc;
     if ((rc = alloc_zero(&L.gtmp32, (size_t)L.nghost + 1))) return rc;
   }
+  if (!S.bc_off.empty() && S.bc_off.size() > 1) {
+    L.nchunks = (int)S.bc_own.size();
+    L.bc_smax = S.bc_smax;
+    L.bc_gmax = S.bc_gmax;
+    L.bc_opsmax = S.bc_opsmax;
+    L.bc_nown = (int)S.bc_own_node.size();
+    L.bc_phases = 1 + 3 * H->grid.lambda;
+    if ((rc = upload(&L.bc_off, S.bc_off))) return rc;
+    if ((rc = upload(&L.bc_own, S.bc_own))) return rc;
+    if ((rc = upload(&L.bc_out_off, S.bc_out_off))) return rc;
+    if ((rc = upload(&L.bc_node, S.bc_node))) return rc;
+    if ((rc = upload(&L.bc_nbr, S.bc_nbr))) return rc;
+    if ((rc = upload(&L.bc_goff, S.bc_goff))) return rc;
+    if ((rc = upload(&L.bc_gent, S.bc_gent))) return rc;
+    if ((rc = upload(&L.bc_gidx, S.bc_gidx))) return rc;
+    if ((rc = upload(&L.bc_gsten, S.bc_gsten))) return rc;
+    if ((rc = upload(&L.bc_ops, S.bc_ops))) return rc;
+    if ((rc = upload(&L.bc_ops_off, S.bc_ops_off))) return rc;
+    if ((rc = upload(&L.bc_own_node, S.bc_own_node))) return rc;
+    if (need64 && (rc = alloc_zero(&L.bc_out64, (size_t)L.bc_nown + 1))) return rc;
+    if (dc && (rc = alloc_zero(&L.bc_out32, (size_t)L.bc_nown + 1))) return rc;
+  }
+  if (S.ec_off.size() > 1) {
+    L.nechunks = (int)S.ec_own.size();
+    L.ec_smax = S.ec_smax;
+    if ((rc = upload(&L.ec_off, S.ec_off))) return rc;
+    if ((rc = upload(&L.ec_own, S.ec_own))) return rc;
+    if ((rc = upload(&L.ec_next, S.ec_next))) return rc;
+    if ((rc = upload(&L.ec_node, S.ec_node))) return rc;
+    if ((rc = upload(&L.ec_src, S.ec_src))) return rc;
+    if ((rc = upload(&L.ec_wt, S.ec_wt))) return rc;
+    if ((rc = upload(&L.ec_ops, S.ec_ops))) return rc;
+    if ((rc = upload(&L.ec_lvl, S.ec_lvl))) return rc;
+    if ((rc = upload(&L.ec_lvl_start, S.ec_lvl_start))) return rc;
+  }
   if (l == H->L) {
     L.nu_max = max_span(S.umap_off);
     if ((rc = upload(&L.umap, S.umap))) return rc;
@@ -107,6 +144,7 @@ template <typename T>
 struct Arr;
 template <>
 struct Arr<double> {
+  static double* bout(DevLevel& L) { return L.bc_out64; }
   static double* u(DevLevel& L) { return L.u64; }
   static double* rhs(DevLevel& L) { return L.rhs64; }
   static double* r(DevLevel& L) { return L.r64; }
@@ -114,19 +152,30 @@ struct Arr<double> {
 };
 template <>
 struct Arr<float> {
+  static float* bout(DevLevel& L) { return L.bc_out32; }
   static float* u(DevLevel& L) { return L.u32; }
   static float* rhs(DevLevel& L) { return L.rhs32; }
   static float* r(DevLevel& L) { return L.r32; }
   static float* tmp(DevLevel& L) { return L.gtmp32; }
 };
 
+// Ghost relaxation and the lambda band sweeps: LDS chunks where the level has them, else
+// one launch per phase.
+template <int D, typename T>
+void band(mg_handle_s* H, int l, hipStream_t s) {
+  DevLevel& L = H->dev[l];
+  if (L.nchunks)
+    launch_band_chunks<D, T>(L, H->grid, Arr<T>::u(L), Arr<T>::rhs(L), Arr<T>::bout(L), s);
+  else
+    launch_band<D, T>(L, H->grid, Arr<T>::u(L), Arr<T>::rhs(L), Arr<T>::tmp(L), false, H->batch, s);
+}
+
 // One relaxation: red-black interior sweep, then ghost relaxation and lambda band sweeps.
 template <int D, typename T>
 void relax(mg_handle_s* H, int l, hipStream_t s) {
   DevLevel& L = H->dev[l];
   launch_smooth<D, T>(L, Arr<T>::u(L), Arr<T>::rhs(L), s);
-  const bool single = L.max_bandp + L.max_gp <= kSingleWgBand;
-  launch_band<D, T>(L, H->grid, Arr<T>::u(L), Arr<T>::rhs(L), Arr<T>::tmp(L), single, H->batch, s);
+  band<D, T>(H, l, s);
 }
 
 // The cycle of Sec. 2.4 from level l (TGCS recursion, gamma = 1 V, 2 W).
@@ -139,7 +188,10 @@ void cycle(mg_handle_s* H, int l, hipStream_t s) {
   }
   for (int i = 0; i < H->grid.nu1; ++i) relax<D, T>(H, l, s);
   launch_defect<D, T, T>(L, Arr<T>::u(L), Arr<T>::rhs(L), Arr<T>::r(L), nullptr, s);
-  launch_extend<T>(L, Arr<T>::r(L), L.max_extp <= kSingleWgExt, H->batch, s);
+  if (L.nechunks)
+    launch_extend_chunks<T>(L, Arr<T>::r(L), s);
+  else
+    launch_extend<T>(L, Arr<T>::r(L), L.max_extp <= kSingleWgExt, H->batch, s);
   DevLevel& C = H->dev[l + 1];
   launch_restrict<D, T>(L, C, Arr<T>::r(L), Arr<T>::rhs(C), Arr<T>::u(C), s);
   for (int k = 0; k < H->grid.gamma; ++k) cycle<D, T>(H, l + 1, s);
@@ -300,7 +352,12 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
 }
 
 void free_level(DevLevel& L) {
-  void* ptrs[] = {L.cls, L.phi, L.tiles, L.ghosts, L.ghost_off, L.red, L.black, L.red_off, L.black_off,
+  void* ptrs[] = {L.bc_off, L.bc_own, L.bc_out_off, L.bc_node, L.bc_nbr, L.bc_goff, L.bc_gent,
+                  L.bc_gidx, L.bc_gsten,
+                  L.bc_ops, L.bc_ops_off, L.bc_own_node, L.bc_out64, L.bc_out32,
+                  L.ec_off, L.ec_own, L.ec_next, L.ec_node, L.ec_src, L.ec_wt, L.ec_ops,
+                  L.ec_lvl, L.ec_lvl_start,
+                  L.cls, L.phi, L.tiles, L.ghosts, L.ghost_off, L.red, L.black, L.red_off, L.black_off,
                   L.ext, L.ext_merged, L.ext_off, L.dag_off, L.dag_start, L.rcode, L.u64, L.rhs64,
                   L.r64, L.gtmp64, L.u32, L.rhs32, L.r32, L.gtmp32, L.umap, L.umap_off,
                   L.ainv_off, L.ainv};
@@ -381,6 +438,19 @@ int mg_setup(const double* phi, const mg_bc_rule* bc, const mg_grid* grid, mg_ha
     std::memcpy(phi_h.data(), phi, phi_h.size() * sizeof(double));
   }
   int rc = build_hierarchy(H, phi_h.data());
+  // boundary-band chunks (levels that relax: all but the coarsest)
+  if (!rc)
+    for (int l = 0; l < L; ++l)
+      if (!build_band_chunks(H, l, kChunkOwn, kChunkLds, 4.0)) {
+        H->host[l].bc_off.clear();
+        H->host[l].bc_own.clear();
+      }
+  if (!rc)
+    for (int l = 0; l < L; ++l)
+      if (!build_ext_chunks(H, l, kChunkOwn, 8192)) {
+        H->host[l].ec_off.assign(1, 0);
+        H->host[l].ec_own.clear();
+      }
   // the coarsest right-hand side of one problem is staged in 64 KB of LDS
   if (!rc && max_span(H->host[L].umap_off) > kMaxCoarse) rc = MG_EINVAL;
   if (!rc) {
@@ -518,13 +588,13 @@ int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_m
         if (kernel == 1) launch_defect<2, float, float>(L, L.u32, L.rhs32, L.r32, nullptr, s);
         if (kernel == 2) launch_restrict<2, float>(L, h->dev[level + 1], L.r32, h->dev[level + 1].rhs32, h->dev[level + 1].u32, s);
         if (kernel == 3) launch_prolong<2, float>(L, h->dev[level + 1], h->dev[level + 1].u32, L.u32, s);
-        if (kernel == 4) launch_band<2, float>(L, h->grid, L.u32, L.rhs32, L.gtmp32, L.max_bandp + L.max_gp <= kSingleWgBand, h->batch, s);
+        if (kernel == 4) band<2, float>(h, level, s);
       } else {
         if (kernel == 0) launch_smooth<2, double>(L, L.u64, L.rhs64, s);
         if (kernel == 1) launch_defect<2, double, double>(L, L.u64, L.rhs64, L.r64, nullptr, s);
         if (kernel == 2) launch_restrict<2, double>(L, h->dev[level + 1], L.r64, h->dev[level + 1].rhs64, h->dev[level + 1].u64, s);
         if (kernel == 3) launch_prolong<2, double>(L, h->dev[level + 1], h->dev[level + 1].u64, L.u64, s);
-        if (kernel == 4) launch_band<2, double>(L, h->grid, L.u64, L.rhs64, L.gtmp64, L.max_bandp + L.max_gp <= kSingleWgBand, h->batch, s);
+        if (kernel == 4) band<2, double>(h, level, s);
       }
     } else {
       if (dc) {
@@ -532,13 +602,13 @@ int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_m
         if (kernel == 1) launch_defect<3, float, float>(L, L.u32, L.rhs32, L.r32, nullptr, s);
         if (kernel == 2) launch_restrict<3, float>(L, h->dev[level + 1], L.r32, h->dev[level + 1].rhs32, h->dev[level + 1].u32, s);
         if (kernel == 3) launch_prolong<3, float>(L, h->dev[level + 1], h->dev[level + 1].u32, L.u32, s);
-        if (kernel == 4) launch_band<3, float>(L, h->grid, L.u32, L.rhs32, L.gtmp32, L.max_bandp + L.max_gp <= kSingleWgBand, h->batch, s);
+        if (kernel == 4) band<3, float>(h, level, s);
       } else {
         if (kernel == 0) launch_smooth<3, double>(L, L.u64, L.rhs64, s);
         if (kernel == 1) launch_defect<3, double, double>(L, L.u64, L.rhs64, L.r64, nullptr, s);
         if (kernel == 2) launch_restrict<3, double>(L, h->dev[level + 1], L.r64, h->dev[level + 1].rhs64, h->dev[level + 1].u64, s);
         if (kernel == 3) launch_prolong<3, double>(L, h->dev[level + 1], h->dev[level + 1].u64, L.u64, s);
-        if (kernel == 4) launch_band<3, double>(L, h->grid, L.u64, L.rhs64, L.gtmp64, L.max_bandp + L.max_gp <= kSingleWgBand, h->batch, s);
+        if (kernel == 4) band<3, double>(h, level, s);
       }
     }
   };

@@ -62,6 +62,34 @@ struct HostLevel {
   std::vector<uint8_t> rcode;           // restriction code of every node of this level
   std::vector<int4> tiles;              // (problem, tx, ty, tz) of tiles holding unknowns
   int64_t nint = 0, nghost = 0, nband = 0;
+  // boundary band in LDS-resident chunks: each chunk owns band/ghost nodes and carries
+  // every node its owned results depend on through the 1 + 3 lambda relaxation phases
+  std::vector<int32_t> bc_off;          // chunks + 1: offsets into bc_node
+  std::vector<int32_t> bc_own;          // chunks: owned nodes (the first entries of the chunk)
+  std::vector<int32_t> bc_out_off;      // chunks + 1: offsets of the owned results
+  std::vector<int32_t> bc_node;         // node of every chunk entry
+  std::vector<int16_t> bc_nbr;          // 2D local neighbour ids per entry (-1 unused)
+  std::vector<int32_t> bc_goff;         // chunks + 1: offsets into the ghost slots
+  std::vector<int16_t> bc_gent;         // per ghost slot: its local entry id
+  std::vector<int32_t> bc_gidx;         // per ghost slot: ghost record index
+  std::vector<int16_t> bc_gsten;        // per ghost slot: 3^D local stencil ids (-1 unused)
+  std::vector<int16_t> bc_ops;          // per phase: local entry ids (interior phases) or
+                                        // ghost slots (ghost phases)
+  std::vector<int32_t> bc_ops_off;      // chunks * (phases + 1)
+  std::vector<int32_t> bc_own_node;     // owned nodes in output order
+  int bc_smax = 0, bc_gmax = 0, bc_opsmax = 0;  // largest chunk, ghost slots, op list
+  // defect extension in LDS-resident chunks: owned extension nodes, the extension nodes
+  // they depend on, then the ghost defects they read
+  std::vector<int32_t> ec_off;          // chunks + 1: offsets into ec_node
+  std::vector<int32_t> ec_own;          // chunks: owned entries (first)
+  std::vector<int32_t> ec_next;         // chunks: extension entries (owned + dependencies)
+  std::vector<int32_t> ec_node;         // node of every entry
+  std::vector<int16_t> ec_src;          // 3 local source ids per entry (-1 absent)
+  std::vector<double> ec_wt;            // 3 weights per entry
+  std::vector<int16_t> ec_ops;          // extension entries by DAG level
+  std::vector<int32_t> ec_lvl;          // DAG level boundaries into ec_ops, flattened
+  std::vector<int32_t> ec_lvl_start;    // chunks + 1: first boundary of each chunk
+  int ec_smax = 0;
   // coarsest level
   std::vector<int32_t> umap;            // unknown node indices, by problem
   std::vector<int32_t> umap_off;        // batch + 1
@@ -73,6 +101,17 @@ struct DevLevel {
   Geo g;
   int ntiles = 0, nghost = 0, nred = 0, nblack = 0, next = 0, ndag = 0;
   int max_gp = 0, max_bandp = 0, max_extp = 0;   // largest per-problem list sizes
+  int nchunks = 0, bc_smax = 0, bc_gmax = 0, bc_opsmax = 0, bc_nown = 0, bc_phases = 0;
+  int32_t *bc_off = nullptr, *bc_own = nullptr, *bc_out_off = nullptr, *bc_node = nullptr,
+          *bc_goff = nullptr, *bc_gidx = nullptr, *bc_ops_off = nullptr, *bc_own_node = nullptr;
+  int16_t *bc_nbr = nullptr, *bc_gent = nullptr, *bc_gsten = nullptr, *bc_ops = nullptr;
+  double* bc_out64 = nullptr;
+  float* bc_out32 = nullptr;
+  int nechunks = 0, ec_smax = 0;
+  int32_t *ec_off = nullptr, *ec_own = nullptr, *ec_next = nullptr, *ec_node = nullptr,
+          *ec_lvl = nullptr, *ec_lvl_start = nullptr;
+  int16_t *ec_src = nullptr, *ec_ops = nullptr;
+  double* ec_wt = nullptr;
   int8_t* cls = nullptr;
   double* phi = nullptr;
   int4* tiles = nullptr;

@@ -19,6 +19,22 @@ struct BandArgs {
   int lambda;
 };
 
+template <typename T>
+struct BandChunkArgs {
+  const int32_t *off, *own, *out_off, *node, *goff, *gidx, *ops_off;
+  const int16_t *nbr, *gent, *gsten, *ops;
+  const GhostRec* ghosts;
+  T* u;
+  const T* rhs;
+  T* out;
+  int smax, gmax, opsmax, phases;
+  T h2, inv2d;
+  double inv_h, cD, cNh;
+};
+
+template <int D, typename T>
+void launch_band_chunks(const DevLevel& L, const mg_grid& G, T* u, const T* rhs, T* out,
+                        hipStream_t s);
 template <int D, typename T>
 void launch_smooth(const DevLevel& L, T* u, const T* rhs, hipStream_t s);
 template <int D, typename T>
@@ -49,5 +65,10 @@ template <int D>
 void launch_dc_update(const DevLevel& L, double* u64, float* u32, hipStream_t s);
 
 int build_hierarchy(mg_handle_s* H, const double* phi);
+bool build_band_chunks(mg_handle_s* H, int l, int own_target, int lds_budget,
+                       double max_redundancy);
+bool build_ext_chunks(mg_handle_s* H, int l, int own_target, int max_entries);
+template <typename T>
+void launch_extend_chunks(const DevLevel& L, T* r, hipStream_t s);
 
 }  // namespace ghostmg

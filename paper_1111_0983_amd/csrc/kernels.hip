@@ -208,6 +208,90 @@ __global__ void __launch_bounds__(1024) k_band(BandArgs<T> a) {
   }
 }
 
+// Ghost relaxation and lambda band sweeps with the band held in LDS: one workgroup per
+// chunk runs all 1 + 3 lambda phases (ghosts; then red band, black band, ghosts, lambda
+// times) on the chunk's dependency-closed node set, with workgroup barriers between phases,
+// and stores the results of the nodes it owns.  k_band_scatter then writes them to u (no
+// chunk may overwrite a value another chunk is still loading).
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_band_chunk(BandChunkArgs<T> a) {
+  constexpr int K = Pow3<D>::value;
+  extern __shared__ double lds_d[];
+  const int c = blockIdx.x;
+  const int s0 = a.off[c], ns = a.off[c + 1] - s0;
+  const int g0 = a.goff[c], ngc = a.goff[c + 1] - g0;
+  const int32_t* ops_off = a.ops_off + (int64_t)c * (a.phases + 1);
+  const int o_base = ops_off[0], nops = ops_off[a.phases] - o_base;
+  // LDS layout: ghost weights, ghost constants (FP64); u, rhs, new ghost values (T);
+  // neighbour ids, ghost stencil ids, ghost entry ids, op lists (int16)
+  double* gw = lds_d;
+  double* gc = gw + (size_t)a.gmax * K;
+  T* su = (T*)(gc + a.gmax);
+  T* sr = su + a.smax;
+  T* st = sr + a.smax;
+  int16_t* nb = (int16_t*)(st + a.gmax);
+  int16_t* gs = nb + (size_t)a.smax * 2 * D;
+  int16_t* ge = gs + (size_t)a.gmax * K;
+  int16_t* ops = ge + a.gmax;
+  for (int i = threadIdx.x; i < ns; i += 256) {
+    const int32_t v = a.node[s0 + i];
+    su[i] = a.u[v];
+    sr[i] = a.rhs[v];
+  }
+  for (int i = threadIdx.x; i < ns * 2 * D; i += 256) nb[i] = a.nbr[(int64_t)s0 * 2 * D + i];
+  for (int i = threadIdx.x; i < ngc * K; i += 256) gs[i] = a.gsten[(int64_t)g0 * K + i];
+  for (int i = threadIdx.x; i < nops; i += 256) ops[i] = a.ops[o_base + i];
+  for (int j = threadIdx.x; j < ngc; j += 256) {
+    const GhostRec r = a.ghosts[a.gidx[g0 + j]];
+    double w[K];
+    const uint32_t used = ghost_row<D>(r, a.inv_h, w);
+#pragma unroll
+    for (int t = 0; t < K; ++t) gw[(size_t)j * K + t] = (used >> t & 1u) ? w[t] : 0.0;
+    gc[j] = r.type ? a.cD : a.cNh;
+    ge[j] = a.gent[g0 + j];
+  }
+  __syncthreads();
+  for (int p = 0; p < a.phases; ++p) {
+    const int kind = p == 0 ? 3 : ((p - 1) % 3 == 0 ? 1 : ((p - 1) % 3 == 1 ? 2 : 3));
+    const int o0 = ops_off[p] - o_base, o1 = ops_off[p + 1] - o_base;
+    if (kind != 3) {
+      for (int i = o0 + threadIdx.x; i < o1; i += 256) {
+        const int v = ops[i];
+        const int16_t* n = nb + v * (2 * D);
+        const T cv = su[v];
+        T sum = (su[n[0]] - cv) + (su[n[1]] - cv);
+        sum += (su[n[2]] - cv) + (su[n[3]] - cv);
+        if (D == 3) sum += (su[n[4]] - cv) + (su[n[5]] - cv);
+        su[v] = cv + (a.h2 * sr[v] + sum) * a.inv2d;
+      }
+    } else {
+      for (int i = o0 + threadIdx.x; i < o1; i += 256) {
+        const int j = ops[i];
+        const int v = ge[j];
+        const double* w = gw + (size_t)j * K;
+        const int16_t* sn = gs + (size_t)j * K;
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < K; ++t)
+          if (sn[t] >= 0) acc += w[t] * (double)su[sn[t]];
+        st[j] = (T)((double)su[v] + gc[j] * ((double)sr[v] - acc));
+      }
+      __syncthreads();
+      for (int i = o0 + threadIdx.x; i < o1; i += 256) su[ge[ops[i]]] = st[ops[i]];
+    }
+    __syncthreads();
+  }
+  const int own = a.own[c], out0 = a.out_off[c];
+  for (int i = threadIdx.x; i < own; i += 256) a.out[out0 + i] = su[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_band_scatter(const int32_t* __restrict__ node, int n,
+                                                      const T* __restrict__ out, T* __restrict__ u) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) u[node[i]] = out[i];
+}
+
 // ---------------------------------------------------------------------------------------
 // defect (Sec. 2.4 step 3) with per-problem infinity norms
 // ---------------------------------------------------------------------------------------
@@ -311,6 +395,44 @@ __global__ void __launch_bounds__(1024) k_extend_wg(const ExtRec* __restrict__ e
     for (int i = dag_off[d] + threadIdx.x; i < dag_off[d + 1]; i += 1024) extend_one<T>(ext[i], r);
     __syncthreads();
   }
+}
+
+// chunked extension: the chunk's ghost defects are read into LDS, its extension nodes are
+// computed DAG level by DAG level in LDS, and only the owned nodes are written back
+template <typename T>
+__global__ void __launch_bounds__(256) k_extend_chunk(const int32_t* __restrict__ off,
+                                                      const int32_t* __restrict__ own,
+                                                      const int32_t* __restrict__ next,
+                                                      const int32_t* __restrict__ node,
+                                                      const int16_t* __restrict__ src,
+                                                      const double* __restrict__ wt,
+                                                      const int16_t* __restrict__ ops,
+                                                      const int32_t* __restrict__ lvl,
+                                                      const int32_t* __restrict__ lvl_start,
+                                                      T* __restrict__ r) {
+  extern __shared__ double ext_lds[];
+  const int c = blockIdx.x;
+  const int s0 = off[c], ns = off[c + 1] - s0, ne = next[c];
+  double* sv = ext_lds;
+  for (int i = threadIdx.x; i < ns; i += 256) sv[i] = i >= ne ? (double)r[node[s0 + i]] : 0.0;
+  __syncthreads();
+  for (int d = lvl_start[c]; d + 1 < lvl_start[c + 1]; ++d) {
+    for (int k = lvl[d] + threadIdx.x; k < lvl[d + 1]; k += 256) {
+      const int i = ops[k];
+      double num = 0.0, den = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int q = src[(int64_t)(s0 + i) * 3 + a];
+        if (q < 0) continue;
+        const double w = wt[(int64_t)(s0 + i) * 3 + a];
+        num += w * sv[q];
+        den += w;
+      }
+      sv[i] = den > 0.0 ? num / den : 0.0;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < own[c]; i += 256) r[node[s0 + i]] = (T)sv[i];
 }
 
 // all problems' nodes of one DAG level
@@ -570,6 +692,45 @@ void launch_band(const DevLevel& L, const mg_grid& G, T* u, const T* rhs, T* tmp
   }
 }
 
+template <int D, typename T>
+void launch_band_chunks(const DevLevel& L, const mg_grid& G, T* u, const T* rhs, T* out,
+                        hipStream_t s) {
+  if (!L.nchunks) return;
+  BandChunkArgs<T> a;
+  a.off = L.bc_off;
+  a.own = L.bc_own;
+  a.out_off = L.bc_out_off;
+  a.node = L.bc_node;
+  a.nbr = L.bc_nbr;
+  a.goff = L.bc_goff;
+  a.gidx = L.bc_gidx;
+  a.gent = L.bc_gent;
+  a.gsten = L.bc_gsten;
+  a.ops = L.bc_ops;
+  a.ops_off = L.bc_ops_off;
+  a.ghosts = L.ghosts;
+  a.u = u;
+  a.rhs = rhs;
+  a.out = out;
+  a.smax = L.bc_smax;
+  a.gmax = L.bc_gmax;
+  a.opsmax = L.bc_opsmax;
+  a.phases = L.bc_phases;
+  a.h2 = (T)(L.g.h * L.g.h);
+  a.inv2d = (T)(1.0 / (2.0 * D));
+  a.inv_h = 1.0 / L.g.h;
+  a.cD = G.cD;
+  a.cNh = G.cN * L.g.h;
+  constexpr int K = Pow3<D>::value;
+  const size_t lds = (size_t)L.bc_gmax * (K + 1) * sizeof(double) +
+                     (size_t)(2 * L.bc_smax + L.bc_gmax) * sizeof(T) +
+                     ((size_t)L.bc_smax * 2 * D + (size_t)L.bc_gmax * (K + 1) + L.bc_opsmax) *
+                         sizeof(int16_t);
+  hipLaunchKernelGGL((k_band_chunk<D, T>), dim3(L.nchunks), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((k_band_scatter<T>), dim3(lin_grid(L.bc_nown)), dim3(256), 0, s, L.bc_own_node,
+                     L.bc_nown, (const T*)out, u);
+}
+
 template <int D, typename T, typename TO>
 void launch_defect(const DevLevel& L, const T* u, const T* rhs, TO* r, uint64_t* norms,
                    hipStream_t s) {
@@ -602,6 +763,14 @@ void launch_extend(const DevLevel& L, T* r, bool single_wg, int batch, hipStream
       hipLaunchKernelGGL((k_extend_level<T>), dim3(lin_grid(b - a)), dim3(256), 0, s,
                          L.ext_merged, a, b, r);
   }
+}
+
+template <typename T>
+void launch_extend_chunks(const DevLevel& L, T* r, hipStream_t s) {
+  if (!L.nechunks) return;
+  hipLaunchKernelGGL((k_extend_chunk<T>), dim3(L.nechunks), dim3(256), L.ec_smax * sizeof(double), s,
+                     L.ec_off, L.ec_own, L.ec_next, L.ec_node, L.ec_src, L.ec_wt, L.ec_ops, L.ec_lvl,
+                     L.ec_lvl_start, r);
 }
 
 template <int D, typename T>
@@ -656,6 +825,8 @@ void launch_dc_update(const DevLevel& L, double* u64, float* u32, hipStream_t s)
 
 #define GHOSTMG_INST(D, T)                                                                    \
   template void launch_smooth<D, T>(const DevLevel&, T*, const T*, hipStream_t);             \
+  template void launch_band_chunks<D, T>(const DevLevel&, const mg_grid&, T*, const T*, T*,   \
+                                         hipStream_t);                                        \
   template void launch_band<D, T>(const DevLevel&, const mg_grid&, T*, const T*, T*, bool, int, \
                                   hipStream_t);                                               \
   template void launch_defect<D, T, T>(const DevLevel&, const T*, const T*, T*, uint64_t*,    \
@@ -674,6 +845,8 @@ template void launch_defect<3, double, float>(const DevLevel&, const double*, co
                                               uint64_t*, hipStream_t);
 template void launch_extend<double>(const DevLevel&, double*, bool, int, hipStream_t);
 template void launch_extend<float>(const DevLevel&, float*, bool, int, hipStream_t);
+template void launch_extend_chunks<double>(const DevLevel&, double*, hipStream_t);
+template void launch_extend_chunks<float>(const DevLevel&, float*, hipStream_t);
 template void launch_coarse<double>(const DevLevel&, const double*, double*, int, hipStream_t);
 template void launch_coarse<float>(const DevLevel&, const float*, float*, int, hipStream_t);
 template void launch_fill<double>(double*, int64_t, double, hipStream_t);

@@ -693,3 +693,310 @@ int build_hierarchy(mg_handle_s* H, const double* phi) {
 }
 
 }  // namespace ghostmg
+
+namespace ghostmg {
+namespace {
+
+uint64_t spread_bits(uint64_t v, int D) {
+  uint64_t r = 0;
+  for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ull) << (D * b);
+  return r;
+}
+
+}  // namespace
+
+// Partition the boundary band of level l into chunks for the LDS band kernel.  Phase 0
+// relaxes the ghosts; phases 3k-2, 3k-1, 3k (k = 1..lambda) the red band, the black band and
+// the ghosts.  For every chunk the set S of nodes is closed backwards over the phases: a node
+// whose value after phase t is needed, and which phase t updates, needs the values after
+// phase t-1 of every node it reads.  Returns false when chunks would exceed smax entries or
+// the redundant work would exceed `max_redundancy` (then the phases run as separate launches).
+bool build_band_chunks(mg_handle_s* H, int l, int own_target, int lds_budget,
+                       double max_redundancy) {
+  HostLevel& HL = H->host[l];
+  const int D = H->dim, lambda = H->grid.lambda;
+  const Geo& g = HL.g;
+  const int K = D == 2 ? 9 : 27;
+  const int P = 1 + 3 * lambda;
+  const size_t nn = HL.cls.size();
+  const int elem = 8;  // LDS sized for FP64 values (the FP32 kernels need less)
+  // role of a node: 1 red, 2 black, 3 ghost, 0 other
+  std::vector<int8_t> role(nn, 0);
+  std::vector<int32_t> gidx(nn, -1);
+  for (int32_t v : HL.red) role[v] = 1;
+  for (int32_t v : HL.black) role[v] = 2;
+  for (size_t i = 0; i < HL.ghosts.size(); ++i) {
+    role[HL.ghosts[i].node] = 3;
+    gidx[HL.ghosts[i].node] = (int32_t)i;
+  }
+  auto kind = [&](int p) { return p == 0 ? 3 : ((p - 1) % 3 == 0 ? 1 : ((p - 1) % 3 == 1 ? 2 : 3)); };
+  const double inv_h = 1.0 / g.h;
+  auto stencil = [&](int32_t v, std::vector<int32_t>& out) {
+    out.clear();
+    const GhostRec& r = HL.ghosts[gidx[v]];
+    double w[27];
+    const uint32_t used = D == 2 ? ghost_row<2>(r, inv_h, w) : ghost_row<3>(r, inv_h, w);
+    for (int t = 0; t < K; ++t)
+      out.push_back(used >> t & 1u ? (int32_t)(v + (D == 2 ? template_offset<2>(t, r.s, g.st)
+                                                            : template_offset<3>(t, r.s, g.st)))
+                                   : -1);
+  };
+  auto reads = [&](int32_t v, std::vector<int32_t>& out) {
+    if (role[v] == 3) {
+      stencil(v, out);
+      out.erase(std::remove(out.begin(), out.end(), -1), out.end());
+      out.push_back(v);
+    } else {
+      out.clear();
+      out.push_back(v);
+      for (int a = 0; a < D; ++a) {
+        out.push_back((int32_t)(v - g.st[a]));
+        out.push_back((int32_t)(v + g.st[a]));
+      }
+    }
+  };
+  // updatable nodes in Morton order within each problem
+  std::vector<std::pair<uint64_t, int32_t>> U;
+  for (size_t v = 0; v < nn; ++v) {
+    if (!role[v]) continue;
+    const int64_t p = (int64_t)v / g.npp;
+    int64_t loc = (int64_t)v - p * g.npp;
+    const int64_t z = D == 3 ? loc / g.st[2] : 0;
+    loc -= z * g.st[2];
+    const int64_t y = loc / g.st[1], x = loc - y * g.st[1];
+    const uint64_t key = spread_bits(x, D) | (spread_bits(y, D) << 1) | (spread_bits(z, D) << 2);
+    U.push_back({((uint64_t)p << 60) | key, (int32_t)v});
+  }
+  std::sort(U.begin(), U.end());
+  HL.bc_off.assign(1, 0);
+  HL.bc_out_off.assign(1, 0);
+  HL.bc_goff.assign(1, 0);
+  HL.bc_own.clear();
+  HL.bc_node.clear();
+  HL.bc_nbr.clear();
+  HL.bc_gent.clear();
+  HL.bc_gidx.clear();
+  HL.bc_gsten.clear();
+  HL.bc_ops.clear();
+  HL.bc_ops_off.clear();
+  HL.bc_own_node.clear();
+  HL.bc_smax = HL.bc_gmax = HL.bc_opsmax = 0;
+  std::vector<int16_t> need(nn, -2);
+  std::vector<int32_t> lid(nn, -1);
+  std::vector<int32_t> touched, rd;
+  int64_t total_s = 0;
+  std::vector<std::pair<size_t, size_t>> pending;
+  for (size_t a = 0; a < U.size();) {
+    size_t b = std::min(U.size(), a + (size_t)own_target);
+    const uint64_t pa = U[a].first >> 60;
+    size_t e = a;
+    while (e < b && (U[e].first >> 60) == pa) ++e;
+    pending.push_back({a, e});
+    a = e;
+  }
+  while (!pending.empty()) {
+    const auto [a, b] = pending.back();
+    pending.pop_back();
+    touched.clear();
+    for (size_t i = a; i < b; ++i) {
+      need[U[i].second] = (int16_t)(P - 1);
+      touched.push_back(U[i].second);
+    }
+    for (int p = P - 1; p >= 0; --p) {
+      const int k = kind(p);
+      const size_t nt = touched.size();
+      for (size_t i = 0; i < nt; ++i) {
+        const int32_t v = touched[i];
+        if (role[v] != k || need[v] < p) continue;
+        reads(v, rd);
+        for (int32_t w : rd) {
+          if (need[w] == -2) touched.push_back(w);
+          if (need[w] < p - 1) need[w] = (int16_t)(p - 1);
+        }
+      }
+    }
+    const int ns = (int)touched.size();
+    int ng_c = 0, nops = 0;
+    for (int32_t v : touched) {
+      if (role[v] == 3) ++ng_c;
+      for (int p = 0; p < P; ++p)
+        if (role[v] == kind(p) && need[v] >= p) ++nops;
+    }
+    // LDS bytes of the chunk kernel: u, rhs; neighbour ids; ghost weights, constants,
+    // new values, stencil ids and entry ids; op lists
+    const int64_t lds = (int64_t)ns * (2 * elem + 4 * D) + (int64_t)ng_c * (8 * K + 8 + elem + 2 * K + 2) +
+                        (int64_t)nops * 2 + 64;
+    if (lds > lds_budget || ns > 32767) {
+      for (int32_t v : touched) need[v] = -2;
+      if (b - a <= 16) return false;
+      const size_t m = a + (b - a) / 2;
+      pending.push_back({m, b});
+      pending.push_back({a, m});
+      continue;
+    }
+    total_s += ns;
+    std::sort(touched.begin() + (b - a), touched.end());
+    for (int i = 0; i < ns; ++i) lid[touched[i]] = i;
+    std::vector<int16_t> slot(ns, -1);
+    int gs = 0;
+    for (int i = 0; i < ns; ++i) {
+      const int32_t v = touched[i];
+      HL.bc_node.push_back(v);
+      for (int a2 = 0; a2 < 2 * D; ++a2) {
+        int16_t q = -1;
+        if (role[v] == 1 || role[v] == 2) {
+          const int32_t w = (int32_t)(v + ((a2 & 1) ? g.st[a2 / 2] : -g.st[a2 / 2]));
+          q = (int16_t)lid[w];
+        }
+        HL.bc_nbr.push_back(q);
+      }
+      if (role[v] == 3) {
+        slot[i] = (int16_t)gs++;
+        HL.bc_gent.push_back((int16_t)i);
+        HL.bc_gidx.push_back(gidx[v]);
+        stencil(v, rd);
+        for (int t = 0; t < K; ++t) HL.bc_gsten.push_back(rd[t] >= 0 ? (int16_t)lid[rd[t]] : (int16_t)-1);
+      }
+    }
+    const int32_t ops0 = (int32_t)HL.bc_ops.size();
+    for (int p = 0; p < P; ++p) {
+      HL.bc_ops_off.push_back((int32_t)HL.bc_ops.size());
+      const int k = kind(p);
+      for (int i = 0; i < ns; ++i) {
+        const int32_t v = touched[i];
+        if (role[v] == k && need[v] >= p) HL.bc_ops.push_back(k == 3 ? slot[i] : (int16_t)i);
+      }
+    }
+    HL.bc_ops_off.push_back((int32_t)HL.bc_ops.size());
+    HL.bc_own.push_back((int32_t)(b - a));
+    for (size_t i = a; i < b; ++i) HL.bc_own_node.push_back(U[i].second);
+    HL.bc_off.push_back((int32_t)HL.bc_node.size());
+    HL.bc_out_off.push_back((int32_t)HL.bc_own_node.size());
+    HL.bc_goff.push_back((int32_t)HL.bc_gent.size());
+    HL.bc_smax = std::max(HL.bc_smax, ns);
+    HL.bc_gmax = std::max(HL.bc_gmax, gs);
+    HL.bc_opsmax = std::max(HL.bc_opsmax, (int)HL.bc_ops.size() - ops0);
+    for (int32_t v : touched) {
+      need[v] = -2;
+      lid[v] = -1;
+    }
+  }
+  if (!U.empty() && (double)total_s > max_redundancy * (double)U.size()) return false;
+  // the kernel lays out LDS for the largest chunk of each kind at once
+  const int64_t lds_max = (int64_t)HL.bc_smax * (2 * elem + 4 * D) +
+                          (int64_t)HL.bc_gmax * (8 * K + 8 + elem + 2 * K + 2) +
+                          (int64_t)HL.bc_opsmax * 2 + 64;
+  return lds_max <= 150 * 1024;
+}
+
+// Partition the extension nodes of level l into chunks for the LDS extension kernel: each
+// chunk owns a Morton-ordered run of extension nodes and carries every extension node they
+// depend on (transitively through their upwind sources), then the ghost defects read.
+bool build_ext_chunks(mg_handle_s* H, int l, int own_target, int max_entries) {
+  HostLevel& HL = H->host[l];
+  const int D = H->dim;
+  const Geo& g = HL.g;
+  HL.ec_off.assign(1, 0);
+  HL.ec_lvl_start.assign(1, 0);
+  HL.ec_own.clear();
+  HL.ec_next.clear();
+  HL.ec_node.clear();
+  HL.ec_src.clear();
+  HL.ec_wt.clear();
+  HL.ec_ops.clear();
+  HL.ec_lvl.clear();
+  HL.ec_smax = 0;
+  if (HL.ext.empty()) return true;
+  const size_t nn = HL.cls.size();
+  std::vector<int32_t> eid(nn, -1);
+  for (size_t i = 0; i < HL.ext.size(); ++i) eid[HL.ext[i].node] = (int32_t)i;
+  // DAG level of each extension record (ghost sources are level 0)
+  std::vector<int> dag(HL.ext.size(), 1);
+  for (size_t i = 0; i < HL.ext.size(); ++i)  // records are stored in DAG order per problem
+    for (int a = 0; a < 3; ++a) {
+      const int32_t q = HL.ext[i].src[a];
+      if (q >= 0 && eid[q] >= 0) dag[i] = std::max(dag[i], dag[eid[q]] + 1);
+    }
+  std::vector<std::pair<uint64_t, int32_t>> U;
+  for (size_t i = 0; i < HL.ext.size(); ++i) {
+    const int32_t v = HL.ext[i].node;
+    const int64_t p = (int64_t)v / g.npp;
+    int64_t loc = (int64_t)v - p * g.npp;
+    const int64_t z = D == 3 ? loc / g.st[2] : 0;
+    loc -= z * g.st[2];
+    const int64_t y = loc / g.st[1], x = loc - y * g.st[1];
+    const uint64_t key = spread_bits(x, D) | (spread_bits(y, D) << 1) | (spread_bits(z, D) << 2);
+    U.push_back({((uint64_t)p << 60) | key, (int32_t)i});
+  }
+  std::sort(U.begin(), U.end());
+  std::vector<int32_t> lid(nn, -1);
+  for (size_t a = 0; a < U.size();) {
+    const uint64_t pa = U[a].first >> 60;
+    size_t b = a;
+    while (b < U.size() && b < a + (size_t)own_target && (U[b].first >> 60) == pa) ++b;
+    // closure over extension sources
+    std::vector<int32_t> ext_e, ghosts_e;
+    std::vector<char> in(HL.ext.size(), 0);
+    for (size_t i = a; i < b; ++i) {
+      ext_e.push_back(U[i].second);
+      in[U[i].second] = 1;
+    }
+    for (size_t k = 0; k < ext_e.size(); ++k)
+      for (int c = 0; c < 3; ++c) {
+        const int32_t q = HL.ext[ext_e[k]].src[c];
+        if (q < 0 || eid[q] < 0 || in[eid[q]]) continue;
+        in[eid[q]] = 1;
+        ext_e.push_back(eid[q]);
+      }
+    for (int32_t e : ext_e)
+      for (int c = 0; c < 3; ++c) {
+        const int32_t q = HL.ext[e].src[c];
+        if (q >= 0 && eid[q] < 0 && lid[q] == -1) {
+          lid[q] = -2;
+          ghosts_e.push_back(q);
+        }
+      }
+    const int ns = (int)(ext_e.size() + ghosts_e.size());
+    if (ns > max_entries) {
+      for (int32_t q : ghosts_e) lid[q] = -1;
+      return false;
+    }
+    int k = 0;
+    for (int32_t e : ext_e) lid[HL.ext[e].node] = k++;
+    for (int32_t q : ghosts_e) lid[q] = k++;
+    for (int32_t e : ext_e) {
+      const ExtRec& r = HL.ext[e];
+      HL.ec_node.push_back(r.node);
+      for (int c = 0; c < 3; ++c) {
+        HL.ec_src.push_back(r.src[c] >= 0 ? (int16_t)lid[r.src[c]] : (int16_t)-1);
+        HL.ec_wt.push_back(r.wt[c]);
+      }
+    }
+    for (int32_t q : ghosts_e) {
+      HL.ec_node.push_back(q);
+      for (int c = 0; c < 3; ++c) {
+        HL.ec_src.push_back(-1);
+        HL.ec_wt.push_back(0.0);
+      }
+    }
+    int maxd = 0;
+    for (int32_t e : ext_e) maxd = std::max(maxd, dag[e]);
+    for (int d = 1; d <= maxd; ++d) {
+      HL.ec_lvl.push_back((int32_t)HL.ec_ops.size());
+      for (size_t i = 0; i < ext_e.size(); ++i)
+        if (dag[ext_e[i]] == d) HL.ec_ops.push_back((int16_t)i);
+    }
+    HL.ec_lvl.push_back((int32_t)HL.ec_ops.size());
+    HL.ec_lvl_start.push_back((int32_t)HL.ec_lvl.size());
+    HL.ec_own.push_back((int32_t)(b - a));
+    HL.ec_next.push_back((int32_t)ext_e.size());
+    HL.ec_off.push_back((int32_t)HL.ec_node.size());
+    HL.ec_smax = std::max(HL.ec_smax, ns);
+    for (int32_t e : ext_e) lid[HL.ext[e].node] = -1;
+    for (int32_t q : ghosts_e) lid[q] = -1;
+    a = b;
+  }
+  return true;
+}
+
+}  // namespace ghostmg

@@ -1,0 +1,306 @@
+"""Training and evaluation of the learned initial guess (random ellipse-union problems).
+
+* generate(): seeded batches of problems are solved by the GPU solver itself (FP64, zero
+  guess); the network inputs and targets are taken on one coarse level of each problem's
+  hierarchy and kept on the GPU.
+* train(): minibatch Adam with the project's BF16 MFMA kernels.
+* evaluate(): cycles and time to the tolerance with the zero guess (FP64 cycles) against
+  the learned guess (FP32 cycles inside FP64 defect correction).
+
+Samples whose domain comes within 3 coarsest mesh widths of the box, or which have a
+connected component without a Dirichlet ghost (a singular problem), are rejected.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import cnn, ghostmg as gm
+
+N_FINE, N_COARSE, LEVEL = 512, 32, 3   # the network works on the 65 x 65 level
+
+
+def _components_ok(cls: np.ndarray, ghosts: dict, n: int) -> bool:
+    from scipy import ndimage
+
+    inside = (cls == 1).reshape(n + 1, n + 1)
+    lab, nlab = ndimage.label(inside)
+    if nlab == 0:
+        return False
+    dirich = ghosts["node"][ghosts["type"] == 1]
+    if len(dirich) == 0:
+        return False
+    # a Dirichlet ghost is attached to the components of its interior neighbours
+    has = np.zeros(nlab + 1, bool)
+    gy, gx = np.divmod(dirich, n + 1)
+    for dy, dx in ((0, 1), (0, -1), (1, 0), (-1, 0)):
+        yy, xx = gy + dy, gx + dx
+        ok = (yy >= 0) & (yy <= n) & (xx >= 0) & (xx <= n)
+        has[lab[yy[ok], xx[ok]]] = True
+    has[0] = False
+    return bool(has[1:].all())
+
+
+def _diverging(solver, f, n, B):
+    """Problems whose defect grows between cycles 5 and 10 from the zero guess: the
+    coarsest grid does not resolve their boundary well enough for the cycle to converge
+    (the paper's caveat on too-coarse grids), so they are rejected like singular ones."""
+    cls = torch.from_numpy(np.concatenate([solver.classes(i) for i in range(B)])).to(f.device)
+    fi = torch.where(cls == 1, f, torch.zeros_like(f)).contiguous()
+    g = torch.zeros_like(fi)
+    u = torch.zeros_like(fi)
+    solver.cycles(fi, g, u, 5)
+    r5 = solver.residual(fi, g, u).max(axis=1)
+    solver.cycles(fi, g, u, 5)
+    r10 = solver.residual(fi, g, u).max(axis=1)
+    return [i for i in range(B) if not (r10[i] < r5[i])]
+
+
+def build_batch(seeds, n=N_FINE, nc=N_COARSE, device="cuda:0", precision=gm.MG_FP64,
+                inner_cycles=2, screen=True):
+    """Solver handle plus f, g for the accepted problems among `seeds`."""
+    from workloads import ellipses as el
+
+    probs, phis, fs = [], [], []
+    for s in seeds:
+        p = el.draw(int(s))
+        phi = el.nodal_phi(p, n, device=device)
+        if not el.accept(phi, n, 3.0 * 2.0 / nc):
+            continue
+        probs.append(p)
+        phis.append(phi)
+        fs.append(el.nodal_f(p, n, device=device))
+    while probs:
+        grid = gm.mg_grid_default(2, n, nc, batch=len(probs), precision=precision,
+                                  inner_cycles=inner_cycles, max_cycles=200)
+        try:
+            solver = gm.Solver(torch.cat(phis), [p.rule for p in probs], grid)
+        except gm.GhostMGError as e:
+            if e.code != gm.MG_EGEOM:
+                raise
+            # find the offending problems one by one on their coarsest grid
+            keep = []
+            for i, (p, phi) in enumerate(zip(probs, phis)):
+                ph = phi.reshape(n + 1, n + 1)[:: n // nc, :: n // nc].contiguous().reshape(-1)
+                try:
+                    gm.Solver(ph, [p.rule], gm.mg_grid_default(2, nc, nc // 2)).close()
+                    keep.append(i)
+                except gm.GhostMGError:
+                    pass
+            if len(keep) == len(probs):
+                raise
+            probs = [probs[i] for i in keep]
+            phis = [phis[i] for i in keep]
+            fs = [fs[i] for i in keep]
+            continue
+        bad = [i for i in range(len(probs))
+               if not _components_ok(solver.classes(i), solver.ghosts(i), n)]
+        if not bad and screen:
+            bad = _diverging(solver, torch.cat(fs), n, len(probs))
+        if bad:
+            solver.close()
+            probs = [p for i, p in enumerate(probs) if i not in bad]
+            phis = [p for i, p in enumerate(phis) if i not in bad]
+            fs = [p for i, p in enumerate(fs) if i not in bad]
+            continue
+        f = torch.cat(fs)
+        # f on the interior nodes only; g = 0 on every ghost
+        cls = torch.from_numpy(np.concatenate([solver.classes(i) for i in range(len(probs))]))
+        f = torch.where(cls.to(f.device) == 1, f, torch.zeros_like(f)).contiguous()
+        g = torch.zeros_like(f)
+        return solver, f, g, probs
+    return None, None, None, []
+
+
+def generate(n_samples: int, seed0: int = 0, batch: int = 64, device="cuda:0", log=print):
+    xs, ts, ms = [], [], []
+    seed = seed0
+    t0 = time.time()
+    total = 0
+    rejected = 0
+    from workloads import ellipses as el
+
+    while total < n_samples:
+        want = min(batch, n_samples - total)
+        seeds = []
+        while len(seeds) < want:  # screen the box margin cheaply before building solvers
+            p = el.draw(seed)
+            if el.accept(el.nodal_phi(p, N_FINE, device=device), N_FINE, 3.0 * 2.0 / N_COARSE):
+                seeds.append(seed)
+            else:
+                rejected += 1
+            seed += 1
+        solver, f, g, probs = build_batch(seeds, device=device)
+        rejected += want - len(probs)
+        if solver is None:
+            continue
+        u = torch.zeros_like(f)
+        info = solver.solve(f, g, u, tol=1e-10)
+        x, scale, (B, H, W) = cnn.features(solver, LEVEL, f, g)
+        tgt, mask = cnn.target(solver, LEVEL, u, scale)
+        xs.append(x.reshape(B, H * W * 8))
+        ts.append(tgt.reshape(B, H * W))
+        ms.append(mask.reshape(B, H * W))
+        total += B
+        solver.close()
+        if log and len(xs) % 10 == 1:
+            log(f"[learned] generated {total}/{n_samples} ({rejected} rejected, "
+                f"last solve {info['cycles']} cycles) {time.time() - t0:.1f}s")
+    return dict(x=torch.cat(xs)[:n_samples], t=torch.cat(ts)[:n_samples],
+                m=torch.cat(ms)[:n_samples], H=H, W=W, rejected=rejected,
+                seconds=time.time() - t0)
+
+
+def train(net: cnn.GuessNet, data: dict, steps: int, batch: int = 64, lr: float = 2e-3,
+          seed: int = 0, log=print, val: dict | None = None):
+    H, W = data["H"], data["W"]
+    n = data["x"].shape[0]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    hist = []
+    t0 = time.time()
+    for step in range(steps):
+        idx = torch.randint(0, n, (batch,), generator=g).to(data["x"].device)
+        x = data["x"][idx].reshape(-1)
+        t = data["t"][idx].reshape(-1)
+        m = data["m"][idx].reshape(-1)
+        lr_t = lr * 0.5 * (1 + np.cos(np.pi * step / steps))
+        pred = net.forward(x, batch, H, W)
+        out, dy = cnn.loss(pred, t, m)
+        net.adam(net.backward(dy, batch, H, W), lr=lr_t)
+        if step % 100 == 0 or step == steps - 1:
+            rec = dict(step=step, loss=out[0].item())
+            if val is not None:
+                rec["val"] = validate(net, val)
+            hist.append(rec)
+            if log:
+                log(f"[learned] step {step} loss {rec['loss']:.4e}"
+                    + (f" val {rec['val']:.4e}" if "val" in rec else "")
+                    + f" {time.time() - t0:.1f}s")
+    return hist
+
+
+def validate(net: cnn.GuessNet, data: dict, batch: int = 64) -> float:
+    H, W = data["H"], data["W"]
+    tot, cnt = 0.0, 0
+    for s in range(0, data["x"].shape[0], batch):
+        x = data["x"][s:s + batch]
+        B = x.shape[0]
+        pred = net.forward(x.reshape(-1), B, H, W)
+        out, _ = cnn.loss(pred, data["t"][s:s + batch].reshape(-1),
+                          data["m"][s:s + batch].reshape(-1), with_grad=False)
+        tot += out[0].item() * B
+        cnt += B
+    return tot / max(cnt, 1)
+
+
+def evaluate(net: cnn.GuessNet | None, seeds, tol: float = 1e-10, device="cuda:0", reps: int = 3):
+    """Solve the batch with (a) FP64 cycles from the zero guess and (b) FP32 defect
+    correction from the learned guess (and from the zero guess); returns cycles and times."""
+    out = {}
+    s64, f, g, probs = build_batch(seeds, device=device)
+    sdc, _, _, _ = build_batch([p.seed for p in probs], device=device, precision=gm.MG_FP32_DC)
+    B = len(probs)
+    u = torch.zeros_like(f)
+
+    def timed(fn):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return info, best
+
+    def zero64():
+        u.zero_()
+        return s64.solve(f, g, u, tol=tol)
+
+    info, dt = timed(zero64)
+    ref = u.clone()
+    out["fp64_zero"] = dict(cycles=info["cycles"], ms=1e3 * dt, rel=info["rel"])
+
+    def zerodc():
+        u.zero_()
+        return sdc.solve(f, g, u, tol=tol)
+
+    info, dt = timed(zerodc)
+    out["fp32dc_zero"] = dict(cycles=info["cycles"], outer=info["outer"], ms=1e3 * dt,
+                              rel=info["rel"])
+    if net is not None:
+        def learned():
+            cnn.guess(net, sdc, LEVEL, f, g, u)
+            return sdc.solve(f, g, u, tol=tol)
+
+        info, dt = timed(learned)
+        out["fp32dc_learned"] = dict(cycles=info["cycles"], outer=info["outer"], ms=1e3 * dt,
+                                     rel=info["rel"],
+                                     diff_vs_fp64=(u - ref).abs().max().item() / ref.abs().max().item())
+        # error of the initial guess itself (relative, on the unknowns)
+        u0 = torch.zeros_like(u)
+        cnn.guess(net, sdc, LEVEL, f, g, u0)
+        out["guess_rel_error"] = ((u0 - ref).abs().max() / ref.abs().max()).item()
+
+        def learned64():
+            cnn.guess(net, s64, LEVEL, f, g, u)
+            return s64.solve(f, g, u, tol=tol)
+
+        info, dt = timed(learned64)
+        out["fp64_learned"] = dict(cycles=info["cycles"], ms=1e3 * dt, rel=info["rel"])
+    unknowns = int(sum((s64.classes(i) > 0).sum() for i in range(B)))
+    out["problems"] = B
+    out["unknowns"] = unknowns
+    s64.close()
+    sdc.close()
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import os
+
+    ap = argparse.ArgumentParser(description="train and evaluate the learned initial guess")
+    ap.add_argument("--samples", type=int, default=20000)
+    ap.add_argument("--val", type=int, default=512)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--eval", type=int, default=64)
+    ap.add_argument("--out", default="gpurun_out/learned")
+    ap.add_argument("--weights", default=None, help="skip training, load these weights")
+    args = ap.parse_args(argv)
+    os.makedirs(args.out, exist_ok=True)
+    net = cnn.GuessNet(seed=0)
+    res = {}
+    if args.weights:
+        net.load(dict(np.load(args.weights)))
+    else:
+        t0 = time.time()
+        data = generate(args.samples, seed0=0)
+        val = generate(args.val, seed0=20000)
+        res["generate_s"] = time.time() - t0
+        res["rejected"] = data["rejected"]
+        t0 = time.time()
+        res["train_hist"] = train(net, data, args.steps, batch=args.batch, lr=args.lr, val=val)
+        res["train_s"] = time.time() - t0
+        np.savez(os.path.join(args.out, "guessnet.npz"), **net.state())
+    seeds = []
+    s = 1_000_000
+    from workloads import ellipses as el
+    while len(seeds) < args.eval:
+        p = el.draw(s)
+        if el.accept(el.nodal_phi(p, N_FINE, device="cuda:0"), N_FINE, 3.0 * 2.0 / N_COARSE):
+            seeds.append(s)
+        s += 1
+    res["eval"] = evaluate(net, seeds)
+    print(json.dumps(res["eval"]))
+    with open(os.path.join(args.out, "learned.json"), "w") as f:
+        json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

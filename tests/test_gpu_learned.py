@@ -1,0 +1,26 @@
+"""The learned initial guess end to end on a small budget: solver-generated training data,
+training with the BF16 MFMA kernels, and solves from the learned guess that still reach the
+tolerance and agree with the zero-guess FP64 solution."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def test_learned_guess_pipeline():
+    from paper_1111_0983_amd import cnn, learned
+    data = learned.generate(192, seed0=0, log=None)
+    assert data["x"].shape[0] == 192
+    net = cnn.GuessNet(seed=0)
+    val = learned.generate(64, seed0=50000, log=None)
+    before = learned.validate(net, val)
+    learned.train(net, data, 150, batch=32, lr=3e-3, log=None)
+    after = learned.validate(net, val)
+    assert after < 0.5 * before, (before, after)
+    seeds = [1_000_000 + i for i in range(40)]
+    res = learned.evaluate(net, seeds, reps=1)
+    assert res["problems"] >= 4
+    assert res["fp32dc_learned"]["rel"] <= 1e-10 and res["fp64_zero"]["rel"] <= 1e-10
+    assert res["fp32dc_learned"]["diff_vs_fp64"] <= 1e-9
+    assert res["guess_rel_error"] < 1.0
