@@ -81,8 +81,11 @@ typedef struct {
   int outer;            /* defect-correction steps (DC mode), else 0 */
   double rel_residual;  /* final max over problems of ||r||_inf / ||(f_h, g_h)||_inf */
   double solve_ms;      /* wall time of the call on its stream */
-  const double* history;/* per cycle (or DC step) relative residual, max over problems;
-                           owned by the handle, valid until the next solve or mg_free */
+  const double* history;/* relative residual (max over problems) at each residual check:
+                           before the first cycle, after every cycle (or DC step) until a
+                           convergence factor is known, then after the batch of cycles the
+                           factor predicts are still needed minus one; owned by the handle,
+                           valid until the next solve or mg_free */
   int history_len;
 } mg_stats;
 

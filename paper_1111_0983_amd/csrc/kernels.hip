@@ -295,46 +295,47 @@ __global__ void __launch_bounds__(256) k_band_scatter(const int32_t* __restrict_
 // ---------------------------------------------------------------------------------------
 // defect (Sec. 2.4 step 3) with per-problem infinity norms
 // ---------------------------------------------------------------------------------------
+// One launch: workgroups [0, nbt) take the active tiles (interior rows), the rest take the
+// ghost records (boundary rows).  Per-problem maxima of |r| go to norms[2p] (interior) and
+// norms[2p + 1] (ghosts) through order-independent integer maxima, so the result is
+// deterministic.
 template <int D, typename T, typename TO>
-__global__ void __launch_bounds__(256) k_defect_tile(const int4* __restrict__ tiles, int ntiles, Geo g,
-                                                     const int8_t* __restrict__ cls,
-                                                     const T* __restrict__ u, const T* __restrict__ rhs,
-                                                     TO* __restrict__ r, T inv_h2,
-                                                     uint64_t* __restrict__ norms) {
+__global__ void __launch_bounds__(256) k_defect(const int4* __restrict__ tiles, int ntiles, int nbt,
+                                                const GhostRec* __restrict__ gs, int ng, Geo g,
+                                                const int8_t* __restrict__ cls,
+                                                const T* __restrict__ u, const T* __restrict__ rhs,
+                                                TO* __restrict__ r, T inv_h2, double inv_h,
+                                                uint64_t* __restrict__ norms) {
   constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
   __shared__ double red[4];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile >= ntiles) return;
-  const int4 t = tiles[tile];
-  const int64_t base = (int64_t)t.x * g.npp;
-  double m = 0.0;
-  for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
-    const int x = t.y * TX + i % TX, y = t.z * TY + (i / TX) % TY;
-    const int z = D == 3 ? t.w * TZ + i / (TX * TY) : 0;
-    if (!in_box(x, y, z, g.np, D)) continue;
-    const int64_t P = base + x + g.st[1] * y + g.st[2] * z;
-    if (cls[P] != 1) continue;
-    const T c = u[P];
-    T s = (u[P - 1] - c) + (u[P + 1] - c);
-    s += (u[P - g.st[1]] - c) + (u[P + g.st[1]] - c);
-    if (D == 3) s += (u[P - g.st[2]] - c) + (u[P + g.st[2]] - c);
-    const T v = rhs[P] + s * inv_h2;
-    r[P] = (TO)v;
-    m = fmax(m, fabs((double)v));
-    if (!(v == v)) m = __longlong_as_double(0x7ff0000000000000LL);
+  if ((int)blockIdx.x < nbt) {
+    const int tile = xcd_tile(blockIdx.x, nbt);
+    if (tile >= ntiles) return;
+    const int4 t = tiles[tile];
+    const int64_t base = (int64_t)t.x * g.npp;
+    double m = 0.0;
+    for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
+      const int x = t.y * TX + i % TX, y = t.z * TY + (i / TX) % TY;
+      const int z = D == 3 ? t.w * TZ + i / (TX * TY) : 0;
+      if (!in_box(x, y, z, g.np, D)) continue;
+      const int64_t P = base + x + g.st[1] * y + g.st[2] * z;
+      if (cls[P] != 1) continue;
+      const T c = u[P];
+      T s = (u[P - 1] - c) + (u[P + 1] - c);
+      s += (u[P - g.st[1]] - c) + (u[P + g.st[1]] - c);
+      if (D == 3) s += (u[P - g.st[2]] - c) + (u[P + g.st[2]] - c);
+      const T v = rhs[P] + s * inv_h2;
+      r[P] = (TO)v;
+      m = fmax(m, fabs((double)v));
+      if (!(v == v)) m = __longlong_as_double(0x7ff0000000000000LL);
+    }
+    if (norms) {
+      m = block_max(m, red);
+      if (threadIdx.x == 0) atomic_max_pos(&norms[2 * t.x], m);
+    }
+    return;
   }
-  if (norms) {
-    m = block_max(m, red);
-    if (threadIdx.x == 0) atomic_max_pos(&norms[2 * t.x], m);
-  }
-}
-
-template <int D, typename T, typename TO>
-__global__ void __launch_bounds__(256) k_defect_ghost(const GhostRec* __restrict__ gs, int ng, Geo g,
-                                                      const T* __restrict__ u, const T* __restrict__ rhs,
-                                                      TO* __restrict__ r, double inv_h,
-                                                      uint64_t* __restrict__ norms) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int i = ((int)blockIdx.x - nbt) * 256 + threadIdx.x;
   if (i >= ng) return;
   const GhostRec rec = gs[i];
   const double v = (double)rhs[rec.node] - ghost_apply<D, T>(rec, g, u, inv_h);
@@ -734,12 +735,12 @@ void launch_band_chunks(const DevLevel& L, const mg_grid& G, T* u, const T* rhs,
 template <int D, typename T, typename TO>
 void launch_defect(const DevLevel& L, const T* u, const T* rhs, TO* r, uint64_t* norms,
                    hipStream_t s) {
-  if (L.ntiles)
-    hipLaunchKernelGGL((k_defect_tile<D, T, TO>), dim3(tile_grid(L.ntiles)), dim3(256), 0, s,
-                       L.tiles, L.ntiles, L.g, L.cls, u, rhs, r, (T)(1.0 / (L.g.h * L.g.h)), norms);
-  if (L.nghost)
-    hipLaunchKernelGGL((k_defect_ghost<D, T, TO>), dim3(lin_grid(L.nghost)), dim3(256), 0, s,
-                       L.ghosts, L.nghost, L.g, u, rhs, r, 1.0 / L.g.h, norms);
+  const int nbt = L.ntiles ? tile_grid(L.ntiles) : 0;
+  const int nb = nbt + (L.nghost ? lin_grid(L.nghost) : 0);
+  if (!nb) return;
+  hipLaunchKernelGGL((k_defect<D, T, TO>), dim3(nb), dim3(256), 0, s, L.tiles, L.ntiles, nbt,
+                     L.ghosts, L.nghost, L.g, L.cls, u, rhs, r, (T)(1.0 / (L.g.h * L.g.h)),
+                     1.0 / L.g.h, norms);
 }
 
 template <int D>

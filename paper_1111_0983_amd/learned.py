@@ -80,12 +80,11 @@ def build_batch(seeds, n=N_FINE, nc=N_COARSE, device="cuda:0", precision=gm.MG_F
         except gm.GhostMGError as e:
             if e.code != gm.MG_EGEOM:
                 raise
-            # find the offending problems one by one on their coarsest grid
+            # find the offending problems one by one
             keep = []
             for i, (p, phi) in enumerate(zip(probs, phis)):
-                ph = phi.reshape(n + 1, n + 1)[:: n // nc, :: n // nc].contiguous().reshape(-1)
                 try:
-                    gm.Solver(ph, [p.rule], gm.mg_grid_default(2, nc, nc // 2)).close()
+                    gm.Solver(phi, [p.rule], gm.mg_grid_default(2, n, nc)).close()
                     keep.append(i)
                 except gm.GhostMGError:
                     pass
@@ -137,7 +136,8 @@ def generate(n_samples: int, seed0: int = 0, batch: int = 64, device="cuda:0", l
         if solver is None:
             continue
         u = torch.zeros_like(f)
-        info = solver.solve(f, g, u, tol=1e-10)
+        # training targets: 1e-8 is far below what the network can reproduce
+        info = solver.solve(f, g, u, tol=1e-8)
         x, scale, (B, H, W) = cnn.features(solver, LEVEL, f, g)
         tgt, mask = cnn.target(solver, LEVEL, u, scale)
         xs.append(x.reshape(B, H * W * 8))
@@ -200,7 +200,8 @@ def evaluate(net: cnn.GuessNet | None, seeds, tol: float = 1e-10, device="cuda:0
     correction from the learned guess (and from the zero guess); returns cycles and times."""
     out = {}
     s64, f, g, probs = build_batch(seeds, device=device)
-    sdc, _, _, _ = build_batch([p.seed for p in probs], device=device, precision=gm.MG_FP32_DC)
+    sdc, _, _, _ = build_batch([p.seed for p in probs], device=device, precision=gm.MG_FP32_DC,
+                               screen=False)
     B = len(probs)
     u = torch.zeros_like(f)
 
