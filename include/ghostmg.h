@@ -132,11 +132,15 @@ int mg_cycles(mg_handle_t h, const double* f, const double* g, double* u, int nc
 int mg_residual(mg_handle_t h, const double* f, const double* g, const double* u, double* r,
                 double* norms);
 
-/* Time one kernel of the cycle at one level on the handle's stream with HIP events,
- * launched reps times after one warm-up; kernel 0 = red-black interior relaxation,
- * 1 = defect, 2 = restriction, 3 = interpolation + correction, 4 = boundary band sweeps.
- * avg_ms: mean duration; bytes: the kernel's algorithmic HBM bytes per launch (every
- * array element it must read or write once). */
+/* Time one launch of the cycle at one level on the handle's stream with HIP events, run
+ * reps times after one warm-up; kernel 0 = one relaxation (red-black interior sweep with the
+ * ghost relaxation and the lambda boundary sweeps of Sec. 3.2; one launch on levels with
+ * relaxation chunks), 1 = defect with its extension, Eq. (exp), 2 = restriction,
+ * 3 = interpolation + correction, 4 = defect with its norms (the stopping test).  The level's
+ * iterate, defect and coarse arrays are overwritten.  avg_ms: mean duration; bytes: the
+ * algorithmic HBM bytes per launch (every array element it must read or write once: per
+ * unknown the iterate read and written, the right-hand side and the node code; per ghost
+ * its row weights; per extension node its value and weights). */
 int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_ms,
                    double* bytes);
 

@@ -43,13 +43,13 @@ int max_span(const std::vector<int32_t>& off) {
   return m;
 }
 
-// Per-problem band + ghost work that one workgroup handles within its barriers; larger
-// boundary bands (3D) are swept by one launch per phase instead.
-constexpr int kSingleWgBand = 24576;
-constexpr int kSingleWgExt = 24576;
 constexpr int kMaxCoarse = 8192;
-constexpr int kChunkOwn = 512;   // owned band nodes per LDS chunk
-constexpr int kChunkLds = 64 * 1024;  // LDS bytes per chunk
+// relaxation chunks: owned band and ghost nodes per chunk, and the redundant work (chunk
+// entries per owned node) above which a level relaxes its boundary with one launch per
+// phase instead; owned extension nodes per extension chunk
+constexpr int kChunkOwn = 320;
+constexpr double kChunkRedundancy = 4.0;
+constexpr int kExtChunkOwn = 512;
 
 int upload_level(mg_handle_s* H, int l) {
   const HostLevel& S = H->host[l];
@@ -82,53 +82,35 @@ int upload_level(mg_handle_s* H, int l) {
   if ((rc = upload(&L.dag_off, S.dag_off))) return rc;
   if ((rc = upload(&L.dag_start, S.dag_start))) return rc;
   if ((rc = upload(&L.rcode, S.rcode))) return rc;
+  if ((rc = upload(&L.rcls, S.rcls))) return rc;
+  if ((rc = upload(&L.gw, S.gw))) return rc;
   const bool need64 = !dc || l == 0;
   if (need64) {
-    if ((rc = alloc_zero(&L.u64, nn))) return rc;
+    for (int k = 0; k < 2; ++k)
+      if ((rc = alloc_zero(&L.u64[k], nn))) return rc;
     if ((rc = alloc_zero(&L.rhs64, nn))) return rc;
     if ((rc = alloc_zero(&L.r64, nn))) return rc;
     if ((rc = alloc_zero(&L.gtmp64, (size_t)L.nghost + 1))) return rc;
   }
   if (dc) {
-    if ((rc = alloc_zero(&L.u32, nn))) return rc;
+    for (int k = 0; k < 2; ++k)
+      if ((rc = alloc_zero(&L.u32[k], nn))) return rc;
     if ((rc = alloc_zero(&L.rhs32, nn))) return rc;
     if ((rc = alloc_zero(&L.r32, nn))) return rc;
     if ((rc = alloc_zero(&L.gtmp32, (size_t)L.nghost + 1))) return rc;
   }
-  if (!S.bc_off.empty() && S.bc_off.size() > 1) {
-    L.nchunks = (int)S.bc_own.size();
+  if (S.bc_nchunks) {
+    L.nchunks = S.bc_nchunks;
     L.bc_smax = S.bc_smax;
-    L.bc_gmax = S.bc_gmax;
-    L.bc_opsmax = S.bc_opsmax;
-    L.bc_nown = (int)S.bc_own_node.size();
-    L.bc_phases = 1 + 3 * H->grid.lambda;
-    if ((rc = upload(&L.bc_off, S.bc_off))) return rc;
-    if ((rc = upload(&L.bc_own, S.bc_own))) return rc;
-    if ((rc = upload(&L.bc_out_off, S.bc_out_off))) return rc;
-    if ((rc = upload(&L.bc_node, S.bc_node))) return rc;
-    if ((rc = upload(&L.bc_nbr, S.bc_nbr))) return rc;
-    if ((rc = upload(&L.bc_goff, S.bc_goff))) return rc;
-    if ((rc = upload(&L.bc_gent, S.bc_gent))) return rc;
-    if ((rc = upload(&L.bc_gidx, S.bc_gidx))) return rc;
-    if ((rc = upload(&L.bc_gsten, S.bc_gsten))) return rc;
-    if ((rc = upload(&L.bc_ops, S.bc_ops))) return rc;
-    if ((rc = upload(&L.bc_ops_off, S.bc_ops_off))) return rc;
-    if ((rc = upload(&L.bc_own_node, S.bc_own_node))) return rc;
-    if (need64 && (rc = alloc_zero(&L.bc_out64, (size_t)L.bc_nown + 1))) return rc;
-    if (dc && (rc = alloc_zero(&L.bc_out32, (size_t)L.bc_nown + 1))) return rc;
+    L.bc_phases = 3 + 3 * H->grid.lambda;
+    if ((rc = upload(&L.bc_hdr, S.bc_hdr))) return rc;
+    if ((rc = upload(&L.bc_data, S.bc_data))) return rc;
   }
-  if (S.ec_off.size() > 1) {
-    L.nechunks = (int)S.ec_own.size();
+  if (S.ec_nchunks) {
+    L.nechunks = S.ec_nchunks;
     L.ec_smax = S.ec_smax;
-    if ((rc = upload(&L.ec_off, S.ec_off))) return rc;
-    if ((rc = upload(&L.ec_own, S.ec_own))) return rc;
-    if ((rc = upload(&L.ec_next, S.ec_next))) return rc;
-    if ((rc = upload(&L.ec_node, S.ec_node))) return rc;
-    if ((rc = upload(&L.ec_src, S.ec_src))) return rc;
-    if ((rc = upload(&L.ec_wt, S.ec_wt))) return rc;
-    if ((rc = upload(&L.ec_ops, S.ec_ops))) return rc;
-    if ((rc = upload(&L.ec_lvl, S.ec_lvl))) return rc;
-    if ((rc = upload(&L.ec_lvl_start, S.ec_lvl_start))) return rc;
+    if ((rc = upload(&L.ec_hdr, S.ec_hdr))) return rc;
+    if ((rc = upload(&L.ec_data, S.ec_data))) return rc;
   }
   if (l == H->L) {
     L.nu_max = max_span(S.umap_off);
@@ -144,66 +126,54 @@ template <typename T>
 struct Arr;
 template <>
 struct Arr<double> {
-  static double* bout(DevLevel& L) { return L.bc_out64; }
-  static double* u(DevLevel& L) { return L.u64; }
+  static double* u(DevLevel& L, int k) { return L.u64[k]; }
   static double* rhs(DevLevel& L) { return L.rhs64; }
   static double* r(DevLevel& L) { return L.r64; }
   static double* tmp(DevLevel& L) { return L.gtmp64; }
 };
 template <>
 struct Arr<float> {
-  static float* bout(DevLevel& L) { return L.bc_out32; }
-  static float* u(DevLevel& L) { return L.u32; }
+  static float* u(DevLevel& L, int k) { return L.u32[k]; }
   static float* rhs(DevLevel& L) { return L.rhs32; }
   static float* r(DevLevel& L) { return L.r32; }
   static float* tmp(DevLevel& L) { return L.gtmp32; }
 };
 
-// Ghost relaxation and the lambda band sweeps: LDS chunks where the level has them, else
-// one launch per phase.
-template <int D, typename T>
-void band(mg_handle_s* H, int l, hipStream_t s) {
-  DevLevel& L = H->dev[l];
-  if (L.nchunks)
-    launch_band_chunks<D, T>(L, H->grid, Arr<T>::u(L), Arr<T>::rhs(L), Arr<T>::bout(L), s);
-  else
-    launch_band<D, T>(L, H->grid, Arr<T>::u(L), Arr<T>::rhs(L), Arr<T>::tmp(L), false, H->batch, s);
-}
-
-// One relaxation: red-black interior sweep, then ghost relaxation and lambda band sweeps.
+// One relaxation of level l from its current iterate buffer into the other one.
 template <int D, typename T>
 void relax(mg_handle_s* H, int l, hipStream_t s) {
   DevLevel& L = H->dev[l];
-  launch_smooth<D, T>(L, Arr<T>::u(L), Arr<T>::rhs(L), s);
-  band<D, T>(H, l, s);
+  const int c = H->cur[l];
+  launch_relax<D, T>(L, H->grid, Arr<T>::u(L, c), Arr<T>::u(L, 1 - c), Arr<T>::rhs(L),
+                     Arr<T>::tmp(L), H->batch, s);
+  H->cur[l] = 1 - c;
 }
 
-// The cycle of Sec. 2.4 from level l (TGCS recursion, gamma = 1 V, 2 W).
+// The cycle of Sec. 2.4 from level l (TGCS recursion, gamma = 1 V, 2 W).  H->cur tracks,
+// while the launches are recorded, which buffer holds each level's iterate.
 template <int D, typename T>
 void cycle(mg_handle_s* H, int l, hipStream_t s) {
   DevLevel& L = H->dev[l];
   if (l == H->L) {
-    launch_coarse<T>(L, Arr<T>::rhs(L), Arr<T>::u(L), H->batch, s);
+    launch_coarse<T>(L, Arr<T>::rhs(L), Arr<T>::u(L, H->cur[l]), H->batch, s);
     return;
   }
   for (int i = 0; i < H->grid.nu1; ++i) relax<D, T>(H, l, s);
-  launch_defect<D, T, T>(L, Arr<T>::u(L), Arr<T>::rhs(L), Arr<T>::r(L), nullptr, s);
-  if (L.nechunks)
-    launch_extend_chunks<T>(L, Arr<T>::r(L), s);
-  else
-    launch_extend<T>(L, Arr<T>::r(L), L.max_extp <= kSingleWgExt, H->batch, s);
+  launch_defect<D, T, T>(L, Arr<T>::u(L, H->cur[l]), Arr<T>::rhs(L), Arr<T>::r(L), nullptr, true,
+                         H->batch, s);
   DevLevel& C = H->dev[l + 1];
-  launch_restrict<D, T>(L, C, Arr<T>::r(L), Arr<T>::rhs(C), Arr<T>::u(C), s);
+  H->cur[l + 1] = 0;
+  launch_restrict<D, T>(L, C, Arr<T>::r(L), Arr<T>::rhs(C), Arr<T>::u(C, 0), s);
   for (int k = 0; k < H->grid.gamma; ++k) cycle<D, T>(H, l + 1, s);
-  launch_prolong<D, T>(L, C, Arr<T>::u(C), Arr<T>::u(L), s);
+  launch_prolong<D, T>(L, C, Arr<T>::u(C, H->cur[l + 1]), Arr<T>::u(L, H->cur[l]), s);
   for (int i = 0; i < H->grid.nu2; ++i) relax<D, T>(H, l, s);
 }
 
 template <int D>
-void defect_norm64(mg_handle_s* H, hipStream_t s) {
+void defect_norm64(mg_handle_s* H, int c, hipStream_t s) {
   DevLevel& L = H->dev[0];
   launch_fill<uint64_t>(H->norms, 2 * H->batch, 0, s);
-  launch_defect<D, double, double>(L, L.u64, L.rhs64, L.r64, H->norms, s);
+  launch_defect<D, double, double>(L, L.u64[c], L.rhs64, L.r64, H->norms, false, H->batch, s);
 }
 
 // FP64 defect of u64 written as the FP32 right-hand side of the correction problem
@@ -211,38 +181,48 @@ template <int D>
 void dc_defect(mg_handle_s* H, hipStream_t s) {
   DevLevel& L = H->dev[0];
   launch_fill<uint64_t>(H->norms, 2 * H->batch, 0, s);
-  launch_defect<D, double, float>(L, L.u64, L.rhs64, L.rhs32, H->norms, s);
+  launch_defect<D, double, float>(L, L.u64[0], L.rhs64, L.rhs32, H->norms, false, H->batch, s);
 }
 
+// one FP64 cycle from finest buffer c, then the defect norm of its result
 template <int D>
-void record_cycle(mg_handle_s* H, hipStream_t s) {
+void record_cycle(mg_handle_s* H, int c, hipStream_t s) {
+  H->cur[0] = c;
   cycle<D, double>(H, 0, s);
-  defect_norm64<D>(H, s);
+  defect_norm64<D>(H, H->cur[0], s);
 }
 
+// inner_cycles FP32 cycles on the correction (from zero in FP32 buffer 0), u64 += the
+// correction, FP32 buffer 0 cleared for the next step, then the new FP64 defect
 template <int D>
 void record_dc(mg_handle_s* H, hipStream_t s) {
+  H->cur[0] = 0;
   for (int k = 0; k < H->grid.inner_cycles; ++k) cycle<D, float>(H, 0, s);
-  launch_dc_update<D>(H->dev[0], H->dev[0].u64, H->dev[0].u32, s);
+  DevLevel& L = H->dev[0];
+  launch_dc_update<D>(L, L.u64[0], L.u32[H->cur[0]], L.u32[0], s);
   dc_defect<D>(H, s);
 }
 
 hipStream_t stream_of(mg_handle_s* H) { return H->stream; }
 
-int capture(mg_handle_s* H, bool dc, hipGraphExec_t* out) {
+// Record one cycle (FP64 from finest buffer c, or one defect-correction step) into a graph.
+int capture(mg_handle_s* H, bool dc, int c, hipGraphExec_t* out) {
   if (*out) return MG_OK;
   hipStream_t s = stream_of(H);
   hipGraph_t graph;
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   if (H->dim == 2)
-    dc ? record_dc<2>(H, s) : record_cycle<2>(H, s);
+    dc ? record_dc<2>(H, s) : record_cycle<2>(H, c, s);
   else
-    dc ? record_dc<3>(H, s) : record_cycle<3>(H, s);
+    dc ? record_dc<3>(H, s) : record_cycle<3>(H, c, s);
   if (hipStreamEndCapture(s, &graph) != hipSuccess) return MG_EHIP;
   const hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
   hipGraphDestroy(graph);
   return e == hipSuccess ? MG_OK : MG_EHIP;
 }
+
+// finest FP64 buffer after one FP64 cycle that starts in buffer c
+int after_cycle(const mg_handle_s* H, int c) { return (c + H->grid.nu1 + H->grid.nu2) & 1; }
 
 // Read the per-problem norms; returns the max over problems of max(interior, ghost) / r0.
 int read_rel(mg_handle_s* H, double* rel) {
@@ -271,8 +251,9 @@ template <int D>
 int pack(mg_handle_s* H, const double* f, const double* g, const double* u) {
   hipStream_t s = stream_of(H);
   DevLevel& L = H->dev[0];
-  launch_pack<D>(L, f, g, u, L.rhs64, L.u64, s);
-  if (H->grid.precision == MG_FP32_DC) launch_fill<float>(L.u32, (int64_t)H->batch * L.g.npp, 0.f, s);
+  launch_pack<D>(L, f, g, u, L.rhs64, L.u64[0], s);
+  H->cur0 = 0;
+  if (H->grid.precision == MG_FP32_DC) launch_fill<float>(L.u32[0], (int64_t)H->batch * L.g.npp, 0.f, s);
   // r0 = ||(f_h, g_h)||_inf per problem
   launch_fill<uint64_t>(H->norms, 2 * H->batch, 0, s);
   launch_rhs_norm<D>(L, L.rhs64, H->norms, s);
@@ -296,13 +277,17 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
   auto t0 = std::chrono::steady_clock::now();
   rc = H->dim == 2 ? pack<2>(H, f, g, u) : pack<3>(H, f, g, u);
   if (rc) return rc;
-  if ((rc = capture(H, dc, dc ? &H->graph_dc : &H->graph_cycle))) return rc;
-  hipGraphExec_t exec = dc ? H->graph_dc : H->graph_cycle;
+  if (dc) {
+    if ((rc = capture(H, true, 0, &H->graph_dc))) return rc;
+  } else {
+    if ((rc = capture(H, false, 0, &H->graph_cycle[0]))) return rc;
+    if (after_cycle(H, 0) == 1 && (rc = capture(H, false, 1, &H->graph_cycle[1]))) return rc;
+  }
   // defect of the initial guess
   if (H->dim == 2)
-    dc ? dc_defect<2>(H, s) : defect_norm64<2>(H, s);
+    dc ? dc_defect<2>(H, s) : defect_norm64<2>(H, 0, s);
   else
-    dc ? dc_defect<3>(H, s) : defect_norm64<3>(H, s);
+    dc ? dc_defect<3>(H, s) : defect_norm64<3>(H, 0, s);
   double rel;
   if ((rc = read_rel(H, &rel))) return rc;
   H->history.clear();
@@ -337,7 +322,14 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
       }
       k = std::min(k, std::max(1, (H->grid.max_cycles - cycles) / per));
     }
-    for (int i = 0; i < k; ++i) HIP_TRY(hipGraphLaunch(exec, s));
+    for (int i = 0; i < k; ++i) {
+      if (dc) {
+        HIP_TRY(hipGraphLaunch(H->graph_dc, s));
+      } else {
+        HIP_TRY(hipGraphLaunch(H->graph_cycle[H->cur0], s));
+        H->cur0 = after_cycle(H, H->cur0);
+      }
+    }
     cycles += per * k;
     steps += k;
     if ((rc = read_rel(H, &rel))) return rc;
@@ -346,9 +338,9 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
     prev = rel;
   }
   if (H->dim == 2)
-    launch_unpack<2>(H->dev[0], H->batch, H->dev[0].u64, u, s);
+    launch_unpack<2>(H->dev[0], H->batch, H->dev[0].u64[dc ? 0 : H->cur0], u, s);
   else
-    launch_unpack<3>(H->dev[0], H->batch, H->dev[0].u64, u, s);
+    launch_unpack<3>(H->dev[0], H->batch, H->dev[0].u64[dc ? 0 : H->cur0], u, s);
   HIP_TRY(hipStreamSynchronize(s));
   if (hipGetLastError() != hipSuccess) return MG_EHIP;
   auto t1 = std::chrono::steady_clock::now();
@@ -365,18 +357,41 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
 }
 
 void free_level(DevLevel& L) {
-  void* ptrs[] = {L.bc_off, L.bc_own, L.bc_out_off, L.bc_node, L.bc_nbr, L.bc_goff, L.bc_gent,
-                  L.bc_gidx, L.bc_gsten,
-                  L.bc_ops, L.bc_ops_off, L.bc_own_node, L.bc_out64, L.bc_out32,
-                  L.ec_off, L.ec_own, L.ec_next, L.ec_node, L.ec_src, L.ec_wt, L.ec_ops,
-                  L.ec_lvl, L.ec_lvl_start,
+  void* ptrs[] = {L.bc_hdr, L.bc_data, L.ec_hdr, L.ec_data, L.rcls, L.gw,
                   L.cls, L.phi, L.tiles, L.ghosts, L.ghost_off, L.red, L.black, L.red_off, L.black_off,
-                  L.ext, L.ext_merged, L.ext_off, L.dag_off, L.dag_start, L.rcode, L.u64, L.rhs64,
-                  L.r64, L.gtmp64, L.u32, L.rhs32, L.r32, L.gtmp32, L.umap, L.umap_off,
-                  L.ainv_off, L.ainv};
+                  L.ext, L.ext_merged, L.ext_off, L.dag_off, L.dag_start, L.rcode, L.u64[0],
+                  L.u64[1], L.rhs64, L.r64, L.gtmp64, L.u32[0], L.u32[1], L.rhs32, L.r32, L.gtmp32,
+                  L.umap, L.umap_off, L.ainv_off, L.ainv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   L = DevLevel();
+}
+
+template <int D, typename T>
+void time_launch(mg_handle_s* h, int kernel, int level, int i, hipStream_t s) {
+  DevLevel& L = h->dev[level];
+  T* u = Arr<T>::u(L, i & 1);
+  switch (kernel) {
+    case 0:
+      launch_relax<D, T>(L, h->grid, u, Arr<T>::u(L, 1 - (i & 1)), Arr<T>::rhs(L), Arr<T>::tmp(L),
+                         h->batch, s);
+      break;
+    case 1:
+      launch_defect<D, T, T>(L, u, Arr<T>::rhs(L), Arr<T>::r(L), nullptr, true, h->batch, s);
+      break;
+    case 2: {
+      DevLevel& C = h->dev[level + 1];
+      launch_restrict<D, T>(L, C, Arr<T>::r(L), Arr<T>::rhs(C), Arr<T>::u(C, 0), s);
+      break;
+    }
+    case 3: {
+      DevLevel& C = h->dev[level + 1];
+      launch_prolong<D, T>(L, C, Arr<T>::u(C, 0), u, s);
+      break;
+    }
+    default:
+      launch_defect<D, T, T>(L, u, Arr<T>::rhs(L), Arr<T>::r(L), h->norms, false, h->batch, s);
+  }
 }
 
 }  // namespace
@@ -451,19 +466,22 @@ int mg_setup(const double* phi, const mg_bc_rule* bc, const mg_grid* grid, mg_ha
     std::memcpy(phi_h.data(), phi, phi_h.size() * sizeof(double));
   }
   int rc = build_hierarchy(H, phi_h.data());
-  // boundary-band chunks (levels that relax: all but the coarsest)
+  // relaxation and extension chunks (levels that relax: all but the coarsest); a level
+  // whose chunks cannot be built keeps the per-phase boundary launches
   if (!rc)
-    for (int l = 0; l < L; ++l)
-      if (!build_band_chunks(H, l, kChunkOwn, kChunkLds, 4.0)) {
-        H->host[l].bc_off.clear();
-        H->host[l].bc_own.clear();
+    for (int l = 0; l < L; ++l) {
+      HostLevel& S = H->host[l];
+      if (!build_band_chunks(H, l, kChunkOwn, kChunkRedundancy)) {
+        S.bc_nchunks = 0;
+        S.bc_hdr.clear();
+        S.bc_data.clear();
       }
-  if (!rc)
-    for (int l = 0; l < L; ++l)
-      if (!build_ext_chunks(H, l, kChunkOwn, 8192)) {
-        H->host[l].ec_off.assign(1, 0);
-        H->host[l].ec_own.clear();
+      if (!build_ext_chunks(H, l, kExtChunkOwn)) {
+        S.ec_nchunks = 0;
+        S.ec_hdr.clear();
+        S.ec_data.clear();
       }
+    }
   // the coarsest right-hand side of one problem is staged in 64 KB of LDS
   if (!rc && max_span(H->host[L].umap_off) > kMaxCoarse) rc = MG_EINVAL;
   if (!rc) {
@@ -569,9 +587,9 @@ int mg_residual(mg_handle_t h, const double* f, const double* g, const double* u
   DevLevel& L = h->dev[0];
   launch_fill<double>(L.r64, (int64_t)h->batch * L.g.npp, 0.0, s);
   if (h->dim == 2)
-    defect_norm64<2>(h, s);
+    defect_norm64<2>(h, 0, s);
   else
-    defect_norm64<3>(h, s);
+    defect_norm64<3>(h, 0, s);
   HIP_TRY(hipMemcpyAsync(h->norms_host, h->norms, 2 * h->batch * sizeof(uint64_t),
                          hipMemcpyDeviceToHost, s));
   if (r) {
@@ -594,64 +612,38 @@ int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_m
   const HostLevel& S = h->host[level];
   const bool dc = h->grid.precision == MG_FP32_DC;
   const double sz = dc ? 4.0 : 8.0;
-  auto run = [&]() {
-    if (h->dim == 2) {
-      if (dc) {
-        if (kernel == 0) launch_smooth<2, float>(L, L.u32, L.rhs32, s);
-        if (kernel == 1) launch_defect<2, float, float>(L, L.u32, L.rhs32, L.r32, nullptr, s);
-        if (kernel == 2) launch_restrict<2, float>(L, h->dev[level + 1], L.r32, h->dev[level + 1].rhs32, h->dev[level + 1].u32, s);
-        if (kernel == 3) launch_prolong<2, float>(L, h->dev[level + 1], h->dev[level + 1].u32, L.u32, s);
-        if (kernel == 4) band<2, float>(h, level, s);
-      } else {
-        if (kernel == 0) launch_smooth<2, double>(L, L.u64, L.rhs64, s);
-        if (kernel == 1) launch_defect<2, double, double>(L, L.u64, L.rhs64, L.r64, nullptr, s);
-        if (kernel == 2) launch_restrict<2, double>(L, h->dev[level + 1], L.r64, h->dev[level + 1].rhs64, h->dev[level + 1].u64, s);
-        if (kernel == 3) launch_prolong<2, double>(L, h->dev[level + 1], h->dev[level + 1].u64, L.u64, s);
-        if (kernel == 4) band<2, double>(h, level, s);
-      }
-    } else {
-      if (dc) {
-        if (kernel == 0) launch_smooth<3, float>(L, L.u32, L.rhs32, s);
-        if (kernel == 1) launch_defect<3, float, float>(L, L.u32, L.rhs32, L.r32, nullptr, s);
-        if (kernel == 2) launch_restrict<3, float>(L, h->dev[level + 1], L.r32, h->dev[level + 1].rhs32, h->dev[level + 1].u32, s);
-        if (kernel == 3) launch_prolong<3, float>(L, h->dev[level + 1], h->dev[level + 1].u32, L.u32, s);
-        if (kernel == 4) band<3, float>(h, level, s);
-      } else {
-        if (kernel == 0) launch_smooth<3, double>(L, L.u64, L.rhs64, s);
-        if (kernel == 1) launch_defect<3, double, double>(L, L.u64, L.rhs64, L.r64, nullptr, s);
-        if (kernel == 2) launch_restrict<3, double>(L, h->dev[level + 1], L.r64, h->dev[level + 1].rhs64, h->dev[level + 1].u64, s);
-        if (kernel == 3) launch_prolong<3, double>(L, h->dev[level + 1], h->dev[level + 1].u64, L.u64, s);
-        if (kernel == 4) band<3, double>(h, level, s);
-      }
-    }
+  if (dc ? !L.u32[0] : !L.u64[0]) return MG_EINVAL;
+  auto run = [&](int i) {
+    if (h->dim == 2)
+      dc ? time_launch<2, float>(h, kernel, level, i, s) : time_launch<2, double>(h, kernel, level, i, s);
+    else
+      dc ? time_launch<3, float>(h, kernel, level, i, s) : time_launch<3, double>(h, kernel, level, i, s);
   };
-  if (dc && level > 0 && !L.u32) return MG_EINVAL;
-  if (!dc && !L.u64) return MG_EINVAL;
-  run();
+  run(0);
   HIP_TRY(hipEventRecord(h->ev0, s));
-  for (int i = 0; i < reps; ++i) run();
+  for (int i = 1; i <= reps; ++i) run(i);
   HIP_TRY(hipEventRecord(h->ev1, s));
   HIP_TRY(hipEventSynchronize(h->ev1));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
   if (avg_ms) *avg_ms = ms / reps;
   if (bytes) {
-    // algorithmic bytes: each array element the kernel must touch, once
-    const double nint = (double)S.nint, ng = (double)S.nghost;
+    // algorithmic bytes: every array element the kernel must touch, once (iterate read and
+    // written, right-hand side and node code read per unknown; ghost row weights)
+    const double nu = (double)S.nint + (double)S.nghost, ng = (double)S.nghost;
+    const double K = h->dim == 2 ? 9.0 : 27.0;
     double b = 0.0;
-    if (kernel == 0) b = nint * (3.0 * sz + 1.0);
-    if (kernel == 1) b = nint * (3.0 * sz + 1.0) + ng * (2.0 * sz + sizeof(GhostRec));
+    if (kernel == 0) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0;
+    if (kernel == 1) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0 + (double)S.ext.size() * (sz + 24.0);
+    if (kernel == 4) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0;
     if (kernel == 2) {
       const HostLevel& C = h->host[level + 1];
-      b = (nint + ng + (double)S.ext.size()) * sz + (double)(C.nint + C.nghost) * (2.0 * sz + 1.0);
+      b = (nu + (double)S.ext.size()) * sz + (double)(C.nint + C.nghost) * (2.0 * sz + 1.0);
     }
     if (kernel == 3) {
       const HostLevel& C = h->host[level + 1];
-      b = (nint + ng) * (2.0 * sz + 1.0) + (double)(C.nint + C.nghost) * (sz + 1.0);
+      b = nu * (2.0 * sz + 1.0) + (double)(C.nint + C.nghost) * (sz + 1.0);
     }
-    if (kernel == 4)
-      b = h->grid.lambda * (double)S.nband * 3.0 * sz +
-          (h->grid.lambda + 1) * ng * (3.0 * sz + sizeof(GhostRec));
     *bytes = b;
   }
   return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
@@ -659,7 +651,8 @@ int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_m
 
 void mg_free(mg_handle_t h) {
   if (!h) return;
-  if (h->graph_cycle) (void)hipGraphExecDestroy(h->graph_cycle);
+  for (int k = 0; k < 2; ++k)
+    if (h->graph_cycle[k]) (void)hipGraphExecDestroy(h->graph_cycle[k]);
   if (h->graph_dc) (void)hipGraphExecDestroy(h->graph_dc);
   for (DevLevel& L : h->dev) free_level(L);
   if (h->norms) (void)hipFree(h->norms);

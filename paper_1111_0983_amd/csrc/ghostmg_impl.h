@@ -13,6 +13,12 @@
 namespace ghostmg {
 
 constexpr int kMaxLevels = 16;
+// header words of a relaxation chunk and of an extension chunk
+constexpr int kBandHdr = 8;
+constexpr int kExtHdr = 8;
+constexpr int kChunkThreads = 256;     // workgroup size of every chunk kernel
+constexpr int kChunkPerThread = 4;     // chunk entries owned by one thread
+constexpr int kChunkMaxEntries = kChunkPerThread * kChunkThreads;
 
 // Tile shapes of the node-parallel kernels: 64 x 16 nodes in 2D, 16 x 8 x 8 in 3D.
 template <int D>
@@ -62,34 +68,36 @@ struct HostLevel {
   std::vector<uint8_t> rcode;           // restriction code of every node of this level
   std::vector<int4> tiles;              // (problem, tx, ty, tz) of tiles holding unknowns
   int64_t nint = 0, nghost = 0, nband = 0;
-  // boundary band in LDS-resident chunks: each chunk owns band/ghost nodes and carries
-  // every node its owned results depend on through the 1 + 3 lambda relaxation phases
-  std::vector<int32_t> bc_off;          // chunks + 1: offsets into bc_node
-  std::vector<int32_t> bc_own;          // chunks: owned nodes (the first entries of the chunk)
-  std::vector<int32_t> bc_out_off;      // chunks + 1: offsets of the owned results
-  std::vector<int32_t> bc_node;         // node of every chunk entry
-  std::vector<int16_t> bc_nbr;          // 2D local neighbour ids per entry (-1 unused)
-  std::vector<int32_t> bc_goff;         // chunks + 1: offsets into the ghost slots
-  std::vector<int16_t> bc_gent;         // per ghost slot: its local entry id
-  std::vector<int32_t> bc_gidx;         // per ghost slot: ghost record index
-  std::vector<int16_t> bc_gsten;        // per ghost slot: 3^D local stencil ids (-1 unused)
-  std::vector<int16_t> bc_ops;          // per phase: local entry ids (interior phases) or
-                                        // ghost slots (ghost phases)
-  std::vector<int32_t> bc_ops_off;      // chunks * (phases + 1)
-  std::vector<int32_t> bc_own_node;     // owned nodes in output order
-  int bc_smax = 0, bc_gmax = 0, bc_opsmax = 0;  // largest chunk, ghost slots, op list
-  // defect extension in LDS-resident chunks: owned extension nodes, the extension nodes
-  // they depend on, then the ghost defects they read
-  std::vector<int32_t> ec_off;          // chunks + 1: offsets into ec_node
-  std::vector<int32_t> ec_own;          // chunks: owned entries (first)
-  std::vector<int32_t> ec_next;         // chunks: extension entries (owned + dependencies)
-  std::vector<int32_t> ec_node;         // node of every entry
-  std::vector<int16_t> ec_src;          // 3 local source ids per entry (-1 absent)
-  std::vector<double> ec_wt;            // 3 weights per entry
-  std::vector<int16_t> ec_ops;          // extension entries by DAG level
-  std::vector<int32_t> ec_lvl;          // DAG level boundaries into ec_ops, flattened
-  std::vector<int32_t> ec_lvl_start;    // chunks + 1: first boundary of each chunk
-  int ec_smax = 0;
+  // node codes of the relaxation: 0 outside, 1 interior off the band, 2 ghost, 3 interior
+  // band node (the boundary band of Sec. 3.2)
+  std::vector<int8_t> rcls;
+  std::vector<double> gw;               // Pow3<D> row weights per ghost (0 for unused taps)
+  // Relaxation chunks: each chunk owns band and ghost nodes and carries every node that
+  // their values after the whole relaxation depend on, through its 3 + 3 lambda phases
+  // (red interior, black interior, ghosts; lambda times red band, black band, ghosts).
+  // Entry e of a chunk belongs to thread e % kChunkThreads; the updated ghosts come first
+  // (at most one per thread).  Chunk c: header bc_hdr[c * kBandHdr ..] = {entries, updated
+  // ghosts, offsets into bc_data of: the per-entry arrays, the ghost stencil ids, the ghost
+  // weights and the ghost constants, 0, 0}.  Per-entry arrays (int32 words): node index;
+  // phase mask (bit p: updated in phase p; bit 31: owned, written to the output); D words of
+  // (minus, plus) int16 local neighbour ids per axis.  Per ghost (tap-major, ghost fastest):
+  // Pow3<D> local stencil ids (-1 for taps of zero weight) and FP64 weights; one FP64
+  // constant c_G.
+  std::vector<int32_t> bc_hdr;
+  std::vector<int32_t> bc_data;
+  int bc_nchunks = 0, bc_smax = 0, bc_nown = 0;
+  int64_t bc_entries = 0;               // sum of chunk sizes (redundant work included)
+  // Extension chunks: each chunk owns a run of extension nodes, carries the extension
+  // nodes they depend on and evaluates the ghost defects they read (ghost sources first, at
+  // most one per thread).  Chunk c: header ec_hdr[c * kExtHdr ..] = {entries, ghost sources,
+  // offsets into ec_data of: the per-entry arrays, the source id pairs, the source weights,
+  // the ghost stencil nodes, the ghost weights; DAG levels}.  Per entry: node index; DAG level
+  // (0 for ghost sources; bit 31: owned); 2 words of int16 local source ids (-1 absent);
+  // 3 FP64 source weights (source-major).  Per ghost source (tap-major): Pow3<D> stencil node
+  // indices and FP64 row weights.
+  std::vector<int32_t> ec_hdr;
+  std::vector<int32_t> ec_data;
+  int ec_nchunks = 0, ec_smax = 0;
   // coarsest level
   std::vector<int32_t> umap;            // unknown node indices, by problem
   std::vector<int32_t> umap_off;        // batch + 1
@@ -101,17 +109,12 @@ struct DevLevel {
   Geo g;
   int ntiles = 0, nghost = 0, nred = 0, nblack = 0, next = 0, ndag = 0;
   int max_gp = 0, max_bandp = 0, max_extp = 0;   // largest per-problem list sizes
-  int nchunks = 0, bc_smax = 0, bc_gmax = 0, bc_opsmax = 0, bc_nown = 0, bc_phases = 0;
-  int32_t *bc_off = nullptr, *bc_own = nullptr, *bc_out_off = nullptr, *bc_node = nullptr,
-          *bc_goff = nullptr, *bc_gidx = nullptr, *bc_ops_off = nullptr, *bc_own_node = nullptr;
-  int16_t *bc_nbr = nullptr, *bc_gent = nullptr, *bc_gsten = nullptr, *bc_ops = nullptr;
-  double* bc_out64 = nullptr;
-  float* bc_out32 = nullptr;
+  int nchunks = 0, bc_phases = 0, bc_smax = 0;
+  int32_t *bc_hdr = nullptr, *bc_data = nullptr;
   int nechunks = 0, ec_smax = 0;
-  int32_t *ec_off = nullptr, *ec_own = nullptr, *ec_next = nullptr, *ec_node = nullptr,
-          *ec_lvl = nullptr, *ec_lvl_start = nullptr;
-  int16_t *ec_src = nullptr, *ec_ops = nullptr;
-  double* ec_wt = nullptr;
+  int32_t *ec_hdr = nullptr, *ec_data = nullptr;
+  int8_t* rcls = nullptr;
+  double* gw = nullptr;
   int8_t* cls = nullptr;
   double* phi = nullptr;
   int4* tiles = nullptr;
@@ -122,9 +125,10 @@ struct DevLevel {
   int32_t *ext_off = nullptr, *dag_off = nullptr, *dag_start = nullptr;
   std::vector<int32_t> gdag_off;        // host copy for the per-DAG-level launches
   uint8_t* rcode = nullptr;
-  // arrays [batch * npp]
-  double *u64 = nullptr, *rhs64 = nullptr, *r64 = nullptr, *gtmp64 = nullptr;
-  float *u32 = nullptr, *rhs32 = nullptr, *r32 = nullptr, *gtmp32 = nullptr;
+  // arrays [batch * npp]; the iterate has two buffers, a relaxation reads one and writes
+  // the other
+  double *u64[2] = {nullptr, nullptr}, *rhs64 = nullptr, *r64 = nullptr, *gtmp64 = nullptr;
+  float *u32[2] = {nullptr, nullptr}, *rhs32 = nullptr, *r32 = nullptr, *gtmp32 = nullptr;
   // coarsest level
   int nu_max = 0;
   int32_t *umap = nullptr, *umap_off = nullptr;
@@ -148,9 +152,11 @@ struct mg_handle_s {
   double* norms_host = nullptr;       // pinned host mirror
   double* r0 = nullptr;               // per problem ||(f_h, g_h)||_inf (host)
   std::vector<double> history;
-  hipGraphExec_t graph_cycle = nullptr;  // one FP64 cycle + defect norm
+  // one FP64 cycle + defect norm, starting from finest iterate buffer 0 or 1 (a cycle
+  // with an odd number of finest relaxations ends in the other buffer)
+  hipGraphExec_t graph_cycle[2] = {nullptr, nullptr};
   hipGraphExec_t graph_dc = nullptr;     // one defect-correction step + defect norm
-  const double* graph_f = nullptr;       // arrays the graphs were captured with
-  bool band_single_wg = true;
+  int cur0 = 0;                          // buffer holding the finest FP64 iterate
+  int cur[ghostmg::kMaxLevels] = {};     // per level current buffer while recording
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };

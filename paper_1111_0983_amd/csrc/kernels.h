@@ -4,49 +4,72 @@
 
 namespace ghostmg {
 
-constexpr int kCoarseRows = 16;  // rows of the coarsest inverse per workgroup
+constexpr int kCoarseRows = 4;  // rows of the coarsest inverse per workgroup (one per wave)
 
+// Per-phase boundary relaxation (levels without relaxation chunks), in place on u.
 template <typename T>
 struct BandArgs {
   Geo g;
   const GhostRec* ghosts;
+  const double* gw;
   const int32_t *ghost_off, *red, *black, *red_off, *black_off;
   T* u;
   const T* rhs;
   T* tmp;
   T h2, inv2d;
-  double inv_h, cD, cNh;
+  double cD, cNh;
   int lambda;
 };
 
+// One relaxation from uin into uout: workgroups [0, nchunks) run the relaxation chunks,
+// the rest the interior tiles.
 template <typename T>
-struct BandChunkArgs {
-  const int32_t *off, *own, *out_off, *node, *goff, *gidx, *ops_off;
-  const int16_t *nbr, *gent, *gsten, *ops;
-  const GhostRec* ghosts;
-  T* u;
+struct RelaxArgs {
+  const int4* tiles;
+  int ntiles, nbt;
+  Geo g;
+  const int8_t* rcls;
+  const T* uin;
+  T* uout;
   const T* rhs;
-  T* out;
-  int smax, gmax, opsmax, phases;
   T h2, inv2d;
-  double inv_h, cD, cNh;
+  int write_all;  // tiles also write band interior and ghost nodes (levels without chunks)
+  int nchunks, phases;
+  const int32_t *hdr, *data;
 };
 
+// Defect r = rhs - A u: workgroups [0, nechunks) run the extension chunks (Eq. (exp)),
+// then nbt workgroups the interior tiles, then the ghost rows.
+template <typename T, typename TO>
+struct DefectArgs {
+  const int4* tiles;
+  int ntiles, nbt;
+  const GhostRec* ghosts;
+  const double* gw;
+  int nghost;
+  Geo g;
+  const int8_t* cls;
+  const T* u;
+  const T* rhs;
+  TO* r;
+  T inv_h2;
+  uint64_t* norms;
+  int nechunks;
+  const int32_t *hdr, *data;
+};
+
+// One complete relaxation (Sec. 2.4 step 1 with the boundary sweeps of Sec. 3.2): reads
+// uin, writes every unknown of uout (uin != uout).
 template <int D, typename T>
-void launch_band_chunks(const DevLevel& L, const mg_grid& G, T* u, const T* rhs, T* out,
-                        hipStream_t s);
-template <int D, typename T>
-void launch_smooth(const DevLevel& L, T* u, const T* rhs, hipStream_t s);
-template <int D, typename T>
-void launch_band(const DevLevel& L, const mg_grid& G, T* u, const T* rhs, T* tmp, bool single_wg,
-                 int batch, hipStream_t s);
+void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, const T* rhs,
+                  T* tmp, int batch, hipStream_t s);
+// Defect of u into r; with_ext also extends it outside Omega_h (Eq. (exp)).  norms, when
+// given, receives the per-problem infinity norms (no extension then).
 template <int D, typename T, typename TO>
 void launch_defect(const DevLevel& L, const T* u, const T* rhs, TO* r, uint64_t* norms,
-                   hipStream_t s);
+                   bool with_ext, int batch, hipStream_t s);
 template <int D>
 void launch_rhs_norm(const DevLevel& L, const double* rhs, uint64_t* norms, hipStream_t s);
-template <typename T>
-void launch_extend(const DevLevel& L, T* r, bool single_wg, int batch, hipStream_t s);
 template <int D, typename T>
 void launch_restrict(const DevLevel& F, const DevLevel& C, const T* rf, T* rhsc, T* uc,
                      hipStream_t s);
@@ -62,13 +85,16 @@ void launch_pack(const DevLevel& L, const double* f, const double* g, const doub
 template <int D>
 void launch_unpack(const DevLevel& L, int batch, const double* src, double* dst, hipStream_t s);
 template <int D>
-void launch_dc_update(const DevLevel& L, double* u64, float* u32, hipStream_t s);
+void launch_dc_update(const DevLevel& L, double* u64, const float* u32, float* u32_zero,
+                      hipStream_t s);
+
+// dynamic LDS bytes of launch_relax / launch_defect for a level
+template <int D, typename T>
+size_t relax_lds(const DevLevel& L);
+size_t defect_lds(const DevLevel& L);
 
 int build_hierarchy(mg_handle_s* H, const double* phi);
-bool build_band_chunks(mg_handle_s* H, int l, int own_target, int lds_budget,
-                       double max_redundancy);
-bool build_ext_chunks(mg_handle_s* H, int l, int own_target, int max_entries);
-template <typename T>
-void launch_extend_chunks(const DevLevel& L, T* r, hipStream_t s);
+bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redundancy);
+bool build_ext_chunks(mg_handle_s* H, int l, int own_target);
 
 }  // namespace ghostmg

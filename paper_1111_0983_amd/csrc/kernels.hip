@@ -6,6 +6,8 @@
 // Workgroups of a tile kernel are mapped so that each of the 8 XCDs takes a contiguous run
 // of tiles (the dispatcher deals workgroups to XCDs round-robin), which keeps the halo
 // rows a tile shares with its neighbours in one L2.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace ghostmg {
@@ -37,123 +39,282 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------------------
-// red-black relaxation of the interior rows, Eq. (jac2d), one tile per workgroup
+// the two node updates of a relaxation, shared by every path that applies them
 // ---------------------------------------------------------------------------------------
-// The tile and a ring of two nodes are staged in LDS.  Red nodes of tile + ring one are
-// relaxed first (they read only black, ghost or outside values, which this pass leaves
-// unchanged), then the black nodes of the tile (which read the fresh red values); every
-// workgroup writes back only its own tile.  The result is the global red sweep followed
-// by the global black sweep.  The update is written as a correction,
-// u_P += (h^2 f_P + sum_nb (u_nb - u_P)) / (2D).
+// interior node, Eq. (jac2d) as a correction: u_P + (h^2 f_P + sum_nb (u_nb - u_P)) / (2D);
+// nb holds the neighbour values in the order x-, x+, y-, y+ (, z-, z+)
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_smooth(const int4* __restrict__ tiles, int ntiles,
-                                                 Geo g, const int8_t* __restrict__ cls,
-                                                 T* __restrict__ u, const T* __restrict__ rhs,
-                                                 T h2, T inv2d) {
-  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
-  constexpr int UX = TX + 4, UY = TY + 4, UZ = D == 3 ? TZ + 4 : 1;
-  constexpr int FX = TX + 2, FY = TY + 2, FZ = D == 3 ? TZ + 2 : 1;
-  __shared__ T su[UZ * UY * UX];
-  __shared__ T sf[FZ * FY * FX];
-  __shared__ int8_t sc[FZ * FY * FX];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile >= ntiles) return;
-  const int4 t = tiles[tile];
-  const int64_t base = (int64_t)t.x * g.npp;
-  const int ox = t.y * TX, oy = t.z * TY, oz = t.w * TZ;
-  for (int i = threadIdx.x; i < UZ * UY * UX; i += 256) {
-    const int x = i % UX, y = (i / UX) % UY, z = i / (UX * UY);
-    const int gx = ox + x - 2, gy = oy + y - 2, gz = D == 3 ? oz + z - 2 : 0;
-    T v = 0;
-    if (in_box(gx, gy, gz, g.np, D)) v = u[base + gx + g.st[1] * gy + g.st[2] * gz];
-    su[i] = v;
-  }
-  for (int i = threadIdx.x; i < FZ * FY * FX; i += 256) {
-    const int x = i % FX, y = (i / FX) % FY, z = i / (FX * FY);
-    const int gx = ox + x - 1, gy = oy + y - 1, gz = D == 3 ? oz + z - 1 : 0;
-    T f = 0;
-    int8_t c = 0;
-    if (in_box(gx, gy, gz, g.np, D)) {
-      const int64_t gi = base + gx + g.st[1] * gy + g.st[2] * gz;
-      c = cls[gi];
-      if (c == 1) f = rhs[gi];
-    }
-    sf[i] = f;
-    sc[i] = c;
-  }
-  __syncthreads();
-  constexpr int SY = UX, SZ = UX * UY;
-  for (int i = threadIdx.x; i < FZ * FY * FX; i += 256) {
-    if (sc[i] != 1) continue;
-    const int x = i % FX, y = (i / FX) % FY, z = i / (FX * FY);
-    const int gx = ox + x - 1, gy = oy + y - 1, gz = D == 3 ? oz + z - 1 : 0;
-    if ((gx + gy + gz) & 1) continue;
-    const int ui = (x + 1) + SY * (y + 1) + (D == 3 ? SZ * (z + 1) : 0);
-    const T c = su[ui];
-    T s = (su[ui - 1] - c) + (su[ui + 1] - c);
-    s += (su[ui - SY] - c) + (su[ui + SY] - c);
-    if (D == 3) s += (su[ui - SZ] - c) + (su[ui + SZ] - c);
-    su[ui] = c + (h2 * sf[i] + s) * inv2d;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
-    const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
-    const int fi = (x + 1) + FX * (y + 1) + (D == 3 ? FX * FY * (z + 1) : 0);
-    if (sc[fi] != 1) continue;
-    const int gx = ox + x, gy = oy + y, gz = D == 3 ? oz + z : 0;
-    if (!((gx + gy + gz) & 1)) continue;
-    const int ui = (x + 2) + SY * (y + 2) + (D == 3 ? SZ * (z + 2) : 0);
-    const T c = su[ui];
-    T s = (su[ui - 1] - c) + (su[ui + 1] - c);
-    s += (su[ui - SY] - c) + (su[ui + SY] - c);
-    if (D == 3) s += (su[ui - SZ] - c) + (su[ui + SZ] - c);
-    su[ui] = c + (h2 * sf[fi] + s) * inv2d;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
-    const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
-    const int fi = (x + 1) + FX * (y + 1) + (D == 3 ? FX * FY * (z + 1) : 0);
-    if (sc[fi] != 1) continue;
-    const int ui = (x + 2) + SY * (y + 2) + (D == 3 ? SZ * (z + 2) : 0);
-    u[base + (ox + x) + g.st[1] * (oy + y) + g.st[2] * (D == 3 ? oz + z : 0)] = su[ui];
-  }
+__device__ __forceinline__ T interior_update(T c, const T* nb, T f, T h2, T inv2d) {
+  T s = (nb[0] - c) + (nb[1] - c);
+  s += (nb[2] - c) + (nb[3] - c);
+  if (D == 3) s += (nb[4] - c) + (nb[5] - c);
+  return c + (h2 * f + s) * inv2d;
 }
 
-// ---------------------------------------------------------------------------------------
-// ghost rows: Eqs. (dir2d) / (neu2d) and the boundary part of the defect
-// ---------------------------------------------------------------------------------------
+// ghost node, Eqs. (dir2d) / (neu2d): u_G + c_G (g_G - L_G u), with L_G u accumulated over
+// the taps of nonzero weight in template order
+template <typename T>
+__device__ __forceinline__ T ghost_update(T uG, T gG, double Lu, double cG) {
+  return (T)((double)uG + cG * ((double)gG - Lu));
+}
+
+// L_G u of ghost i from the global arrays
 template <int D, typename T>
-__device__ __forceinline__ double ghost_apply(const GhostRec& r, const Geo& g,
-                                              const T* __restrict__ u, double inv_h) {
+__device__ __forceinline__ double ghost_apply(const GhostRec& r, const double* __restrict__ w,
+                                              const Geo& g, const T* __restrict__ u) {
   constexpr int K = Pow3<D>::value;
-  double w[K];
-  const uint32_t used = ghost_row<D>(r, inv_h, w);
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < K; ++t) {
-    if (!(used >> t & 1u)) continue;
-    acc += w[t] * (double)u[r.node + template_offset<D>(t, r.s, g.st)];
+    const double wt = w[t];
+    if (wt != 0.0) acc += wt * (double)u[r.node + template_offset<D>(t, r.s, g.st)];
   }
   return acc;
 }
 
+// ---------------------------------------------------------------------------------------
+// relaxation, interior tiles: red-black sweep of Eq. (jac2d), one tile per workgroup
+// ---------------------------------------------------------------------------------------
+// The tile and a ring of two nodes of uin are staged in LDS.  Red interior nodes of tile +
+// ring one are relaxed first (they read only black, ghost or outside values, which this
+// pass leaves unchanged), then the black interior nodes of the tile (which read the fresh
+// red values).  The result is the global red sweep followed by the global black sweep;
+// every workgroup writes its own tile of uout: the interior nodes off the boundary band
+// (the relaxation chunks write the band and the ghosts), or, with write_all, every unknown.
 template <int D, typename T>
-__device__ __forceinline__ T ghost_new_value(const GhostRec& r, const Geo& g,
-                                             const T* __restrict__ u, const T* __restrict__ rhs,
-                                             double inv_h, double cD, double cNh) {
-  const double Lu = ghost_apply<D, T>(r, g, u, inv_h);
-  const double c = r.type ? cD : cNh;
-  return (T)((double)u[r.node] + c * ((double)rhs[r.node] - Lu));
+__device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
+  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+  constexpr int UX = TX + 4, UY = TY + 4, UZ = D == 3 ? TZ + 4 : 1;
+  constexpr int FX = TX + 2, FY = TY + 2, FZ = D == 3 ? TZ + 2 : 1;
+  T* su = (T*)lds;
+  T* sf = su + UZ * UY * UX;
+  int8_t* sc = (int8_t*)(sf + FZ * FY * FX);
+  const int tile = xcd_tile(tb, a.nbt);
+  if (tile >= a.ntiles) return;
+  const Geo& g = a.g;
+  const int4 t = a.tiles[tile];
+  const int64_t base = (int64_t)t.x * g.npp;
+  const int ox = t.y * TX, oy = t.z * TY, oz = t.w * TZ;
+  // every global load of the thread is issued before the first is used: positions outside
+  // the box read the tile's first node and are replaced by zero afterwards
+  constexpr int NU = (UZ * UY * UX + 255) / 256, NF = (FZ * FY * FX + 255) / 256;
+  T uv[NU], fv[NF];
+  int8_t cv[NF];
+  bool uok[NU], fok[NF];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    const int x = i % UX, y = (i / UX) % UY, z = i / (UX * UY);
+    const int gx = ox + x - 2, gy = oy + y - 2, gz = D == 3 ? oz + z - 2 : 0;
+    uok[k] = i < UZ * UY * UX && in_box(gx, gy, gz, g.np, D);
+    uv[k] = a.uin[uok[k] ? base + gx + g.st[1] * gy + g.st[2] * gz : base];
+  }
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    const int x = i % FX, y = (i / FX) % FY, z = i / (FX * FY);
+    const int gx = ox + x - 1, gy = oy + y - 1, gz = D == 3 ? oz + z - 1 : 0;
+    fok[k] = i < FZ * FY * FX && in_box(gx, gy, gz, g.np, D);
+    const int64_t gi = fok[k] ? base + gx + g.st[1] * gy + g.st[2] * gz : base;
+    cv[k] = a.rcls[gi];
+    fv[k] = a.rhs[gi];
+  }
+#pragma unroll
+  for (int k = 0; k < NU; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < UZ * UY * UX) su[i] = uok[k] ? uv[k] : (T)0;
+  }
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < FZ * FY * FX) {
+      const int8_t c = fok[k] ? cv[k] : (int8_t)0;
+      sc[i] = c;
+      sf[i] = (c == 1 || c == 3) ? fv[k] : (T)0;
+    }
+  }
+  __syncthreads();
+  constexpr int SY = UX, SZ = UX * UY;
+  for (int i = threadIdx.x; i < FZ * FY * FX; i += 256) {
+    if (sc[i] != 1 && sc[i] != 3) continue;
+    const int x = i % FX, y = (i / FX) % FY, z = i / (FX * FY);
+    const int gx = ox + x - 1, gy = oy + y - 1, gz = D == 3 ? oz + z - 1 : 0;
+    if ((gx + gy + gz) & 1) continue;
+    const int ui = (x + 1) + SY * (y + 1) + (D == 3 ? SZ * (z + 1) : 0);
+    T nb[2 * D];
+    nb[0] = su[ui - 1];
+    nb[1] = su[ui + 1];
+    nb[2] = su[ui - SY];
+    nb[3] = su[ui + SY];
+    if (D == 3) {
+      nb[4] = su[ui - SZ];
+      nb[5] = su[ui + SZ];
+    }
+    su[ui] = interior_update<D, T>(su[ui], nb, sf[i], a.h2, a.inv2d);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
+    const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
+    const int fi = (x + 1) + FX * (y + 1) + (D == 3 ? FX * FY * (z + 1) : 0);
+    if (sc[fi] != 1 && sc[fi] != 3) continue;
+    const int gx = ox + x, gy = oy + y, gz = D == 3 ? oz + z : 0;
+    if (!((gx + gy + gz) & 1)) continue;
+    const int ui = (x + 2) + SY * (y + 2) + (D == 3 ? SZ * (z + 2) : 0);
+    T nb[2 * D];
+    nb[0] = su[ui - 1];
+    nb[1] = su[ui + 1];
+    nb[2] = su[ui - SY];
+    nb[3] = su[ui + SY];
+    if (D == 3) {
+      nb[4] = su[ui - SZ];
+      nb[5] = su[ui + SZ];
+    }
+    su[ui] = interior_update<D, T>(su[ui], nb, sf[fi], a.h2, a.inv2d);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
+    const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
+    const int fi = (x + 1) + FX * (y + 1) + (D == 3 ? FX * FY * (z + 1) : 0);
+    const int8_t c = sc[fi];
+    if (c == 0 || (c != 1 && !a.write_all)) continue;
+    const int ui = (x + 2) + SY * (y + 2) + (D == 3 ? SZ * (z + 2) : 0);
+    a.uout[base + (ox + x) + g.st[1] * (oy + y) + g.st[2] * (D == 3 ? oz + z : 0)] = su[ui];
+  }
 }
 
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_ghost_new(const GhostRec* __restrict__ gs, int ng, Geo g,
+constexpr size_t tile_lds() {
+  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+  constexpr int UX = TX + 4, UY = TY + 4, UZ = D == 3 ? TZ + 4 : 1;
+  constexpr int FX = TX + 2, FY = TY + 2, FZ = D == 3 ? TZ + 2 : 1;
+  return (size_t)(UZ * UY * UX + FZ * FY * FX) * sizeof(T) + (size_t)FZ * FY * FX;
+}
+
+// ---------------------------------------------------------------------------------------
+// relaxation, boundary chunks: the whole relaxation of one chunk's node set
+// ---------------------------------------------------------------------------------------
+// The chunk's node set is closed under the dependencies of its owned nodes (band and
+// ghost nodes) through the 3 + 3 lambda phases (red interior, black interior, ghosts; then
+// lambda times red band, black band, ghosts, Sec. 3.2).  Each thread owns up to
+// kChunkPerThread entries and keeps their node index, phase mask, neighbour ids and
+// right-hand side in registers (the thread owning an updated ghost also keeps its stencil
+// ids, weights and constant); only the node values are shared, in LDS.  Phases are separated
+// by workgroup barriers; a ghost phase computes every new ghost value before any is stored.
+// The owned entries are written to uout.
+template <int D, typename T>
+__device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
+  constexpr int K = Pow3<D>::value;
+  constexpr int NK = kChunkPerThread;
+  // the header is uniform over the workgroup; every per-entry load below is issued without
+  // a branch (entries past the end read entry 0 and are masked off)
+  const int cu = __builtin_amdgcn_readfirstlane(c);
+  int32_t hd[kBandHdr];
+#pragma unroll
+  for (int q = 0; q < kBandHdr; ++q) hd[q] = a.hdr[(int64_t)cu * kBandHdr + q];
+  const int ns = hd[0], ng = hd[1];
+  const int32_t* E = a.data + hd[2];
+  const int tid = threadIdx.x;
+  int32_t node[NK];
+  uint32_t mask[NK];
+  int32_t nbw[NK][D];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int e = tid + k * kChunkThreads;
+    const int ec = e < ns ? e : 0;
+    node[k] = E[ec];
+    const uint32_t mk = (uint32_t)E[ns + ec];
+    mask[k] = e < ns ? mk : 0u;
+#pragma unroll
+    for (int q = 0; q < D; ++q) nbw[k][q] = E[2 * ns + ec * D + q];
+  }
+  const bool ghost = tid < ng;
+  int32_t gid[K];
+  double gwt[K];
+  double gc = 0.0;
+  if (ng > 0) {
+    const int tg = ghost ? tid : 0;
+    const int32_t* gi = a.data + hd[3];
+    const double* gw = (const double*)(a.data + hd[4]);
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      gid[q] = gi[q * ng + tg];
+      gwt[q] = gw[q * ng + tg];
+    }
+    gc = ((const double*)(a.data + hd[5]))[tg];
+  }
+  T rv[NK], uv[NK];
+  T* su = (T*)lds;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    uv[k] = a.uin[node[k]];
+    rv[k] = a.rhs[node[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int e = tid + k * kChunkThreads;
+    if (e < ns) su[e] = uv[k];
+  }
+  __syncthreads();
+  for (int p = 0; p < a.phases; ++p) {
+    if (p % 3 != 2) {
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        if (!((mask[k] >> p) & 1u)) continue;
+        const int e = tid + k * kChunkThreads;
+        T nv[2 * D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          nv[2 * q] = su[(int16_t)(nbw[k][q] & 0xffff)];
+          nv[2 * q + 1] = su[(int16_t)((uint32_t)nbw[k][q] >> 16)];
+        }
+        su[e] = interior_update<D, T>(su[e], nv, rv[k], a.h2, a.inv2d);
+      }
+      __syncthreads();
+    } else {
+      const bool upd = ghost && ((mask[0] >> p) & 1u);
+      T gnew = 0;
+      if (upd) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+          if (gid[q] >= 0) acc += gwt[q] * (double)su[gid[q]];
+        gnew = ghost_update<T>(su[tid], rv[0], acc, gc);
+      }
+      __syncthreads();
+      if (upd) su[tid] = gnew;
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int e = tid + k * kChunkThreads;
+    if (e < ns && (mask[k] >> 31)) a.uout[node[k]] = su[e];
+  }
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_relax(RelaxArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char relax_smem[];
+  if ((int)blockIdx.x < a.nchunks)
+    relax_chunk<D, T>(a, blockIdx.x, relax_smem);
+  else
+    relax_tile<D, T>(a, (int)blockIdx.x - a.nchunks, relax_smem);
+}
+
+// ---------------------------------------------------------------------------------------
+// boundary relaxation one phase per launch (levels without relaxation chunks), in place
+// ---------------------------------------------------------------------------------------
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_ghost_new(const GhostRec* __restrict__ gs,
+                                                   const double* __restrict__ gw, int ng, Geo g,
                                                    const T* __restrict__ u, const T* __restrict__ rhs,
-                                                   T* __restrict__ tmp, double inv_h, double cD,
-                                                   double cNh) {
+                                                   T* __restrict__ tmp, double cD, double cNh) {
+  constexpr int K = Pow3<D>::value;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= ng) return;
-  tmp[i] = ghost_new_value<D, T>(gs[i], g, u, rhs, inv_h, cD, cNh);
+  const GhostRec r = gs[i];
+  const double Lu = ghost_apply<D, T>(r, gw + (size_t)i * K, g, u);
+  tmp[i] = ghost_update<T>(u[r.node], rhs[r.node], Lu, r.type ? cD : cNh);
 }
 
 template <typename T>
@@ -167,11 +328,16 @@ __global__ void __launch_bounds__(256) k_ghost_store(const GhostRec* __restrict_
 template <int D, typename T>
 __device__ __forceinline__ void relax_node(int64_t P, const Geo& g, T* __restrict__ u,
                                            const T* __restrict__ rhs, T h2, T inv2d) {
-  const T c = u[P];
-  T s = (u[P - 1] - c) + (u[P + 1] - c);
-  s += (u[P - g.st[1]] - c) + (u[P + g.st[1]] - c);
-  if (D == 3) s += (u[P - g.st[2]] - c) + (u[P + g.st[2]] - c);
-  u[P] = c + (h2 * rhs[P] + s) * inv2d;
+  T nb[2 * D];
+  nb[0] = u[P - 1];
+  nb[1] = u[P + 1];
+  nb[2] = u[P - g.st[1]];
+  nb[3] = u[P + g.st[1]];
+  if (D == 3) {
+    nb[4] = u[P - g.st[2]];
+    nb[5] = u[P + g.st[2]];
+  }
+  u[P] = interior_update<D, T>(u[P], nb, rhs[P], h2, inv2d);
 }
 
 template <int D, typename T>
@@ -188,6 +354,7 @@ __global__ void __launch_bounds__(256) k_relax_list(const int32_t* __restrict__ 
 // is separated by a workgroup barrier, so the whole sequence is one launch.
 template <int D, typename T>
 __global__ void __launch_bounds__(1024) k_band(BandArgs<T> a) {
+  constexpr int K = Pow3<D>::value;
   const int p = blockIdx.x;
   const int g0 = a.ghost_off[p], g1 = a.ghost_off[p + 1];
   const int r0 = a.red_off[p], r1 = a.red_off[p + 1];
@@ -200,147 +367,195 @@ __global__ void __launch_bounds__(1024) k_band(BandArgs<T> a) {
       for (int i = b0 + tid; i < b1; i += 1024) relax_node<D, T>(a.black[i], a.g, a.u, a.rhs, a.h2, a.inv2d);
       __syncthreads();
     }
-    for (int i = g0 + tid; i < g1; i += 1024)
-      a.tmp[i] = ghost_new_value<D, T>(a.ghosts[i], a.g, a.u, a.rhs, a.inv_h, a.cD, a.cNh);
+    for (int i = g0 + tid; i < g1; i += 1024) {
+      const GhostRec r = a.ghosts[i];
+      const double Lu = ghost_apply<D, T>(r, a.gw + (size_t)i * K, a.g, a.u);
+      a.tmp[i] = ghost_update<T>(a.u[r.node], a.rhs[r.node], Lu, r.type ? a.cD : a.cNh);
+    }
     __syncthreads();
     for (int i = g0 + tid; i < g1; i += 1024) a.u[a.ghosts[i].node] = a.tmp[i];
     __syncthreads();
   }
 }
 
-// Ghost relaxation and lambda band sweeps with the band held in LDS: one workgroup per
-// chunk runs all 1 + 3 lambda phases (ghosts; then red band, black band, ghosts, lambda
-// times) on the chunk's dependency-closed node set, with workgroup barriers between phases,
-// and stores the results of the nodes it owns.  k_band_scatter then writes them to u (no
-// chunk may overwrite a value another chunk is still loading).
-template <int D, typename T>
-__global__ void __launch_bounds__(256) k_band_chunk(BandChunkArgs<T> a) {
-  constexpr int K = Pow3<D>::value;
-  extern __shared__ double lds_d[];
-  const int c = blockIdx.x;
-  const int s0 = a.off[c], ns = a.off[c + 1] - s0;
-  const int g0 = a.goff[c], ngc = a.goff[c + 1] - g0;
-  const int32_t* ops_off = a.ops_off + (int64_t)c * (a.phases + 1);
-  const int o_base = ops_off[0], nops = ops_off[a.phases] - o_base;
-  // LDS layout: ghost weights, ghost constants (FP64); u, rhs, new ghost values (T);
-  // neighbour ids, ghost stencil ids, ghost entry ids, op lists (int16)
-  double* gw = lds_d;
-  double* gc = gw + (size_t)a.gmax * K;
-  T* su = (T*)(gc + a.gmax);
-  T* sr = su + a.smax;
-  T* st = sr + a.smax;
-  int16_t* nb = (int16_t*)(st + a.gmax);
-  int16_t* gs = nb + (size_t)a.smax * 2 * D;
-  int16_t* ge = gs + (size_t)a.gmax * K;
-  int16_t* ops = ge + a.gmax;
-  for (int i = threadIdx.x; i < ns; i += 256) {
-    const int32_t v = a.node[s0 + i];
-    su[i] = a.u[v];
-    sr[i] = a.rhs[v];
-  }
-  for (int i = threadIdx.x; i < ns * 2 * D; i += 256) nb[i] = a.nbr[(int64_t)s0 * 2 * D + i];
-  for (int i = threadIdx.x; i < ngc * K; i += 256) gs[i] = a.gsten[(int64_t)g0 * K + i];
-  for (int i = threadIdx.x; i < nops; i += 256) ops[i] = a.ops[o_base + i];
-  for (int j = threadIdx.x; j < ngc; j += 256) {
-    const GhostRec r = a.ghosts[a.gidx[g0 + j]];
-    double w[K];
-    const uint32_t used = ghost_row<D>(r, a.inv_h, w);
+// ---------------------------------------------------------------------------------------
+// defect (Sec. 2.4 step 3) with per-problem infinity norms, and its extension outside
+// Omega_h, Eq. (exp) in its steady state
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void extend_one(const ExtRec& e, T* __restrict__ r) {
+  double num = 0.0, den = 0.0;
 #pragma unroll
-    for (int t = 0; t < K; ++t) gw[(size_t)j * K + t] = (used >> t & 1u) ? w[t] : 0.0;
-    gc[j] = r.type ? a.cD : a.cNh;
-    ge[j] = a.gent[g0 + j];
+  for (int a = 0; a < 3; ++a) {
+    if (e.src[a] < 0) continue;
+    num += e.wt[a] * (double)r[e.src[a]];
+    den += e.wt[a];
+  }
+  r[e.node] = (T)(den > 0.0 ? num / den : 0.0);
+}
+
+// Extension chunk: the ghost defects the chunk reads are evaluated from u (the same
+// arithmetic as the ghost rows of the defect), then its extension nodes are computed DAG
+// level by DAG level (each value rounded to the defect's type, as when it is stored) and the
+// owned ones are written to r.  Each thread owns up to kChunkPerThread entries and keeps
+// their node index, DAG level, source ids and weights in registers; only the values are
+// shared, in LDS.
+template <int D, typename T, typename TO>
+__device__ void extend_chunk(const DefectArgs<T, TO>& a, int c, unsigned char* lds) {
+  constexpr int K = Pow3<D>::value;
+  constexpr int NK = kChunkPerThread;
+  const int cu = __builtin_amdgcn_readfirstlane(c);
+  int32_t hd[kExtHdr];
+#pragma unroll
+  for (int q = 0; q < kExtHdr; ++q) hd[q] = a.hdr[(int64_t)cu * kExtHdr + q];
+  const int nt = hd[0], ngs = hd[1], nlvl = hd[7];
+  const int32_t* E = a.data + hd[2];
+  const int32_t* S = a.data + hd[3];
+  const double* W = (const double*)(a.data + hd[4]);
+  const int tid = threadIdx.x;
+  int32_t node[NK], src[NK][2];
+  uint32_t meta[NK];
+  double w[NK][3];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int e = tid + k * kChunkThreads;
+    const int ec = e < nt ? e : 0;
+    node[k] = E[ec];
+    const uint32_t mt = (uint32_t)E[nt + ec];
+    meta[k] = e < nt ? mt : 0u;
+    src[k][0] = S[2 * ec];
+    src[k][1] = S[2 * ec + 1];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) w[k][q] = W[q * nt + ec];
+  }
+  double* sv = (double*)lds;
+  if (ngs > 0) {
+    const bool gsrc = tid < ngs;
+    const int tg = gsrc ? tid : 0;
+    const int32_t* gn = a.data + hd[5];
+    const double* gw = (const double*)(a.data + hd[6]);
+    int32_t gnode[K];
+    double gwt[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      gnode[q] = gn[q * ngs + tg];
+      gwt[q] = gw[q * ngs + tg];
+    }
+    double uq[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) uq[q] = (double)a.u[gnode[q]];
+    const double rG = (double)a.rhs[node[0]];
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+      if (gwt[q] != 0.0) acc += gwt[q] * uq[q];
+    if (gsrc) sv[tid] = (double)(TO)(rG - acc);
   }
   __syncthreads();
-  for (int p = 0; p < a.phases; ++p) {
-    const int kind = p == 0 ? 3 : ((p - 1) % 3 == 0 ? 1 : ((p - 1) % 3 == 1 ? 2 : 3));
-    const int o0 = ops_off[p] - o_base, o1 = ops_off[p + 1] - o_base;
-    if (kind != 3) {
-      for (int i = o0 + threadIdx.x; i < o1; i += 256) {
-        const int v = ops[i];
-        const int16_t* n = nb + v * (2 * D);
-        const T cv = su[v];
-        T sum = (su[n[0]] - cv) + (su[n[1]] - cv);
-        sum += (su[n[2]] - cv) + (su[n[3]] - cv);
-        if (D == 3) sum += (su[n[4]] - cv) + (su[n[5]] - cv);
-        su[v] = cv + (a.h2 * sr[v] + sum) * a.inv2d;
-      }
-    } else {
-      for (int i = o0 + threadIdx.x; i < o1; i += 256) {
-        const int j = ops[i];
-        const int v = ge[j];
-        const double* w = gw + (size_t)j * K;
-        const int16_t* sn = gs + (size_t)j * K;
-        double acc = 0.0;
+  for (int d = 1; d <= nlvl; ++d) {
 #pragma unroll
-        for (int t = 0; t < K; ++t)
-          if (sn[t] >= 0) acc += w[t] * (double)su[sn[t]];
-        st[j] = (T)((double)su[v] + gc[j] * ((double)sr[v] - acc));
+    for (int k = 0; k < NK; ++k) {
+      if ((int)(meta[k] & 0xffff) != d) continue;
+      double num = 0.0, den = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int s = q < 2 ? (int16_t)((uint32_t)src[k][0] >> (16 * q)) : (int16_t)(src[k][1] & 0xffff);
+        if (s < 0) continue;
+        num += w[k][q] * sv[s];
+        den += w[k][q];
       }
-      __syncthreads();
-      for (int i = o0 + threadIdx.x; i < o1; i += 256) su[ge[ops[i]]] = st[ops[i]];
+      sv[tid + k * kChunkThreads] = (double)(TO)(den > 0.0 ? num / den : 0.0);
     }
     __syncthreads();
   }
-  const int own = a.own[c], out0 = a.out_off[c];
-  for (int i = threadIdx.x; i < own; i += 256) a.out[out0 + i] = su[i];
+#pragma unroll
+  for (int k = 0; k < NK; ++k)
+    if (meta[k] >> 31) a.r[node[k]] = (TO)sv[tid + k * kChunkThreads];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_band_scatter(const int32_t* __restrict__ node, int n,
-                                                      const T* __restrict__ out, T* __restrict__ u) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) u[node[i]] = out[i];
-}
-
-// ---------------------------------------------------------------------------------------
-// defect (Sec. 2.4 step 3) with per-problem infinity norms
-// ---------------------------------------------------------------------------------------
-// One launch: workgroups [0, nbt) take the active tiles (interior rows), the rest take the
-// ghost records (boundary rows).  Per-problem maxima of |r| go to norms[2p] (interior) and
+// One launch: extension chunks, then the active tiles (interior rows), then the ghost
+// records (boundary rows).  Per-problem maxima of |r| go to norms[2p] (interior) and
 // norms[2p + 1] (ghosts) through order-independent integer maxima, so the result is
 // deterministic.
 template <int D, typename T, typename TO>
-__global__ void __launch_bounds__(256) k_defect(const int4* __restrict__ tiles, int ntiles, int nbt,
-                                                const GhostRec* __restrict__ gs, int ng, Geo g,
-                                                const int8_t* __restrict__ cls,
-                                                const T* __restrict__ u, const T* __restrict__ rhs,
-                                                TO* __restrict__ r, T inv_h2, double inv_h,
-                                                uint64_t* __restrict__ norms) {
+__global__ void __launch_bounds__(256) k_defect(DefectArgs<T, TO> a) {
   constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+  constexpr int K = Pow3<D>::value;
+  extern __shared__ __align__(16) unsigned char defect_smem[];
   __shared__ double red[4];
-  if ((int)blockIdx.x < nbt) {
-    const int tile = xcd_tile(blockIdx.x, nbt);
-    if (tile >= ntiles) return;
-    const int4 t = tiles[tile];
+  int b = blockIdx.x;
+  if (b < a.nechunks) {
+    extend_chunk<D, T, TO>(a, b, defect_smem);
+    return;
+  }
+  b -= a.nechunks;
+  const Geo& g = a.g;
+  if (b < a.nbt) {
+    const int tile = xcd_tile(b, a.nbt);
+    if (tile >= a.ntiles) return;
+    const int4 t = a.tiles[tile];
     const int64_t base = (int64_t)t.x * g.npp;
+    constexpr int NK = TZ * TY * TX / 256;
+    int64_t P[NK];
+    bool ok[NK];
+    int8_t cl[NK];
+    T uc[NK], f[NK], un[NK][2 * D];
+    // all loads first (neighbours outside the box read the node itself)
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      const int j[3] = {t.y * TX + i % TX, t.z * TY + (i / TX) % TY, D == 3 ? t.w * TZ + i / (TX * TY) : 0};
+      ok[k] = in_box(j[0], j[1], j[2], g.np, D);
+      P[k] = ok[k] ? base + j[0] + g.st[1] * j[1] + g.st[2] * j[2] : base;
+      cl[k] = a.cls[P[k]];
+      uc[k] = a.u[P[k]];
+      f[k] = a.rhs[P[k]];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        un[k][2 * q] = a.u[ok[k] && j[q] > 0 ? P[k] - g.st[q] : P[k]];
+        un[k][2 * q + 1] = a.u[ok[k] && j[q] < g.np - 1 ? P[k] + g.st[q] : P[k]];
+      }
+    }
     double m = 0.0;
-    for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
-      const int x = t.y * TX + i % TX, y = t.z * TY + (i / TX) % TY;
-      const int z = D == 3 ? t.w * TZ + i / (TX * TY) : 0;
-      if (!in_box(x, y, z, g.np, D)) continue;
-      const int64_t P = base + x + g.st[1] * y + g.st[2] * z;
-      if (cls[P] != 1) continue;
-      const T c = u[P];
-      T s = (u[P - 1] - c) + (u[P + 1] - c);
-      s += (u[P - g.st[1]] - c) + (u[P + g.st[1]] - c);
-      if (D == 3) s += (u[P - g.st[2]] - c) + (u[P + g.st[2]] - c);
-      const T v = rhs[P] + s * inv_h2;
-      r[P] = (TO)v;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      if (!ok[k] || cl[k] != 1) continue;
+      const T c = uc[k];
+      T s = (un[k][0] - c) + (un[k][1] - c);
+      s += (un[k][2] - c) + (un[k][3] - c);
+      if (D == 3) s += (un[k][4] - c) + (un[k][5] - c);
+      const T v = f[k] + s * a.inv_h2;
+      a.r[P[k]] = (TO)v;
       m = fmax(m, fabs((double)v));
       if (!(v == v)) m = __longlong_as_double(0x7ff0000000000000LL);
     }
-    if (norms) {
+    if (a.norms) {
       m = block_max(m, red);
-      if (threadIdx.x == 0) atomic_max_pos(&norms[2 * t.x], m);
+      if (threadIdx.x == 0) atomic_max_pos(&a.norms[2 * t.x], m);
     }
     return;
   }
-  const int i = ((int)blockIdx.x - nbt) * 256 + threadIdx.x;
-  if (i >= ng) return;
-  const GhostRec rec = gs[i];
-  const double v = (double)rhs[rec.node] - ghost_apply<D, T>(rec, g, u, inv_h);
-  r[rec.node] = (TO)v;
-  if (norms) atomic_max_pos(&norms[2 * (rec.node / g.npp) + 1], fabs(v));
+  const int i = (b - a.nbt) * 256 + threadIdx.x;
+  int p = -1;
+  double m = 0.0;
+  if (i < a.nghost) {
+    const GhostRec rec = a.ghosts[i];
+    const double v = (double)a.rhs[rec.node] - ghost_apply<D, T>(rec, a.gw + (size_t)i * K, g, a.u);
+    a.r[rec.node] = (TO)v;
+    p = (int)(rec.node / g.npp);
+    m = fabs(v);
+    if (!(m == m)) m = __longlong_as_double(0x7ff0000000000000LL);
+  }
+  if (!a.norms) return;
+  // one atomic per wave when its ghosts all belong to one problem (ghosts are ordered by
+  // problem, so this is the common case)
+  const int p0 = __shfl(p, 0);
+  if (__all(p == p0 || p < 0)) {
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0 && p0 >= 0) atomic_max_pos(&a.norms[2 * p0 + 1], m);
+  } else if (p >= 0) {
+    atomic_max_pos(&a.norms[2 * p + 1], m);
+  }
 }
 
 // ||(f_h, g_h)||_inf per problem: max |rhs| over the unknowns
@@ -355,36 +570,33 @@ __global__ void __launch_bounds__(256) k_rhs_norm(const int4* __restrict__ tiles
   if (tile >= ntiles) return;
   const int4 t = tiles[tile];
   const int64_t base = (int64_t)t.x * g.npp;
-  double m = 0.0;
-  for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
+  constexpr int NK = TZ * TY * TX / 256;
+  bool ok[NK];
+  int8_t c[NK];
+  double f[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int i = threadIdx.x + 256 * k;
     const int x = t.y * TX + i % TX, y = t.z * TY + (i / TX) % TY;
     const int z = D == 3 ? t.w * TZ + i / (TX * TY) : 0;
-    if (!in_box(x, y, z, g.np, D)) continue;
-    const int64_t P = base + x + g.st[1] * y + g.st[2] * z;
-    if (cls[P] == 0) continue;
-    m = fmax(m, fabs(rhs[P]));
-    if (!(rhs[P] == rhs[P])) m = __longlong_as_double(0x7ff0000000000000LL);
+    ok[k] = in_box(x, y, z, g.np, D);
+    const int64_t P = ok[k] ? base + x + g.st[1] * y + g.st[2] * z : base;
+    c[k] = cls[P];
+    f[k] = rhs[P];
+  }
+  double m = 0.0;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    if (!ok[k] || c[k] == 0) continue;
+    m = fmax(m, fabs(f[k]));
+    if (!(f[k] == f[k])) m = __longlong_as_double(0x7ff0000000000000LL);
   }
   m = block_max(m, red);
   if (threadIdx.x == 0) atomic_max_pos(&norms[2 * t.x], m);
 }
 
-// ---------------------------------------------------------------------------------------
-// extension of the defect outside Omega_h, Eq. (exp) in its steady state
-// ---------------------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void extend_one(const ExtRec& e, T* __restrict__ r) {
-  double num = 0.0, den = 0.0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (e.src[a] < 0) continue;
-    num += e.wt[a] * (double)r[e.src[a]];
-    den += e.wt[a];
-  }
-  r[e.node] = (T)(den > 0.0 ? num / den : 0.0);
-}
-
-// one workgroup per problem, DAG levels separated by barriers
+// extension without chunks: one workgroup per problem with DAG levels separated by
+// barriers, or one launch per DAG level
 template <typename T>
 __global__ void __launch_bounds__(1024) k_extend_wg(const ExtRec* __restrict__ ext,
                                                     const int32_t* __restrict__ dag_off,
@@ -398,45 +610,6 @@ __global__ void __launch_bounds__(1024) k_extend_wg(const ExtRec* __restrict__ e
   }
 }
 
-// chunked extension: the chunk's ghost defects are read into LDS, its extension nodes are
-// computed DAG level by DAG level in LDS, and only the owned nodes are written back
-template <typename T>
-__global__ void __launch_bounds__(256) k_extend_chunk(const int32_t* __restrict__ off,
-                                                      const int32_t* __restrict__ own,
-                                                      const int32_t* __restrict__ next,
-                                                      const int32_t* __restrict__ node,
-                                                      const int16_t* __restrict__ src,
-                                                      const double* __restrict__ wt,
-                                                      const int16_t* __restrict__ ops,
-                                                      const int32_t* __restrict__ lvl,
-                                                      const int32_t* __restrict__ lvl_start,
-                                                      T* __restrict__ r) {
-  extern __shared__ double ext_lds[];
-  const int c = blockIdx.x;
-  const int s0 = off[c], ns = off[c + 1] - s0, ne = next[c];
-  double* sv = ext_lds;
-  for (int i = threadIdx.x; i < ns; i += 256) sv[i] = i >= ne ? (double)r[node[s0 + i]] : 0.0;
-  __syncthreads();
-  for (int d = lvl_start[c]; d + 1 < lvl_start[c + 1]; ++d) {
-    for (int k = lvl[d] + threadIdx.x; k < lvl[d + 1]; k += 256) {
-      const int i = ops[k];
-      double num = 0.0, den = 0.0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int q = src[(int64_t)(s0 + i) * 3 + a];
-        if (q < 0) continue;
-        const double w = wt[(int64_t)(s0 + i) * 3 + a];
-        num += w * sv[q];
-        den += w;
-      }
-      sv[i] = den > 0.0 ? num / den : 0.0;
-    }
-    __syncthreads();
-  }
-  for (int i = threadIdx.x; i < own[c]; i += 256) r[node[s0 + i]] = (T)sv[i];
-}
-
-// all problems' nodes of one DAG level
 template <typename T>
 __global__ void __launch_bounds__(256) k_extend_level(const ExtRec* __restrict__ ext, int a, int b,
                                                       T* __restrict__ r) {
@@ -456,31 +629,62 @@ __global__ void __launch_bounds__(256) k_restrict(const int4* __restrict__ tiles
                                                   const T* __restrict__ rf, T* __restrict__ rhsc,
                                                   T* __restrict__ uc) {
   constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+  constexpr int KT = Pow3<D>::value;
+  constexpr int NK = TZ * TY * TX / 256;
+  constexpr int NB = D == 2 ? NK : 1;  // coarse nodes whose fine taps are loaded together
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntiles) return;
   const int4 t = tiles[tile];
   const int64_t basec = (int64_t)t.x * gc.npp, basef = (int64_t)t.x * gf.npp;
-  for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
-    const int x = t.y * TX + i % TX, y = t.z * TY + (i / TX) % TY;
-    const int z = D == 3 ? t.w * TZ + i / (TX * TY) : 0;
-    if (!in_box(x, y, z, gc.np, D)) continue;
-    const int64_t X = basec + x + gc.st[1] * y + gc.st[2] * z;
-    uc[X] = (T)0;
-    const uint8_t c = code[X];
-    if (c == kNoUnknown) continue;
-    const int lx = (c & 1) ? -1 : 0, hx = (c & 2) ? 1 : 0;
-    const int ly = (c & 4) ? -1 : 0, hy = (c & 8) ? 1 : 0;
-    const int lz = D == 3 && (c & 16) ? -1 : 0, hz = D == 3 && (c & 32) ? 1 : 0;
-    const int64_t F0 = basef + 2 * x + gf.st[1] * 2 * y + gf.st[2] * 2 * z;
-    T s = 0;
-    for (int kx = lx; kx <= hx; ++kx)
-      for (int ky = ly; ky <= hy; ++ky)
-        for (int kz = lz; kz <= hz; ++kz) {
-          const T w = (T)(restrict_w1d(lx, hx, kx) * restrict_w1d(ly, hy, ky) *
-                          (D == 3 ? restrict_w1d(lz, hz, kz) : 1.0));
-          s += w * rf[F0 + kx + gf.st[1] * ky + gf.st[2] * kz];
-        }
-    rhsc[X] = s;
+#pragma unroll
+  for (int k0 = 0; k0 < NK; k0 += NB) {
+    int64_t X[NB];
+    bool ok[NB];
+    uint8_t cd[NB];
+    T rv[NB][KT];
+    // the 3^D fine neighbourhood of every coarse node is loaded before any is used (taps
+    // outside the fine box read the centre); taps outside the node's box get weight 0,
+    // which leaves the sum over the box, taken in the same order, unchanged
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int i = threadIdx.x + 256 * (k0 + k);
+      const int x = t.y * TX + i % TX, y = t.z * TY + (i / TX) % TY;
+      const int z = D == 3 ? t.w * TZ + i / (TX * TY) : 0;
+      ok[k] = in_box(x, y, z, gc.np, D);
+      X[k] = ok[k] ? basec + x + gc.st[1] * y + gc.st[2] * z : basec;
+      cd[k] = code[X[k]];
+      const int fx = 2 * x, fy = 2 * y, fz = 2 * z;
+      const int64_t F0 = basef + fx + gf.st[1] * fy + gf.st[2] * fz;
+#pragma unroll
+      for (int q = 0; q < KT; ++q) {
+        const int kx = q / (D == 3 ? 9 : 3) - 1, ky = (q / (D == 3 ? 3 : 1)) % 3 - 1;
+        const int kz = D == 3 ? q % 3 - 1 : 0;
+        const bool in = ok[k] && in_box(fx + kx, fy + ky, fz + kz, gf.np, D);
+        rv[k][q] = rf[in ? F0 + kx + gf.st[1] * ky + gf.st[2] * kz : (ok[k] ? F0 : basef)];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      if (!ok[k]) continue;
+      uc[X[k]] = (T)0;
+      const uint8_t c = cd[k];
+      if (c == kNoUnknown) continue;
+      const int lx = (c & 1) ? -1 : 0, hx = (c & 2) ? 1 : 0;
+      const int ly = (c & 4) ? -1 : 0, hy = (c & 8) ? 1 : 0;
+      const int lz = D == 3 && (c & 16) ? -1 : 0, hz = D == 3 && (c & 32) ? 1 : 0;
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < KT; ++q) {
+        const int kx = q / (D == 3 ? 9 : 3) - 1, ky = (q / (D == 3 ? 3 : 1)) % 3 - 1;
+        const int kz = D == 3 ? q % 3 - 1 : 0;
+        const bool inbox = kx >= lx && kx <= hx && ky >= ly && ky <= hy && kz >= lz && kz <= hz;
+        const T w = inbox ? (T)(restrict_w1d(lx, hx, kx) * restrict_w1d(ly, hy, ky) *
+                                (D == 3 ? restrict_w1d(lz, hz, kz) : 1.0))
+                          : (T)0;
+        s += w * rv[k][q];
+      }
+      rhsc[X[k]] = s;
+    }
   }
 }
 
@@ -494,42 +698,60 @@ __global__ void __launch_bounds__(256) k_prolong(const int4* __restrict__ tiles,
                                                  const int8_t* __restrict__ clsc,
                                                  const T* __restrict__ uc, T* __restrict__ uf) {
   constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+  constexpr int NK = TZ * TY * TX / 256;
+  constexpr int NC = 1 << D;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntiles) return;
   const int4 t = tiles[tile];
   const int64_t basef = (int64_t)t.x * gf.npp, basec = (int64_t)t.x * gc.npp;
-  for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
-    const int x = t.y * TX + i % TX, y = t.z * TY + (i / TX) % TY;
-    const int z = D == 3 ? t.w * TZ + i / (TX * TY) : 0;
-    if (!in_box(x, y, z, gf.np, D)) continue;
-    const int64_t P = basef + x + gf.st[1] * y + gf.st[2] * z;
-    if (clsf[P] == 0) continue;
-    const int j[3] = {x, y, z};
-    T num = 0, den = 0;
+  int64_t P[NK];
+  bool ok[NK];
+  int8_t cf[NK], cc[NK][NC];
+  T ufv[NK], ucv[NK][NC], wv[NK][NC];
+  // all loads first; candidates that do not exist read the first coarse node with weight 0
 #pragma unroll
-    for (int m = 0; m < (1 << D); ++m) {
-      bool skip = false;
+  for (int k = 0; k < NK; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    const int j[3] = {t.y * TX + i % TX, t.z * TY + (i / TX) % TY, D == 3 ? t.w * TZ + i / (TX * TY) : 0};
+    ok[k] = in_box(j[0], j[1], j[2], gf.np, D);
+    P[k] = ok[k] ? basef + j[0] + gf.st[1] * j[1] + gf.st[2] * j[2] : basef;
+    cf[k] = clsf[P[k]];
+    ufv[k] = uf[P[k]];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+      bool skip = !ok[k];
       T w = 1;
       int64_t X = basec;
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const int bit = (m >> a) & 1;
+      for (int q = 0; q < D; ++q) {
+        const int bit = (m >> q) & 1;
         int jc;
-        if ((j[a] & 1) == 0) {
+        if ((j[q] & 1) == 0) {
           if (bit) skip = true;
-          jc = j[a] >> 1;
+          jc = j[q] >> 1;
         } else {
-          jc = bit ? (j[a] + 1) >> 1 : (j[a] - 1) >> 1;
+          jc = bit ? (j[q] + 1) >> 1 : (j[q] - 1) >> 1;
           w *= (T)0.5;
         }
-        X += gc.st[a] * jc;
+        X += gc.st[q] * jc;
       }
-      if (skip) continue;
-      if (clsc[X] == 0) continue;
-      num += w * uc[X];
-      den += w;
+      if (skip) X = basec;
+      wv[k][m] = skip ? (T)0 : w;
+      cc[k][m] = clsc[X];
+      ucv[k][m] = uc[X];
     }
-    if (den > (T)0) uf[P] += num / den;
+  }
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    if (!ok[k] || cf[k] == 0) continue;
+    T num = 0, den = 0;
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+      if (wv[k][m] == (T)0 || cc[k][m] == 0) continue;
+      num += wv[k][m] * ucv[k][m];
+      den += wv[k][m];
+    }
+    if (den > (T)0) uf[P[k]] = ufv[k] + num / den;
   }
 }
 
@@ -547,18 +769,43 @@ __global__ void __launch_bounds__(256) k_coarse(const int32_t* __restrict__ umap
   const int a = umap_off[p], nu = umap_off[p + 1] - a;
   const int row0 = blockIdx.x * kCoarseRows;
   if (row0 >= nu) return;
-  for (int i = threadIdx.x; i < nu; i += 256) bsh[i] = (double)rhs[umap[a + i]];
+  // right-hand side in LDS, 8 gathers in flight per thread
+  for (int i0 = 0; i0 < nu; i0 += 8 * 256) {
+    int32_t idx[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + threadIdx.x + 256 * q;
+      idx[q] = i < nu ? umap[a + i] : umap[a];
+    }
+    T v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = rhs[idx[q]];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + threadIdx.x + 256 * q;
+      if (i < nu) bsh[i] = (double)v[q];
+    }
+  }
   __syncthreads();
   const double* A = ainv + ainv_off[p];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row1 = min(row0 + kCoarseRows, nu);
-  for (int r = row0 + w; r < row1; r += 4) {
-    double acc = 0.0;
-    const double* Ar = A + (int64_t)r * nu;
-    for (int j = lane; j < nu; j += 64) acc += Ar[j] * bsh[j];
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (lane == 0) u[umap[a + r]] = (T)acc;
+  const int r = row0 + w;  // one row per wave
+  if (r >= nu) return;
+  const double* Ar = A + (int64_t)r * nu;
+  double acc = 0.0;
+  for (int j0 = 0; j0 < nu; j0 += 8 * 64) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = j0 + lane + 64 * q;
+      av[q] = j < nu ? Ar[j] : 0.0;
+      bv[q] = j < nu ? bsh[j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += av[q] * bv[q];
   }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) u[umap[a + r]] = (T)acc;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -578,21 +825,35 @@ __global__ void __launch_bounds__(256) k_pack(const int4* __restrict__ tiles, in
                                               const double* __restrict__ uin,
                                               double* __restrict__ rhs, double* __restrict__ u) {
   constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+  constexpr int NK = TZ * TY * TX / 256;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntiles) return;
   const int4 t = tiles[tile];
   const int64_t base = (int64_t)t.x * g.npp;
   const int64_t nnu = D == 3 ? (int64_t)g.np * g.np * g.np : (int64_t)g.np * g.np;
   const int64_t ubase = (int64_t)t.x * nnu;
-  for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
+  int64_t P[NK];
+  bool ok[NK];
+  int8_t c[NK];
+  double fv[NK], gvv[NK], uv[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int i = threadIdx.x + 256 * k;
     const int x = t.y * TX + i % TX, y = t.z * TY + (i / TX) % TY;
     const int z = D == 3 ? t.w * TZ + i / (TX * TY) : 0;
-    if (!in_box(x, y, z, g.np, D)) continue;
-    const int64_t P = base + x + g.st[1] * y + g.st[2] * z;
-    const int64_t Q = ubase + x + (int64_t)g.np * (y + (int64_t)g.np * z);
-    const int8_t c = cls[P];
-    rhs[P] = c == 1 ? f[Q] : (c == 2 ? gv[Q] : 0.0);
-    if (uin) u[P] = c ? uin[Q] : 0.0;
+    ok[k] = in_box(x, y, z, g.np, D);
+    P[k] = base + x + g.st[1] * y + g.st[2] * z;
+    const int64_t Q = ok[k] ? ubase + x + (int64_t)g.np * (y + (int64_t)g.np * z) : ubase;
+    c[k] = cls[ok[k] ? P[k] : base];
+    fv[k] = f[Q];
+    gvv[k] = gv[Q];
+    uv[k] = uin ? uin[Q] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    if (!ok[k]) continue;
+    rhs[P[k]] = c[k] == 1 ? fv[k] : (c[k] == 2 ? gvv[k] : 0.0);
+    if (uin) u[P[k]] = c[k] ? uv[k] : 0.0;
   }
 }
 
@@ -610,27 +871,45 @@ __global__ void __launch_bounds__(256) k_unpack(int64_t total, Geo g, const int8
   const int y = (int)(q % g.np);
   const int z = (int)(q / g.np);
   const int64_t P = p * g.npp + x + g.st[1] * y + g.st[2] * z;
-  dst[i] = cls[P] ? src[P] : 0.0;
+  const int8_t c = cls[P];
+  const double v = src[P];
+  dst[i] = c ? v : 0.0;
 }
 
-// u64 += u32 at the unknowns (defect correction), and u32 reset for the next step
+// u64 += u32 at the unknowns (defect correction), and u32z (the buffer the next step's
+// FP32 cycles start from; it may be u32 itself) reset to zero
 template <int D>
 __global__ void __launch_bounds__(256) k_dc_update(const int4* __restrict__ tiles, int ntiles, Geo g,
                                                    const int8_t* __restrict__ cls,
-                                                   double* __restrict__ u64, float* __restrict__ u32) {
+                                                   double* __restrict__ u64, const float* u32,
+                                                   float* u32z) {
   constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+  constexpr int NK = TZ * TY * TX / 256;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntiles) return;
   const int4 t = tiles[tile];
   const int64_t base = (int64_t)t.x * g.npp;
-  for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
+  int64_t P[NK];
+  bool ok[NK];
+  int8_t c[NK];
+  double uv[NK];
+  float ev[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int i = threadIdx.x + 256 * k;
     const int x = t.y * TX + i % TX, y = t.z * TY + (i / TX) % TY;
     const int z = D == 3 ? t.w * TZ + i / (TX * TY) : 0;
-    if (!in_box(x, y, z, g.np, D)) continue;
-    const int64_t P = base + x + g.st[1] * y + g.st[2] * z;
-    if (cls[P] == 0) continue;
-    u64[P] += (double)u32[P];
-    u32[P] = 0.0f;
+    ok[k] = in_box(x, y, z, g.np, D);
+    P[k] = ok[k] ? base + x + g.st[1] * y + g.st[2] * z : base;
+    c[k] = cls[P[k]];
+    uv[k] = u64[P[k]];
+    ev[k] = u32[P[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    if (!ok[k] || c[k] == 0) continue;
+    u64[P[k]] = uv[k] + (double)ev[k];
+    u32z[P[k]] = 0.0f;
   }
 }
 
@@ -640,23 +919,28 @@ __global__ void __launch_bounds__(256) k_dc_update(const int4* __restrict__ tile
 static inline int tile_grid(int ntiles) { return (ntiles + 7) / 8 * 8; }
 static inline int lin_grid(int64_t n) { return (int)((n + 255) / 256); }
 
-template <int D, typename T>
-void launch_smooth(const DevLevel& L, T* u, const T* rhs, hipStream_t s) {
-  if (!L.ntiles) return;
-  const T h2 = (T)(L.g.h * L.g.h), inv2d = (T)(1.0 / (2.0 * D));
-  hipLaunchKernelGGL((k_smooth<D, T>), dim3(tile_grid(L.ntiles)), dim3(256), 0, s, L.tiles,
-                     L.ntiles, L.g, L.cls, u, rhs, h2, inv2d);
-}
+// per-problem boundary work that one workgroup sweeps within its barriers (levels without
+// relaxation chunks); larger boundaries take one launch per phase
+constexpr int kSingleWgBand = 8192;
+constexpr int kSingleWgExt = 24576;
 
 template <int D, typename T>
-void launch_band(const DevLevel& L, const mg_grid& G, T* u, const T* rhs, T* tmp, bool single_wg,
-                 int batch, hipStream_t s) {
-  const double inv_h = 1.0 / L.g.h, cNh = G.cN * L.g.h;
+size_t relax_lds(const DevLevel& L) {
+  return std::max(tile_lds<D, T>(), (size_t)L.bc_smax * sizeof(T));
+}
+
+size_t defect_lds(const DevLevel& L) { return (size_t)L.ec_smax * sizeof(double); }
+
+template <int D, typename T>
+static void launch_band(const DevLevel& L, const mg_grid& G, T* u, const T* rhs, T* tmp,
+                        int batch, hipStream_t s) {
+  const double cNh = G.cN * L.g.h;
   const T h2 = (T)(L.g.h * L.g.h), inv2d = (T)(1.0 / (2.0 * D));
-  if (single_wg) {
+  if (L.max_bandp + L.max_gp <= kSingleWgBand) {
     BandArgs<T> a;
     a.g = L.g;
     a.ghosts = L.ghosts;
+    a.gw = L.gw;
     a.ghost_off = L.ghost_off;
     a.red = L.red;
     a.black = L.black;
@@ -667,7 +951,6 @@ void launch_band(const DevLevel& L, const mg_grid& G, T* u, const T* rhs, T* tmp
     a.tmp = tmp;
     a.h2 = h2;
     a.inv2d = inv2d;
-    a.inv_h = inv_h;
     a.cD = G.cD;
     a.cNh = cNh;
     a.lambda = G.lambda;
@@ -677,7 +960,7 @@ void launch_band(const DevLevel& L, const mg_grid& G, T* u, const T* rhs, T* tmp
   auto ghosts = [&]() {
     if (!L.nghost) return;
     hipLaunchKernelGGL((k_ghost_new<D, T>), dim3(lin_grid(L.nghost)), dim3(256), 0, s, L.ghosts,
-                       L.nghost, L.g, (const T*)u, rhs, tmp, inv_h, G.cD, cNh);
+                       L.gw, L.nghost, L.g, (const T*)u, rhs, tmp, G.cD, cNh);
     hipLaunchKernelGGL((k_ghost_store<T>), dim3(lin_grid(L.nghost)), dim3(256), 0, s, L.ghosts,
                        L.nghost, (const T*)tmp, u);
   };
@@ -694,66 +977,34 @@ void launch_band(const DevLevel& L, const mg_grid& G, T* u, const T* rhs, T* tmp
 }
 
 template <int D, typename T>
-void launch_band_chunks(const DevLevel& L, const mg_grid& G, T* u, const T* rhs, T* out,
-                        hipStream_t s) {
-  if (!L.nchunks) return;
-  BandChunkArgs<T> a;
-  a.off = L.bc_off;
-  a.own = L.bc_own;
-  a.out_off = L.bc_out_off;
-  a.node = L.bc_node;
-  a.nbr = L.bc_nbr;
-  a.goff = L.bc_goff;
-  a.gidx = L.bc_gidx;
-  a.gent = L.bc_gent;
-  a.gsten = L.bc_gsten;
-  a.ops = L.bc_ops;
-  a.ops_off = L.bc_ops_off;
-  a.ghosts = L.ghosts;
-  a.u = u;
+void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, const T* rhs,
+                  T* tmp, int batch, hipStream_t s) {
+  RelaxArgs<T> a;
+  a.tiles = L.tiles;
+  a.ntiles = L.ntiles;
+  a.nbt = L.ntiles ? tile_grid(L.ntiles) : 0;
+  a.g = L.g;
+  a.rcls = L.rcls;
+  a.uin = uin;
+  a.uout = uout;
   a.rhs = rhs;
-  a.out = out;
-  a.smax = L.bc_smax;
-  a.gmax = L.bc_gmax;
-  a.opsmax = L.bc_opsmax;
-  a.phases = L.bc_phases;
   a.h2 = (T)(L.g.h * L.g.h);
   a.inv2d = (T)(1.0 / (2.0 * D));
-  a.inv_h = 1.0 / L.g.h;
-  a.cD = G.cD;
-  a.cNh = G.cN * L.g.h;
-  constexpr int K = Pow3<D>::value;
-  const size_t lds = (size_t)L.bc_gmax * (K + 1) * sizeof(double) +
-                     (size_t)(2 * L.bc_smax + L.bc_gmax) * sizeof(T) +
-                     ((size_t)L.bc_smax * 2 * D + (size_t)L.bc_gmax * (K + 1) + L.bc_opsmax) *
-                         sizeof(int16_t);
-  hipLaunchKernelGGL((k_band_chunk<D, T>), dim3(L.nchunks), dim3(256), lds, s, a);
-  hipLaunchKernelGGL((k_band_scatter<T>), dim3(lin_grid(L.bc_nown)), dim3(256), 0, s, L.bc_own_node,
-                     L.bc_nown, (const T*)out, u);
-}
-
-template <int D, typename T, typename TO>
-void launch_defect(const DevLevel& L, const T* u, const T* rhs, TO* r, uint64_t* norms,
-                   hipStream_t s) {
-  const int nbt = L.ntiles ? tile_grid(L.ntiles) : 0;
-  const int nb = nbt + (L.nghost ? lin_grid(L.nghost) : 0);
-  if (!nb) return;
-  hipLaunchKernelGGL((k_defect<D, T, TO>), dim3(nb), dim3(256), 0, s, L.tiles, L.ntiles, nbt,
-                     L.ghosts, L.nghost, L.g, L.cls, u, rhs, r, (T)(1.0 / (L.g.h * L.g.h)),
-                     1.0 / L.g.h, norms);
-}
-
-template <int D>
-void launch_rhs_norm(const DevLevel& L, const double* rhs, uint64_t* norms, hipStream_t s) {
-  if (L.ntiles)
-    hipLaunchKernelGGL((k_rhs_norm<D>), dim3(tile_grid(L.ntiles)), dim3(256), 0, s, L.tiles,
-                       L.ntiles, L.g, L.cls, rhs, norms);
+  a.write_all = L.nchunks ? 0 : 1;
+  a.nchunks = L.nchunks;
+  a.phases = L.bc_phases;
+  a.hdr = L.bc_hdr;
+  a.data = L.bc_data;
+  const int nb = a.nchunks + a.nbt;
+  const size_t lds = relax_lds<D, T>(L);
+  if (nb) hipLaunchKernelGGL((k_relax<D, T>), dim3(nb), dim3(256), lds, s, a);
+  if (!L.nchunks) launch_band<D, T>(L, G, uout, rhs, tmp, batch, s);
 }
 
 template <typename T>
-void launch_extend(const DevLevel& L, T* r, bool single_wg, int batch, hipStream_t s) {
+static void launch_extend(const DevLevel& L, T* r, int batch, hipStream_t s) {
   if (!L.next) return;
-  if (single_wg) {
+  if (L.max_extp <= kSingleWgExt) {
     hipLaunchKernelGGL((k_extend_wg<T>), dim3(batch), dim3(1024), 0, s, L.ext, L.dag_off,
                        L.dag_start, r);
     return;
@@ -766,12 +1017,38 @@ void launch_extend(const DevLevel& L, T* r, bool single_wg, int batch, hipStream
   }
 }
 
-template <typename T>
-void launch_extend_chunks(const DevLevel& L, T* r, hipStream_t s) {
-  if (!L.nechunks) return;
-  hipLaunchKernelGGL((k_extend_chunk<T>), dim3(L.nechunks), dim3(256), L.ec_smax * sizeof(double), s,
-                     L.ec_off, L.ec_own, L.ec_next, L.ec_node, L.ec_src, L.ec_wt, L.ec_ops, L.ec_lvl,
-                     L.ec_lvl_start, r);
+template <int D, typename T, typename TO>
+void launch_defect(const DevLevel& L, const T* u, const T* rhs, TO* r, uint64_t* norms,
+                   bool with_ext, int batch, hipStream_t s) {
+  DefectArgs<T, TO> a;
+  a.tiles = L.tiles;
+  a.ntiles = L.ntiles;
+  a.nbt = L.ntiles ? tile_grid(L.ntiles) : 0;
+  a.ghosts = L.ghosts;
+  a.gw = L.gw;
+  a.nghost = L.nghost;
+  a.g = L.g;
+  a.cls = L.cls;
+  a.u = u;
+  a.rhs = rhs;
+  a.r = r;
+  a.inv_h2 = (T)(1.0 / (L.g.h * L.g.h));
+  a.norms = norms;
+  a.nechunks = with_ext ? L.nechunks : 0;
+  a.hdr = L.ec_hdr;
+  a.data = L.ec_data;
+  const int nb = a.nechunks + a.nbt + (L.nghost ? lin_grid(L.nghost) : 0);
+  if (nb)
+    hipLaunchKernelGGL((k_defect<D, T, TO>), dim3(nb), dim3(256),
+                       a.nechunks ? defect_lds(L) : 0, s, a);
+  if (with_ext && !a.nechunks) launch_extend<TO>(L, r, batch, s);
+}
+
+template <int D>
+void launch_rhs_norm(const DevLevel& L, const double* rhs, uint64_t* norms, hipStream_t s) {
+  if (L.ntiles)
+    hipLaunchKernelGGL((k_rhs_norm<D>), dim3(tile_grid(L.ntiles)), dim3(256), 0, s, L.tiles,
+                       L.ntiles, L.g, L.cls, rhs, norms);
 }
 
 template <int D, typename T>
@@ -818,36 +1095,31 @@ void launch_unpack(const DevLevel& L, int batch, const double* src, double* dst,
 }
 
 template <int D>
-void launch_dc_update(const DevLevel& L, double* u64, float* u32, hipStream_t s) {
+void launch_dc_update(const DevLevel& L, double* u64, const float* u32, float* u32_zero,
+                      hipStream_t s) {
   if (L.ntiles)
     hipLaunchKernelGGL((k_dc_update<D>), dim3(tile_grid(L.ntiles)), dim3(256), 0, s, L.tiles,
-                       L.ntiles, L.g, L.cls, u64, u32);
+                       L.ntiles, L.g, L.cls, u64, u32, u32_zero);
 }
 
 #define GHOSTMG_INST(D, T)                                                                    \
-  template void launch_smooth<D, T>(const DevLevel&, T*, const T*, hipStream_t);             \
-  template void launch_band_chunks<D, T>(const DevLevel&, const mg_grid&, T*, const T*, T*,   \
-                                         hipStream_t);                                        \
-  template void launch_band<D, T>(const DevLevel&, const mg_grid&, T*, const T*, T*, bool, int, \
-                                  hipStream_t);                                               \
+  template void launch_relax<D, T>(const DevLevel&, const mg_grid&, const T*, T*, const T*, T*, \
+                                   int, hipStream_t);                                         \
   template void launch_defect<D, T, T>(const DevLevel&, const T*, const T*, T*, uint64_t*,    \
-                                       hipStream_t);                                          \
+                                       bool, int, hipStream_t);                               \
   template void launch_restrict<D, T>(const DevLevel&, const DevLevel&, const T*, T*, T*,     \
                                       hipStream_t);                                           \
-  template void launch_prolong<D, T>(const DevLevel&, const DevLevel&, const T*, T*, hipStream_t);
+  template void launch_prolong<D, T>(const DevLevel&, const DevLevel&, const T*, T*, hipStream_t); \
+  template size_t relax_lds<D, T>(const DevLevel&);
 
 GHOSTMG_INST(2, double)
 GHOSTMG_INST(2, float)
 GHOSTMG_INST(3, double)
 GHOSTMG_INST(3, float)
 template void launch_defect<2, double, float>(const DevLevel&, const double*, const double*, float*,
-                                              uint64_t*, hipStream_t);
+                                              uint64_t*, bool, int, hipStream_t);
 template void launch_defect<3, double, float>(const DevLevel&, const double*, const double*, float*,
-                                              uint64_t*, hipStream_t);
-template void launch_extend<double>(const DevLevel&, double*, bool, int, hipStream_t);
-template void launch_extend<float>(const DevLevel&, float*, bool, int, hipStream_t);
-template void launch_extend_chunks<double>(const DevLevel&, double*, hipStream_t);
-template void launch_extend_chunks<float>(const DevLevel&, float*, hipStream_t);
+                                              uint64_t*, bool, int, hipStream_t);
 template void launch_coarse<double>(const DevLevel&, const double*, double*, int, hipStream_t);
 template void launch_coarse<float>(const DevLevel&, const float*, float*, int, hipStream_t);
 template void launch_fill<double>(double*, int64_t, double, hipStream_t);
@@ -861,7 +1133,7 @@ template void launch_pack<3>(const DevLevel&, const double*, const double*, cons
                              double*, hipStream_t);
 template void launch_unpack<2>(const DevLevel&, int, const double*, double*, hipStream_t);
 template void launch_unpack<3>(const DevLevel&, int, const double*, double*, hipStream_t);
-template void launch_dc_update<2>(const DevLevel&, double*, float*, hipStream_t);
-template void launch_dc_update<3>(const DevLevel&, double*, float*, hipStream_t);
+template void launch_dc_update<2>(const DevLevel&, double*, const float*, float*, hipStream_t);
+template void launch_dc_update<3>(const DevLevel&, double*, const float*, float*, hipStream_t);
 
 }  // namespace ghostmg

@@ -689,12 +689,30 @@ int build_hierarchy(mg_handle_s* H, const double* phi) {
     }
     HF.gdag_off.push_back((int32_t)HF.ext_merged.size());
   }
+  // relaxation codes (band interior nodes marked 3) and the row weights of every ghost
+  const int K = D == 2 ? 9 : 27;
+  for (int l = 0; l <= L; ++l) {
+    HostLevel& HL = H->host[l];
+    HL.rcls = HL.cls;
+    for (int32_t v : HL.red) HL.rcls[v] = 3;
+    for (int32_t v : HL.black) HL.rcls[v] = 3;
+    HL.gw.assign(HL.ghosts.size() * K, 0.0);
+    const double inv_h = 1.0 / HL.g.h;
+    for (size_t i = 0; i < HL.ghosts.size(); ++i) {
+      double w[27];
+      const uint32_t used = D == 2 ? ghost_row<2>(HL.ghosts[i], inv_h, w)
+                                   : ghost_row<3>(HL.ghosts[i], inv_h, w);
+      for (int t = 0; t < K; ++t)
+        if (used >> t & 1u) HL.gw[i * K + t] = w[t];
+    }
+  }
   return MG_OK;
 }
 
 }  // namespace ghostmg
 
 namespace ghostmg {
+
 namespace {
 
 uint64_t spread_bits(uint64_t v, int D) {
@@ -703,111 +721,143 @@ uint64_t spread_bits(uint64_t v, int D) {
   return r;
 }
 
+void node_coords(const Geo& g, int D, int64_t v, int64_t* p, int j[3]) {
+  *p = v / g.npp;
+  int64_t loc = v - *p * g.npp;
+  const int64_t z = D == 3 ? loc / g.st[2] : 0;
+  loc -= z * g.st[2];
+  const int64_t y = loc / g.st[1];
+  j[0] = (int)(loc - y * g.st[1]);
+  j[1] = (int)y;
+  j[2] = (int)z;
+}
+
+// Morton order within a problem, problems in sequence
+uint64_t morton_key(const Geo& g, int D, int64_t v) {
+  int64_t p;
+  int j[3];
+  node_coords(g, D, v, &p, j);
+  return ((uint64_t)p << 60) | spread_bits(j[0], D) | (spread_bits(j[1], D) << 1) |
+         (spread_bits(j[2], D) << 2);
+}
+
+void pad_even(std::vector<int32_t>& v) {
+  if (v.size() & 1) v.push_back(0);
+}
+
+void put_doubles(std::vector<int32_t>& v, const std::vector<double>& d) {
+  const size_t w0 = v.size();
+  v.resize(w0 + 2 * d.size());
+  if (!d.empty()) std::memcpy(v.data() + w0, d.data(), d.size() * sizeof(double));
+}
+
+int32_t pack16(int a, int b) { return (int32_t)(((uint32_t)(uint16_t)a) | ((uint32_t)(uint16_t)b << 16)); }
+
+// initial runs of at most own_target consecutive (Morton-ordered) nodes of one problem
+std::vector<std::pair<size_t, size_t>> initial_runs(const std::vector<std::pair<uint64_t, int32_t>>& U,
+                                                    int own_target) {
+  std::vector<std::pair<size_t, size_t>> runs;
+  for (size_t a = 0; a < U.size();) {
+    const size_t b = std::min(U.size(), a + (size_t)own_target);
+    const uint64_t pa = U[a].first >> 60;
+    size_t e = a;
+    while (e < b && (U[e].first >> 60) == pa) ++e;
+    runs.push_back({a, e});
+    a = e;
+  }
+  std::reverse(runs.begin(), runs.end());
+  return runs;
+}
+
 }  // namespace
 
-// Partition the boundary band of level l into chunks for the LDS band kernel.  Phase 0
-// relaxes the ghosts; phases 3k-2, 3k-1, 3k (k = 1..lambda) the red band, the black band and
-// the ghosts.  For every chunk the set S of nodes is closed backwards over the phases: a node
-// whose value after phase t is needed, and which phase t updates, needs the values after
-// phase t-1 of every node it reads.  Returns false when chunks would exceed smax entries or
-// the redundant work would exceed `max_redundancy` (then the phases run as separate launches).
-bool build_band_chunks(mg_handle_s* H, int l, int own_target, int lds_budget,
-                       double max_redundancy) {
+// Relaxation chunks of level l.  A relaxation is P = 3 + 3 lambda phases: 0 red interior,
+// 1 black interior, 2 ghosts, then for k = 1..lambda phases 3k (red band), 3k + 1 (black
+// band), 3k + 2 (ghosts).  The nodes written by the boundary part (band and ghost nodes) are
+// split into Morton-ordered runs; each run's node set S is closed backwards over the phases:
+// a node whose value after phase t is needed, and which phase t updates, needs the values
+// after phase t - 1 of every node it reads.  A chunk with more than kChunkMaxEntries nodes or
+// kChunkThreads updated ghosts is split in two.  Returns false when a small run is still too
+// large, when the phases do not fit the 31 bits of a phase mask, or when the redundant work
+// exceeds max_redundancy times the owned nodes (the level then relaxes its boundary part
+// with one launch per phase).
+bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redundancy) {
   HostLevel& HL = H->host[l];
   const int D = H->dim, lambda = H->grid.lambda;
   const Geo& g = HL.g;
   const int K = D == 2 ? 9 : 27;
-  const int P = 1 + 3 * lambda;
+  const int P = 3 + 3 * lambda;
   const size_t nn = HL.cls.size();
-  const int elem = 8;  // LDS sized for FP64 values (the FP32 kernels need less)
-  // role of a node: 1 red, 2 black, 3 ghost, 0 other
+  HL.bc_hdr.clear();
+  HL.bc_data.clear();
+  HL.bc_nchunks = 0;
+  HL.bc_smax = 0;
+  HL.bc_entries = 0;
+  HL.bc_nown = 0;
+  if (P > 31) return false;
+  // role of a node: 1 red band, 2 black band, 3 ghost, 4 red interior off the band,
+  // 5 black interior off the band
   std::vector<int8_t> role(nn, 0);
   std::vector<int32_t> gidx(nn, -1);
-  for (int32_t v : HL.red) role[v] = 1;
-  for (int32_t v : HL.black) role[v] = 2;
+  for (size_t v = 0; v < nn; ++v) {
+    if (HL.cls[v] != 1) continue;
+    int64_t p;
+    int j[3];
+    node_coords(g, D, (int64_t)v, &p, j);
+    const bool black = (j[0] + j[1] + j[2]) & 1;
+    role[v] = HL.rcls[v] == 3 ? (black ? 2 : 1) : (black ? 5 : 4);
+  }
   for (size_t i = 0; i < HL.ghosts.size(); ++i) {
     role[HL.ghosts[i].node] = 3;
     gidx[HL.ghosts[i].node] = (int32_t)i;
   }
-  auto kind = [&](int p) { return p == 0 ? 3 : ((p - 1) % 3 == 0 ? 1 : ((p - 1) % 3 == 1 ? 2 : 3)); };
-  const double inv_h = 1.0 / g.h;
-  auto stencil = [&](int32_t v, std::vector<int32_t>& out) {
-    out.clear();
+  auto updates = [&](int r, int p) {
+    if (p == 0) return r == 1 || r == 4;
+    if (p == 1) return r == 2 || r == 5;
+    if (p % 3 == 2) return r == 3;
+    return p % 3 == 0 ? r == 1 : r == 2;
+  };
+  auto tap_node = [&](int32_t v, int t) {
     const GhostRec& r = HL.ghosts[gidx[v]];
-    double w[27];
-    const uint32_t used = D == 2 ? ghost_row<2>(r, inv_h, w) : ghost_row<3>(r, inv_h, w);
-    for (int t = 0; t < K; ++t)
-      out.push_back(used >> t & 1u ? (int32_t)(v + (D == 2 ? template_offset<2>(t, r.s, g.st)
-                                                            : template_offset<3>(t, r.s, g.st)))
-                                   : -1);
+    return (int32_t)(v + (D == 2 ? template_offset<2>(t, r.s, g.st) : template_offset<3>(t, r.s, g.st)));
   };
   auto reads = [&](int32_t v, std::vector<int32_t>& out) {
+    out.clear();
+    out.push_back(v);
     if (role[v] == 3) {
-      stencil(v, out);
-      out.erase(std::remove(out.begin(), out.end(), -1), out.end());
-      out.push_back(v);
+      for (int t = 0; t < K; ++t)
+        if (HL.gw[(size_t)gidx[v] * K + t] != 0.0) out.push_back(tap_node(v, t));
     } else {
-      out.clear();
-      out.push_back(v);
       for (int a = 0; a < D; ++a) {
         out.push_back((int32_t)(v - g.st[a]));
         out.push_back((int32_t)(v + g.st[a]));
       }
     }
   };
-  // updatable nodes in Morton order within each problem
   std::vector<std::pair<uint64_t, int32_t>> U;
-  for (size_t v = 0; v < nn; ++v) {
-    if (!role[v]) continue;
-    const int64_t p = (int64_t)v / g.npp;
-    int64_t loc = (int64_t)v - p * g.npp;
-    const int64_t z = D == 3 ? loc / g.st[2] : 0;
-    loc -= z * g.st[2];
-    const int64_t y = loc / g.st[1], x = loc - y * g.st[1];
-    const uint64_t key = spread_bits(x, D) | (spread_bits(y, D) << 1) | (spread_bits(z, D) << 2);
-    U.push_back({((uint64_t)p << 60) | key, (int32_t)v});
-  }
+  for (size_t v = 0; v < nn; ++v)
+    if (role[v] >= 1 && role[v] <= 3) U.push_back({morton_key(g, D, (int64_t)v), (int32_t)v});
   std::sort(U.begin(), U.end());
-  HL.bc_off.assign(1, 0);
-  HL.bc_out_off.assign(1, 0);
-  HL.bc_goff.assign(1, 0);
-  HL.bc_own.clear();
-  HL.bc_node.clear();
-  HL.bc_nbr.clear();
-  HL.bc_gent.clear();
-  HL.bc_gidx.clear();
-  HL.bc_gsten.clear();
-  HL.bc_ops.clear();
-  HL.bc_ops_off.clear();
-  HL.bc_own_node.clear();
-  HL.bc_smax = HL.bc_gmax = HL.bc_opsmax = 0;
   std::vector<int16_t> need(nn, -2);
   std::vector<int32_t> lid(nn, -1);
+  std::vector<char> owned(nn, 0);
   std::vector<int32_t> touched, rd;
-  int64_t total_s = 0;
-  std::vector<std::pair<size_t, size_t>> pending;
-  for (size_t a = 0; a < U.size();) {
-    size_t b = std::min(U.size(), a + (size_t)own_target);
-    const uint64_t pa = U[a].first >> 60;
-    size_t e = a;
-    while (e < b && (U[e].first >> 60) == pa) ++e;
-    pending.push_back({a, e});
-    a = e;
-  }
+  std::vector<std::pair<size_t, size_t>> pending = initial_runs(U, own_target);
+  const double cNh = H->grid.cN * g.h;
   while (!pending.empty()) {
     const auto [a, b] = pending.back();
     pending.pop_back();
     touched.clear();
     for (size_t i = a; i < b; ++i) {
       need[U[i].second] = (int16_t)(P - 1);
+      owned[U[i].second] = 1;
       touched.push_back(U[i].second);
     }
     for (int p = P - 1; p >= 0; --p) {
-      const int k = kind(p);
       const size_t nt = touched.size();
       for (size_t i = 0; i < nt; ++i) {
         const int32_t v = touched[i];
-        if (role[v] != k || need[v] < p) continue;
+        if (!updates(role[v], p) || need[v] < p) continue;
         reads(v, rd);
         for (int32_t w : rd) {
           if (need[w] == -2) touched.push_back(w);
@@ -815,101 +865,110 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, int lds_budget,
         }
       }
     }
+    // entries: the updated ghosts (one per thread), then every other node, by node index
+    std::sort(touched.begin(), touched.end(), [&](int32_t x, int32_t y) {
+      const bool gx = role[x] == 3 && need[x] >= 2, gy = role[y] == 3 && need[y] >= 2;
+      if (gx != gy) return gx;
+      return x < y;
+    });
     const int ns = (int)touched.size();
-    int ng_c = 0, nops = 0;
-    for (int32_t v : touched) {
-      if (role[v] == 3) ++ng_c;
-      for (int p = 0; p < P; ++p)
-        if (role[v] == kind(p) && need[v] >= p) ++nops;
+    int ng = 0;
+    while (ng < ns && role[touched[ng]] == 3 && need[touched[ng]] >= 2) ++ng;
+    bool ok = ns <= kChunkMaxEntries && ng <= kChunkThreads;
+    if (ok) {
+      for (int i = 0; i < ns; ++i) lid[touched[i]] = i;
+      for (int i = 0; i < ns && ok; ++i) {
+        const int32_t v = touched[i];
+        if (role[v] == 3 || need[v] < ((role[v] == 1 || role[v] == 4) ? 0 : 1)) continue;
+        for (int a2 = 0; a2 < D; ++a2)
+          if (lid[v - g.st[a2]] < 0 || lid[v + g.st[a2]] < 0) ok = false;
+      }
+      for (int j = 0; j < ng && ok; ++j)
+        for (int t = 0; t < K; ++t)
+          if (HL.gw[(size_t)gidx[touched[j]] * K + t] != 0.0 && lid[tap_node(touched[j], t)] < 0) ok = false;
     }
-    // LDS bytes of the chunk kernel: u, rhs; neighbour ids; ghost weights, constants,
-    // new values, stencil ids and entry ids; op lists
-    const int64_t lds = (int64_t)ns * (2 * elem + 4 * D) + (int64_t)ng_c * (8 * K + 8 + elem + 2 * K + 2) +
-                        (int64_t)nops * 2 + 64;
-    if (lds > lds_budget || ns > 32767) {
-      for (int32_t v : touched) need[v] = -2;
+    if (!ok) {
+      for (int32_t v : touched) {
+        need[v] = -2;
+        lid[v] = -1;
+        owned[v] = 0;
+      }
       if (b - a <= 16) return false;
       const size_t m = a + (b - a) / 2;
       pending.push_back({m, b});
       pending.push_back({a, m});
       continue;
     }
-    total_s += ns;
-    std::sort(touched.begin() + (b - a), touched.end());
-    for (int i = 0; i < ns; ++i) lid[touched[i]] = i;
-    std::vector<int16_t> slot(ns, -1);
-    int gs = 0;
-    for (int i = 0; i < ns; ++i) {
-      const int32_t v = touched[i];
-      HL.bc_node.push_back(v);
-      for (int a2 = 0; a2 < 2 * D; ++a2) {
-        int16_t q = -1;
-        if (role[v] == 1 || role[v] == 2) {
-          const int32_t w = (int32_t)(v + ((a2 & 1) ? g.st[a2 / 2] : -g.st[a2 / 2]));
-          q = (int16_t)lid[w];
-        }
-        HL.bc_nbr.push_back(q);
-      }
-      if (role[v] == 3) {
-        slot[i] = (int16_t)gs++;
-        HL.bc_gent.push_back((int16_t)i);
-        HL.bc_gidx.push_back(gidx[v]);
-        stencil(v, rd);
-        for (int t = 0; t < K; ++t) HL.bc_gsten.push_back(rd[t] >= 0 ? (int16_t)lid[rd[t]] : (int16_t)-1);
-      }
+    // per-chunk data: node, phase mask (bit 31: owned), interior neighbour pairs, ghost
+    // stencil ids and weights (transposed: tap-major), ghost constants
+    std::vector<int32_t>& Dv = HL.bc_data;
+    pad_even(Dv);
+    const int32_t off = (int32_t)Dv.size();
+    for (int32_t v : touched) Dv.push_back(v);
+    for (int32_t v : touched) {
+      uint32_t m = owned[v] ? 0x80000000u : 0u;
+      for (int p = 0; p < P; ++p)
+        if (updates(role[v], p) && need[v] >= p) m |= 1u << p;
+      Dv.push_back((int32_t)m);
     }
-    const int32_t ops0 = (int32_t)HL.bc_ops.size();
-    for (int p = 0; p < P; ++p) {
-      HL.bc_ops_off.push_back((int32_t)HL.bc_ops.size());
-      const int k = kind(p);
-      for (int i = 0; i < ns; ++i) {
-        const int32_t v = touched[i];
-        if (role[v] == k && need[v] >= p) HL.bc_ops.push_back(k == 3 ? slot[i] : (int16_t)i);
+    for (int32_t v : touched)
+      for (int a2 = 0; a2 < D; ++a2) {
+        const bool relaxed = role[v] != 3 && role[v] != 0;
+        const int lo = relaxed && lid[v - g.st[a2]] >= 0 ? lid[v - g.st[a2]] : 0;
+        const int hi = relaxed && lid[v + g.st[a2]] >= 0 ? lid[v + g.st[a2]] : 0;
+        Dv.push_back(pack16(lo, hi));
       }
-    }
-    HL.bc_ops_off.push_back((int32_t)HL.bc_ops.size());
-    HL.bc_own.push_back((int32_t)(b - a));
-    for (size_t i = a; i < b; ++i) HL.bc_own_node.push_back(U[i].second);
-    HL.bc_off.push_back((int32_t)HL.bc_node.size());
-    HL.bc_out_off.push_back((int32_t)HL.bc_own_node.size());
-    HL.bc_goff.push_back((int32_t)HL.bc_gent.size());
+    const int32_t gid_off = (int32_t)Dv.size();
+    for (int t = 0; t < K; ++t)
+      for (int j = 0; j < ng; ++j) {
+        const double w = HL.gw[(size_t)gidx[touched[j]] * K + t];
+        Dv.push_back(w != 0.0 ? lid[tap_node(touched[j], t)] : -1);
+      }
+    pad_even(Dv);
+    const int32_t gw_off = (int32_t)Dv.size();
+    std::vector<double> wv;
+    for (int t = 0; t < K; ++t)
+      for (int j = 0; j < ng; ++j) wv.push_back(HL.gw[(size_t)gidx[touched[j]] * K + t]);
+    put_doubles(Dv, wv);
+    const int32_t gc_off = (int32_t)Dv.size();
+    wv.clear();
+    for (int j = 0; j < ng; ++j) wv.push_back(HL.ghosts[gidx[touched[j]]].type ? H->grid.cD : cNh);
+    put_doubles(Dv, wv);
+    const int32_t hdr[kBandHdr] = {ns, ng, off, gid_off, gw_off, gc_off, 0, 0};
+    HL.bc_hdr.insert(HL.bc_hdr.end(), hdr, hdr + kBandHdr);
+    ++HL.bc_nchunks;
+    HL.bc_entries += ns;
+    HL.bc_nown += (int)(b - a);
     HL.bc_smax = std::max(HL.bc_smax, ns);
-    HL.bc_gmax = std::max(HL.bc_gmax, gs);
-    HL.bc_opsmax = std::max(HL.bc_opsmax, (int)HL.bc_ops.size() - ops0);
     for (int32_t v : touched) {
       need[v] = -2;
       lid[v] = -1;
+      owned[v] = 0;
     }
   }
-  if (!U.empty() && (double)total_s > max_redundancy * (double)U.size()) return false;
-  // the kernel lays out LDS for the largest chunk of each kind at once
-  const int64_t lds_max = (int64_t)HL.bc_smax * (2 * elem + 4 * D) +
-                          (int64_t)HL.bc_gmax * (8 * K + 8 + elem + 2 * K + 2) +
-                          (int64_t)HL.bc_opsmax * 2 + 64;
-  return lds_max <= 150 * 1024;
+  if (!U.empty() && (double)HL.bc_entries > max_redundancy * (double)U.size()) return false;
+  return true;
 }
 
-// Partition the extension nodes of level l into chunks for the LDS extension kernel: each
-// chunk owns a Morton-ordered run of extension nodes and carries every extension node they
-// depend on (transitively through their upwind sources), then the ghost defects read.
-bool build_ext_chunks(mg_handle_s* H, int l, int own_target, int max_entries) {
+// Extension chunks of level l: each chunk owns a Morton-ordered run of extension nodes,
+// carries every extension node they depend on (transitively through their upwind sources)
+// and the ghost nodes among the sources, whose defects it evaluates itself.  A chunk with
+// more than kChunkMaxEntries entries or kChunkThreads ghost sources is split in two;
+// returns false when a single node is still too large.
+bool build_ext_chunks(mg_handle_s* H, int l, int own_target) {
   HostLevel& HL = H->host[l];
   const int D = H->dim;
   const Geo& g = HL.g;
-  HL.ec_off.assign(1, 0);
-  HL.ec_lvl_start.assign(1, 0);
-  HL.ec_own.clear();
-  HL.ec_next.clear();
-  HL.ec_node.clear();
-  HL.ec_src.clear();
-  HL.ec_wt.clear();
-  HL.ec_ops.clear();
-  HL.ec_lvl.clear();
+  const int K = D == 2 ? 9 : 27;
+  HL.ec_hdr.clear();
+  HL.ec_data.clear();
+  HL.ec_nchunks = 0;
   HL.ec_smax = 0;
   if (HL.ext.empty()) return true;
   const size_t nn = HL.cls.size();
-  std::vector<int32_t> eid(nn, -1);
+  std::vector<int32_t> eid(nn, -1), gidx(nn, -1);
   for (size_t i = 0; i < HL.ext.size(); ++i) eid[HL.ext[i].node] = (int32_t)i;
+  for (size_t i = 0; i < HL.ghosts.size(); ++i) gidx[HL.ghosts[i].node] = (int32_t)i;
   // DAG level of each extension record (ghost sources are level 0)
   std::vector<int> dag(HL.ext.size(), 1);
   for (size_t i = 0; i < HL.ext.size(); ++i)  // records are stored in DAG order per problem
@@ -918,28 +977,20 @@ bool build_ext_chunks(mg_handle_s* H, int l, int own_target, int max_entries) {
       if (q >= 0 && eid[q] >= 0) dag[i] = std::max(dag[i], dag[eid[q]] + 1);
     }
   std::vector<std::pair<uint64_t, int32_t>> U;
-  for (size_t i = 0; i < HL.ext.size(); ++i) {
-    const int32_t v = HL.ext[i].node;
-    const int64_t p = (int64_t)v / g.npp;
-    int64_t loc = (int64_t)v - p * g.npp;
-    const int64_t z = D == 3 ? loc / g.st[2] : 0;
-    loc -= z * g.st[2];
-    const int64_t y = loc / g.st[1], x = loc - y * g.st[1];
-    const uint64_t key = spread_bits(x, D) | (spread_bits(y, D) << 1) | (spread_bits(z, D) << 2);
-    U.push_back({((uint64_t)p << 60) | key, (int32_t)i});
-  }
+  for (size_t i = 0; i < HL.ext.size(); ++i)
+    U.push_back({morton_key(g, D, HL.ext[i].node), (int32_t)i});
   std::sort(U.begin(), U.end());
+  std::vector<std::pair<size_t, size_t>> pending = initial_runs(U, own_target);
   std::vector<int32_t> lid(nn, -1);
-  for (size_t a = 0; a < U.size();) {
-    const uint64_t pa = U[a].first >> 60;
-    size_t b = a;
-    while (b < U.size() && b < a + (size_t)own_target && (U[b].first >> 60) == pa) ++b;
-    // closure over extension sources
+  std::vector<char> in(HL.ext.size(), 0), own(HL.ext.size(), 0);
+  while (!pending.empty()) {
+    const auto [a, b] = pending.back();
+    pending.pop_back();
     std::vector<int32_t> ext_e, ghosts_e;
-    std::vector<char> in(HL.ext.size(), 0);
     for (size_t i = a; i < b; ++i) {
       ext_e.push_back(U[i].second);
       in[U[i].second] = 1;
+      own[U[i].second] = 1;
     }
     for (size_t k = 0; k < ext_e.size(); ++k)
       for (int c = 0; c < 3; ++c) {
@@ -948,53 +999,84 @@ bool build_ext_chunks(mg_handle_s* H, int l, int own_target, int max_entries) {
         in[eid[q]] = 1;
         ext_e.push_back(eid[q]);
       }
+    bool ok = true;
     for (int32_t e : ext_e)
       for (int c = 0; c < 3; ++c) {
         const int32_t q = HL.ext[e].src[c];
         if (q >= 0 && eid[q] < 0 && lid[q] == -1) {
+          if (gidx[q] < 0) ok = false;  // a source that is neither extension node nor ghost
           lid[q] = -2;
           ghosts_e.push_back(q);
         }
       }
-    const int ns = (int)(ext_e.size() + ghosts_e.size());
-    if (ns > max_entries) {
+    const int ne = (int)ext_e.size(), ngs = (int)ghosts_e.size(), nt = ne + ngs;
+    ok = ok && nt <= kChunkMaxEntries && ngs <= kChunkThreads;
+    if (!ok) {
+      for (int32_t e : ext_e) in[e] = own[e] = 0;
       for (int32_t q : ghosts_e) lid[q] = -1;
-      return false;
+      if (b - a <= 1) return false;
+      const size_t m = a + (b - a) / 2;
+      pending.push_back({m, b});
+      pending.push_back({a, m});
+      continue;
     }
+    // entries: ghost sources (one per thread), then the extension nodes
     int k = 0;
-    for (int32_t e : ext_e) lid[HL.ext[e].node] = k++;
     for (int32_t q : ghosts_e) lid[q] = k++;
+    for (int32_t e : ext_e) lid[HL.ext[e].node] = k++;
+    int nlvl = 0;
+    for (int32_t e : ext_e) nlvl = std::max(nlvl, dag[e]);
+    std::vector<int32_t>& Dv = HL.ec_data;
+    pad_even(Dv);
+    const int32_t off = (int32_t)Dv.size();
+    for (int32_t q : ghosts_e) Dv.push_back(q);
+    for (int32_t e : ext_e) Dv.push_back(HL.ext[e].node);
+    for (int j = 0; j < ngs; ++j) Dv.push_back(0);
+    for (int32_t e : ext_e) Dv.push_back((int32_t)((uint32_t)dag[e] | (own[e] ? 0x80000000u : 0u)));
+    const int32_t src_off = (int32_t)Dv.size();
+    for (int j = 0; j < ngs; ++j) {
+      Dv.push_back(pack16(-1, -1));
+      Dv.push_back(pack16(-1, -1));
+    }
     for (int32_t e : ext_e) {
       const ExtRec& r = HL.ext[e];
-      HL.ec_node.push_back(r.node);
-      for (int c = 0; c < 3; ++c) {
-        HL.ec_src.push_back(r.src[c] >= 0 ? (int16_t)lid[r.src[c]] : (int16_t)-1);
-        HL.ec_wt.push_back(r.wt[c]);
+      int s[3];
+      for (int c = 0; c < 3; ++c) s[c] = r.src[c] >= 0 ? lid[r.src[c]] : -1;
+      Dv.push_back(pack16(s[0], s[1]));
+      Dv.push_back(pack16(s[2], -1));
+    }
+    pad_even(Dv);
+    const int32_t w_off = (int32_t)Dv.size();
+    std::vector<double> wv;
+    for (int c = 0; c < 3; ++c) {
+      for (int j = 0; j < ngs; ++j) wv.push_back(0.0);
+      for (int32_t e : ext_e) wv.push_back(HL.ext[e].wt[c]);
+    }
+    put_doubles(Dv, wv);
+    const int32_t gn_off = (int32_t)Dv.size();
+    for (int t = 0; t < K; ++t)
+      for (int32_t q : ghosts_e) {
+        // taps of zero weight are skipped by the kernel; they name the ghost itself
+        const GhostRec& r = HL.ghosts[gidx[q]];
+        const bool used = HL.gw[(size_t)gidx[q] * K + t] != 0.0;
+        const int64_t o = D == 2 ? template_offset<2>(t, r.s, g.st) : template_offset<3>(t, r.s, g.st);
+        Dv.push_back(used ? (int32_t)(q + o) : q);
       }
+    pad_even(Dv);
+    const int32_t gw_off = (int32_t)Dv.size();
+    wv.clear();
+    for (int t = 0; t < K; ++t)
+      for (int32_t q : ghosts_e) wv.push_back(HL.gw[(size_t)gidx[q] * K + t]);
+    put_doubles(Dv, wv);
+    const int32_t hdr[kExtHdr] = {nt, ngs, off, src_off, w_off, gn_off, gw_off, nlvl};
+    HL.ec_hdr.insert(HL.ec_hdr.end(), hdr, hdr + kExtHdr);
+    ++HL.ec_nchunks;
+    HL.ec_smax = std::max(HL.ec_smax, nt);
+    for (int32_t e : ext_e) {
+      lid[HL.ext[e].node] = -1;
+      in[e] = own[e] = 0;
     }
-    for (int32_t q : ghosts_e) {
-      HL.ec_node.push_back(q);
-      for (int c = 0; c < 3; ++c) {
-        HL.ec_src.push_back(-1);
-        HL.ec_wt.push_back(0.0);
-      }
-    }
-    int maxd = 0;
-    for (int32_t e : ext_e) maxd = std::max(maxd, dag[e]);
-    for (int d = 1; d <= maxd; ++d) {
-      HL.ec_lvl.push_back((int32_t)HL.ec_ops.size());
-      for (size_t i = 0; i < ext_e.size(); ++i)
-        if (dag[ext_e[i]] == d) HL.ec_ops.push_back((int16_t)i);
-    }
-    HL.ec_lvl.push_back((int32_t)HL.ec_ops.size());
-    HL.ec_lvl_start.push_back((int32_t)HL.ec_lvl.size());
-    HL.ec_own.push_back((int32_t)(b - a));
-    HL.ec_next.push_back((int32_t)ext_e.size());
-    HL.ec_off.push_back((int32_t)HL.ec_node.size());
-    HL.ec_smax = std::max(HL.ec_smax, ns);
-    for (int32_t e : ext_e) lid[HL.ext[e].node] = -1;
     for (int32_t q : ghosts_e) lid[q] = -1;
-    a = b;
   }
   return true;
 }

@@ -3,9 +3,11 @@
 Builds the flower workload (the headline benchmark problem), then launches the requested
 kernel `--reps` times at one level through mg_time_kernel, and finally copies a buffer of
 known size `--copy-mb` MiB with torch (three launches), whose FETCH_SIZE / WRITE_SIZE
-readings calibrate the counters (bytes read = bytes written = the buffer size).
+readings calibrate the counters (bytes read = bytes written = the buffer size).  The
+default 2 GiB is far larger than the 256 MiB last-level cache, so the copy's reads all
+reach HBM.
 
-  python -m paper_1111_0983_amd.kernel_probe --kernel smooth --level 0
+  python -m paper_1111_0983_amd.kernel_probe --kernel relax --level 0
 """
 from __future__ import annotations
 
@@ -16,13 +18,13 @@ import sys
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--kernel", default="smooth",
-                    choices=["smooth", "defect", "restrict", "prolong", "band"])
+    ap.add_argument("--kernel", default="relax",
+                    choices=["relax", "defect", "restrict", "prolong", "residual"])
     ap.add_argument("--level", type=int, default=0)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--fp32", action="store_true")
-    ap.add_argument("--copy-mb", type=int, default=256)
+    ap.add_argument("--copy-mb", type=int, default=2048)
     args = ap.parse_args(argv)
 
     import numpy as np

@@ -7,8 +7,10 @@
 * evaluate(): cycles and time to the tolerance with the zero guess (FP64 cycles) against
   the learned guess (FP32 cycles inside FP64 defect correction).
 
-Samples whose domain comes within 3 coarsest mesh widths of the box, or which have a
-connected component without a Dirichlet ghost (a singular problem), are rejected.
+Samples whose domain comes within 3 coarsest mesh widths of the box, which have a connected
+component without a Dirichlet ghost (a singular problem), or whose cycle reduces the defect
+by less than a factor 0.8 per cycle (a boundary the coarsest grid does not resolve) are
+rejected.
 """
 from __future__ import annotations
 
@@ -43,10 +45,11 @@ def _components_ok(cls: np.ndarray, ghosts: dict, n: int) -> bool:
     return bool(has[1:].all())
 
 
-def _diverging(solver, f, n, B):
-    """Problems whose defect grows between cycles 5 and 10 from the zero guess: the
-    coarsest grid does not resolve their boundary well enough for the cycle to converge
-    (the paper's caveat on too-coarse grids), so they are rejected like singular ones."""
+def _slow(solver, f, n, B, rho_max: float = 0.8):
+    """Problems whose mean defect reduction per cycle between cycles 5 and 10 from the zero
+    guess is worse than rho_max (including growth): the coarsest grid does not resolve their
+    boundary well enough for the cycle to converge at a useful rate (the paper's caveat on
+    too-coarse grids), so they are rejected like singular ones."""
     cls = torch.from_numpy(np.concatenate([solver.classes(i) for i in range(B)])).to(f.device)
     fi = torch.where(cls == 1, f, torch.zeros_like(f)).contiguous()
     g = torch.zeros_like(fi)
@@ -55,7 +58,7 @@ def _diverging(solver, f, n, B):
     r5 = solver.residual(fi, g, u).max(axis=1)
     solver.cycles(fi, g, u, 5)
     r10 = solver.residual(fi, g, u).max(axis=1)
-    return [i for i in range(B) if not (r10[i] < r5[i])]
+    return [i for i in range(B) if not (r10[i] < r5[i] * rho_max ** 5)]
 
 
 def build_batch(seeds, n=N_FINE, nc=N_COARSE, device="cuda:0", precision=gm.MG_FP64,
@@ -97,7 +100,7 @@ def build_batch(seeds, n=N_FINE, nc=N_COARSE, device="cuda:0", precision=gm.MG_F
         bad = [i for i in range(len(probs))
                if not _components_ok(solver.classes(i), solver.ghosts(i), n)]
         if not bad and screen:
-            bad = _diverging(solver, torch.cat(fs), n, len(probs))
+            bad = _slow(solver, torch.cat(fs), n, len(probs))
         if bad:
             solver.close()
             probs = [p for i, p in enumerate(probs) if i not in bad]
@@ -136,14 +139,22 @@ def generate(n_samples: int, seed0: int = 0, batch: int = 64, device="cuda:0", l
         if solver is None:
             continue
         u = torch.zeros_like(f)
-        # training targets: 1e-8 is far below what the network can reproduce
-        info = solver.solve(f, g, u, tol=1e-8)
+        # training targets: 1e-8 is far below what the network can reproduce; a batch whose
+        # slowest problem misses it within the cycle budget keeps the problems that reached it
+        info = solver.solve(f, g, u, tol=1e-8, check=False)
+        if info["status"] not in (gm.MG_OK, gm.MG_ENOCONV):
+            raise gm.GhostMGError(info["status"], "mg_solve")
+        B0 = len(probs)
+        norms = solver.residual(f, g, u).max(axis=1)
+        fmax = f.reshape(B0, -1).abs().max(dim=1).values.cpu().numpy()
+        good = torch.from_numpy(norms <= 1e-8 * np.maximum(fmax, 1e-300)).to(f.device)
         x, scale, (B, H, W) = cnn.features(solver, LEVEL, f, g)
         tgt, mask = cnn.target(solver, LEVEL, u, scale)
-        xs.append(x.reshape(B, H * W * 8))
-        ts.append(tgt.reshape(B, H * W))
-        ms.append(mask.reshape(B, H * W))
-        total += B
+        rejected += int(B0 - good.sum().item())
+        xs.append(x.reshape(B, H * W * 8)[good])
+        ts.append(tgt.reshape(B, H * W)[good])
+        ms.append(mask.reshape(B, H * W)[good])
+        total += int(good.sum().item())
         solver.close()
         if log and len(xs) % 10 == 1:
             log(f"[learned] generated {total}/{n_samples} ({rejected} rejected, "
