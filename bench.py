@@ -79,6 +79,38 @@ def bench_torus(args, gm, pr, geo, np, torch, dev, step):
     return out
 
 
+def bench_learned(args, torch):
+    """The learned-guess workload: ellipse-union problems at 512^2 (evaluation seeds), each
+    solved on its own to 1e-10: FP64 and FP32-DC from the zero guess, FP32-DC and FP64 from
+    the guess of the committed network (inference included)."""
+    import numpy as np
+
+    from paper_1111_0983_amd import cnn, learned
+    from workloads import ellipses as el
+
+    w = os.path.join(ROOT, "paper_1111_0983_amd", "weights", "guessnet.npz")
+    net = cnn.GuessNet(seed=0)
+    net.load(dict(np.load(w)))
+    seeds, s = [], 1_000_000
+    while len(seeds) < args.learned_problems:
+        p = el.draw(s)
+        if el.accept(el.nodal_phi(p, learned.N_FINE, device="cuda:0"), learned.N_FINE,
+                     3.0 * 2.0 / learned.N_COARSE):
+            seeds.append(s)
+        s += 1
+    s64, f, g, probs = learned.build_batch(seeds)
+    s64.close()
+    pp = learned.evaluate_each(net, probs, f, g, reps=2)
+    out = {f"learned_{k}": round(v, 3) for k, v in pp.items() if k.endswith(("_mean", "_median"))}
+    out["learned_problems"] = len(probs)
+    out["learned_workload"] = "ellipse unions 512^2, Nc=32, per-problem solves to 1e-10"
+    log(f"[bench] learned guess: zero FP64 {pp['zero64_cycles_mean']:.1f} cycles "
+        f"{pp['zero64_ms_mean']:.2f} ms, zero FP32-DC {pp['zero_dc_cycles_mean']:.1f} cycles "
+        f"{pp['zero_dc_ms_mean']:.2f} ms, learned FP32-DC {pp['learned_dc_cycles_mean']:.1f} "
+        f"cycles {pp['learned_dc_ms_mean']:.2f} ms (means over {len(probs)} problems)")
+    return out
+
+
 def step_fg(solver, uu, f, g):
     uu.zero_()
     return solver.solve(f, g, uu, tol=1e-10)
@@ -94,6 +126,8 @@ def main():
     ap.add_argument("--no-dc", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--n3d", type=int, default=256)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-problems", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -186,6 +220,8 @@ def main():
 
     if not args.no_3d:
         extra.update(bench_torus(args, gm, pr, geo, np, torch, dev, step))
+    if not args.no_learned:
+        extra.update(bench_learned(args, torch))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -89,6 +89,11 @@ typedef struct {
   int history_len;
 } mg_stats;
 
+/* A caller-defined partition of the boundary (Sec. 2.1: the boundary is the union of
+ * Gamma_D and Gamma_N): returns nonzero when the boundary point B (3 coordinates, unused
+ * ones 0) of problem `problem` belongs to Gamma_D, 0 when it belongs to Gamma_N. */
+typedef int (*mg_bc_fn)(int problem, const double* B, void* ctx);
+
 /* Fill *g with the paper's constants (lambda 5, delta 3h, mu dt 0.9 / 0.9 * 2h/(3 sqrt d)),
  * V(2,1), FP64, batch 1, box [-1, 1]^dim. */
 int mg_grid_default(mg_grid* g, int dim, int n, int n_coarse);
@@ -97,6 +102,13 @@ int mg_grid_default(mg_grid* g, int dim, int n, int n_coarse);
  * nodes).  phi: batch * (n+1)^dim values, host or device memory, negative inside.
  * bc: batch rules (host memory).  On success *out receives a new handle. */
 int mg_setup(const double* phi, const mg_bc_rule* bc, const mg_grid* grid, mg_handle_t* out);
+
+/* mg_setup with the Dirichlet/Neumann partition given by fn instead of half-space rules.
+ * fn is called on the host during this call only (never afterwards), with ctx, at the
+ * closest boundary point of every ghost and of every outside node of the defect extension,
+ * on every level; it must be deterministic.  MG_EINVAL when fn is NULL. */
+int mg_setup_partition(const double* phi, mg_bc_fn fn, void* ctx, const mg_grid* grid,
+                       mg_handle_t* out);
 
 /* Order all later work of the handle on this hipStream_t (NULL = null stream). */
 int mg_set_stream(mg_handle_t h, void* hip_stream);

@@ -46,6 +46,9 @@ class _Rule(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double * 3), ("c", ctypes.c_double), ("strict", ctypes.c_int)]
 
 
+# partition of the boundary: nonzero when the boundary point B (3 doubles) is on Gamma_D
+_BC_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+
 _lib = None
 
 
@@ -59,6 +62,9 @@ def _load():
         _lib.orc_setup.restype = vp
         _lib.orc_setup.argtypes = [dp, ctypes.POINTER(_Rule), ctypes.POINTER(_Grid),
                                    ctypes.POINTER(ctypes.c_int)]
+        _lib.orc_setup_fn.restype = vp
+        _lib.orc_setup_fn.argtypes = [dp, _BC_FN, vp, ctypes.POINTER(_Grid),
+                                      ctypes.POINTER(ctypes.c_int)]
         _lib.orc_free.argtypes = [vp]
         _lib.orc_free.restype = None
         for name in ("orc_num_levels",):
@@ -108,7 +114,10 @@ class OracleError(RuntimeError):
 class Oracle:
     """Ghost-cell multigrid hierarchy built from nodal phi on the finest grid."""
 
-    def __init__(self, phi: np.ndarray, grid: dict, rule: dict):
+    def __init__(self, phi: np.ndarray, grid: dict, rule: dict | None = None,
+                 partition=None):
+        """rule: half-space Dirichlet rule {a, c, strict}; partition: instead of a rule, a
+        Python function of the boundary point B (3 floats) returning True on Gamma_D."""
         lib = _load()
         self.grid = dict(grid)
         self.dim = int(grid["dim"])
@@ -117,12 +126,17 @@ class Oracle:
         if self.phi.size != (self.n + 1) ** self.dim:
             raise ValueError("phi has the wrong size")
         g = _Grid(**{k: grid[k] for k in _Grid._fields_names})
-        a = list(rule.get("a", (0.0, 0.0, 0.0))) + [0.0] * 3
-        r = _Rule((ctypes.c_double * 3)(*a[:3]), float(rule.get("c", 0.0)),
-                  int(rule.get("strict", 1)))
         err = ctypes.c_int(0)
-        self._h = lib.orc_setup(_p(self.phi), ctypes.byref(r), ctypes.byref(g),
-                                ctypes.byref(err))
+        if partition is not None:
+            cb = _BC_FN(lambda B, ctx: int(bool(partition((B[0], B[1], B[2])))))
+            self._h = lib.orc_setup_fn(_p(self.phi), cb, None, ctypes.byref(g),
+                                       ctypes.byref(err))
+        else:
+            a = list(rule.get("a", (0.0, 0.0, 0.0))) + [0.0] * 3
+            r = _Rule((ctypes.c_double * 3)(*a[:3]), float(rule.get("c", 0.0)),
+                      int(rule.get("strict", 1)))
+            self._h = lib.orc_setup(_p(self.phi), ctypes.byref(r), ctypes.byref(g),
+                                    ctypes.byref(err))
         if not self._h:
             raise OracleError(err.value, "orc_setup")
         self.nlev = lib.orc_num_levels(self._h)

@@ -100,13 +100,30 @@ typedef struct {
   double *u, *rhs, *r, *tmp;
 } olev;
 
+/* A general partition of the boundary (Sec. 2.1): nonzero when B lies on Gamma_D. */
+typedef int (*orc_bc_fn)(const double* B, void* ctx);
+
 typedef struct {
   orc_grid g;
   orc_bc_rule bc;
+  orc_bc_fn bc_fn; /* when set, replaces the half-space rule */
+  void* bc_ctx;
   int L; /* index of the coarsest level */
   int K; /* 3^dim */
   olev lev[ORC_MAXLEV];
 } ohandle;
+
+/* Gamma_D or Gamma_N at the boundary point B (dimension d; unused coordinates are 0). */
+static int on_dirichlet(const ohandle* H, int d, const double* B) {
+  if (H->bc_fn) {
+    double b[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) b[a] = B[a];
+    return H->bc_fn(b, H->bc_ctx) != 0;
+  }
+  double v = H->bc.c;
+  for (int a = 0; a < d; ++a) v += H->bc.a[a] * B[a];
+  return H->bc.strict ? (v > 0.0) : (v >= 0.0);
+}
 
 /* ------------------------------------------------------------------------------------ */
 /* indexing helpers                                                                     */
@@ -299,9 +316,7 @@ static int build_ghosts(ohandle* H, int l) {
       L->gB[3 * q + a] = B[a];
     }
     /* boundary-condition type at B */
-    double v = H->bc.c;
-    for (int a = 0; a < d; ++a) v += H->bc.a[a] * B[a];
-    int dir = H->bc.strict ? (v > 0.0) : (v >= 0.0);
+    int dir = on_dirichlet(H, d, B);
     L->gtype[q] = (int8_t)dir;
     L->gc[q] = dir ? H->g.cD : H->g.cN * L->h;
 
@@ -562,9 +577,9 @@ static int build_extension(ohandle* H, int l) {
     }
     {
       /* label: boundary-condition type at the closest boundary point of P */
-      double v = H->bc.c;
-      for (int a = 0; a < d; ++a) v += H->bc.a[a] * (coord(H, F, j[a]) - gr[a] / nrm * F->phi[P]);
-      F->lab[P] = (int8_t)(H->bc.strict ? (v > 0.0) : (v >= 0.0));
+      double Bp[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < d; ++a) Bp[a] = coord(H, F, j[a]) - gr[a] / nrm * F->phi[P];
+      F->lab[P] = (int8_t)on_dirichlet(H, d, Bp);
     }
     int nsame = 0;
     for (int pass = 0; pass < 2; ++pass) {
@@ -764,10 +779,27 @@ void orc_free(void* h) {
   free(H);
 }
 
+static void* setup_impl(const double* phi, const orc_bc_rule* bc, orc_bc_fn fn, void* ctx,
+                        const orc_grid* g, int* err);
+
 /* phi: node values on the finest grid, (n+1)^dim, x fastest. */
 void* orc_setup(const double* phi, const orc_bc_rule* bc, const orc_grid* g, int* err) {
   *err = ORC_EINVAL;
-  if (!phi || !bc || !g) return NULL;
+  if (!bc) return NULL;
+  return setup_impl(phi, bc, NULL, NULL, g, err);
+}
+
+/* orc_setup with the partition of the boundary given by fn (called during setup only). */
+void* orc_setup_fn(const double* phi, orc_bc_fn fn, void* ctx, const orc_grid* g, int* err) {
+  *err = ORC_EINVAL;
+  if (!fn) return NULL;
+  return setup_impl(phi, NULL, fn, ctx, g, err);
+}
+
+static void* setup_impl(const double* phi, const orc_bc_rule* bc, orc_bc_fn fn, void* ctx,
+                        const orc_grid* g, int* err) {
+  *err = ORC_EINVAL;
+  if (!phi || !g) return NULL;
   if (g->dim < 1 || g->dim > 3 || g->n < 2 || g->n_coarse < 2 || g->hi <= g->lo) return NULL;
   if (g->gamma < 1 || g->gamma > 2 || g->nu1 < 0 || g->nu2 < 0 || g->lambda < 0) return NULL;
   int L = 0;
@@ -784,7 +816,9 @@ void* orc_setup(const double* phi, const orc_bc_rule* bc, const orc_grid* g, int
     return NULL;
   }
   H->g = *g;
-  H->bc = *bc;
+  if (bc) H->bc = *bc;
+  H->bc_fn = fn;
+  H->bc_ctx = ctx;
   H->L = L;
   H->K = 1;
   for (int a = 0; a < g->dim; ++a) H->K *= 3;

@@ -99,13 +99,19 @@ def loss(pred, target, mask, with_grad=True, stream=None):
 class GuessNet:
     """FP32 master weights [cout][3][3][cin] with Adam state; BF16 packed operands."""
 
+    # the network predicts gain * u / s: u / s is O(1e-2) for these problems
+    GAIN = 32.0
+
     def __init__(self, seed: int = 0, device="cuda:0", layers=LAYERS):
         self.layers = layers
         self.device = torch.device(device)
+        self.gain = self.GAIN
         g = torch.Generator().manual_seed(seed)
         self.w, self.b = [], []
-        for cin, cout, _ in layers:
-            std = (2.0 / (9 * cin)) ** 0.5
+        for i, (cin, cout, _) in enumerate(layers):
+            # He initialisation; the output layer starts at zero, so the first updates do
+            # not have to undo a random O(1) output (which drives hidden units dead)
+            std = (2.0 / (9 * cin)) ** 0.5 if i < len(layers) - 1 else 0.0
             self.w.append((torch.randn(cout * 9 * cin, generator=g) * std).to(self.device))
             self.b.append(torch.zeros(cout, device=self.device))
         self.m = [torch.zeros_like(t) for t in self.w + self.b]
@@ -155,13 +161,14 @@ class GuessNet:
         self.repack()
 
     def state(self) -> dict:
-        d = {}
+        d = {"gain": np.float64(self.gain)}
         for i, (w, b) in enumerate(zip(self.w, self.b)):
             d[f"w{i}"] = w.detach().cpu().numpy()
             d[f"b{i}"] = b.detach().cpu().numpy()
         return d
 
     def load(self, d: dict):
+        self.gain = float(d["gain"]) if "gain" in d else self.GAIN
         for i in range(len(self.layers)):
             self.w[i].copy_(torch.from_numpy(np.asarray(d[f"w{i}"])))
             self.b[i].copy_(torch.from_numpy(np.asarray(d[f"b{i}"])))
@@ -196,4 +203,4 @@ def guess(net: GuessNet, solver: gm.Solver, level: int, f, g, u0):
     """Write the network's initial iterate for (f, g) into u0 (finest grid)."""
     x, scale, (B, H, W) = features(solver, level, f, g)
     pred = net.forward(x, B, H, W)
-    apply(solver, level, pred, scale, u0)
+    apply(solver, level, pred, scale / net.gain, u0)

@@ -139,34 +139,48 @@ struct Arr<float> {
   static float* tmp(DevLevel& L) { return L.gtmp32; }
 };
 
-// One relaxation of level l from its current iterate buffer into the other one.
+// One relaxation of level l from its current iterate buffer into the other one; with
+// prolong, it starts from the iterate plus the interpolated correction of level l + 1; with
+// restrict_, from zero with the right-hand side restricted from level l - 1's defect.
 template <int D, typename T>
-void relax(mg_handle_s* H, int l, hipStream_t s) {
+void relax(mg_handle_s* H, int l, hipStream_t s, bool prolong = false, bool restrict_ = false) {
   DevLevel& L = H->dev[l];
   const int c = H->cur[l];
+  DevLevel* C = prolong ? &H->dev[l + 1] : nullptr;
+  DevLevel* F = restrict_ ? &H->dev[l - 1] : nullptr;
   launch_relax<D, T>(L, H->grid, Arr<T>::u(L, c), Arr<T>::u(L, 1 - c), Arr<T>::rhs(L),
-                     Arr<T>::tmp(L), H->batch, s);
+                     Arr<T>::tmp(L), H->batch, s, C, C ? Arr<T>::u(*C, H->cur[l + 1]) : nullptr,
+                     F, F ? Arr<T>::r(*F) : nullptr);
   H->cur[l] = 1 - c;
 }
 
 // The cycle of Sec. 2.4 from level l (TGCS recursion, gamma = 1 V, 2 W).  H->cur tracks,
-// while the launches are recorded, which buffer holds each level's iterate.
+// while the launches are recorded, which buffer holds each level's iterate.  fresh: the
+// level has just been entered from level l - 1, whose defect still has to be restricted
+// (Sec. 2.5) into this level's right-hand side, with a zero iterate; the first relaxation
+// does that as it stages its values.
 template <int D, typename T>
-void cycle(mg_handle_s* H, int l, hipStream_t s) {
+void cycle(mg_handle_s* H, int l, hipStream_t s, bool fresh = false) {
   DevLevel& L = H->dev[l];
+  if (fresh && (l == H->L || H->grid.nu1 == 0)) {
+    DevLevel& F = H->dev[l - 1];
+    launch_restrict<D, T>(F, L, Arr<T>::r(F), Arr<T>::rhs(L), Arr<T>::u(L, H->cur[l]), s);
+    fresh = false;
+  }
   if (l == H->L) {
     launch_coarse<T>(L, Arr<T>::rhs(L), Arr<T>::u(L, H->cur[l]), H->batch, s);
     return;
   }
-  for (int i = 0; i < H->grid.nu1; ++i) relax<D, T>(H, l, s);
+  for (int i = 0; i < H->grid.nu1; ++i) relax<D, T>(H, l, s, false, fresh && i == 0);
   launch_defect<D, T, T>(L, Arr<T>::u(L, H->cur[l]), Arr<T>::rhs(L), Arr<T>::r(L), nullptr, true,
                          H->batch, s);
   DevLevel& C = H->dev[l + 1];
   H->cur[l + 1] = 0;
-  launch_restrict<D, T>(L, C, Arr<T>::r(L), Arr<T>::rhs(C), Arr<T>::u(C, 0), s);
-  for (int k = 0; k < H->grid.gamma; ++k) cycle<D, T>(H, l + 1, s);
-  launch_prolong<D, T>(L, C, Arr<T>::u(C, H->cur[l + 1]), Arr<T>::u(L, H->cur[l]), s);
-  for (int i = 0; i < H->grid.nu2; ++i) relax<D, T>(H, l, s);
+  for (int k = 0; k < H->grid.gamma; ++k) cycle<D, T>(H, l + 1, s, k == 0);
+  // interpolation + correction, taken by the first post-relaxation as it stages its values
+  if (H->grid.nu2 == 0)
+    launch_prolong<D, T>(L, C, Arr<T>::u(C, H->cur[l + 1]), Arr<T>::u(L, H->cur[l]), s);
+  for (int i = 0; i < H->grid.nu2; ++i) relax<D, T>(H, l, s, i == 0);
 }
 
 template <int D>
@@ -184,12 +198,12 @@ void dc_defect(mg_handle_s* H, hipStream_t s) {
   launch_defect<D, double, float>(L, L.u64[0], L.rhs64, L.rhs32, H->norms, false, H->batch, s);
 }
 
-// one FP64 cycle from finest buffer c, then the defect norm of its result
+// one FP64 cycle from finest buffer c, then (with norm) the defect norm of its result
 template <int D>
-void record_cycle(mg_handle_s* H, int c, hipStream_t s) {
+void record_cycle(mg_handle_s* H, int c, bool norm, hipStream_t s) {
   H->cur[0] = c;
   cycle<D, double>(H, 0, s);
-  defect_norm64<D>(H, H->cur[0], s);
+  if (norm) defect_norm64<D>(H, H->cur[0], s);
 }
 
 // inner_cycles FP32 cycles on the correction (from zero in FP32 buffer 0), u64 += the
@@ -205,16 +219,17 @@ void record_dc(mg_handle_s* H, hipStream_t s) {
 
 hipStream_t stream_of(mg_handle_s* H) { return H->stream; }
 
-// Record one cycle (FP64 from finest buffer c, or one defect-correction step) into a graph.
-int capture(mg_handle_s* H, bool dc, int c, hipGraphExec_t* out) {
+// Record one cycle (FP64 from finest buffer c, with or without the defect norm, or one
+// defect-correction step) into a graph.
+int capture(mg_handle_s* H, bool dc, int c, bool norm, hipGraphExec_t* out) {
   if (*out) return MG_OK;
   hipStream_t s = stream_of(H);
   hipGraph_t graph;
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   if (H->dim == 2)
-    dc ? record_dc<2>(H, s) : record_cycle<2>(H, c, s);
+    dc ? record_dc<2>(H, s) : record_cycle<2>(H, c, norm, s);
   else
-    dc ? record_dc<3>(H, s) : record_cycle<3>(H, c, s);
+    dc ? record_dc<3>(H, s) : record_cycle<3>(H, c, norm, s);
   if (hipStreamEndCapture(s, &graph) != hipSuccess) return MG_EHIP;
   const hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
   hipGraphDestroy(graph);
@@ -278,10 +293,11 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
   rc = H->dim == 2 ? pack<2>(H, f, g, u) : pack<3>(H, f, g, u);
   if (rc) return rc;
   if (dc) {
-    if ((rc = capture(H, true, 0, &H->graph_dc))) return rc;
+    if ((rc = capture(H, true, 0, true, &H->graph_dc))) return rc;
   } else {
-    if ((rc = capture(H, false, 0, &H->graph_cycle[0]))) return rc;
-    if (after_cycle(H, 0) == 1 && (rc = capture(H, false, 1, &H->graph_cycle[1]))) return rc;
+    for (int c = 0; c < (after_cycle(H, 0) == 1 ? 2 : 1); ++c)
+      for (int nm = 0; nm < 2; ++nm)
+        if ((rc = capture(H, false, c, nm == 1, &H->graph_cycle[c][nm]))) return rc;
   }
   // defect of the initial guess
   if (H->dim == 2)
@@ -326,7 +342,8 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
       if (dc) {
         HIP_TRY(hipGraphLaunch(H->graph_dc, s));
       } else {
-        HIP_TRY(hipGraphLaunch(H->graph_cycle[H->cur0], s));
+        // only the last cycle before a read-back needs its defect norm
+        HIP_TRY(hipGraphLaunch(H->graph_cycle[H->cur0][i == k - 1 ? 1 : 0], s));
         H->cur0 = after_cycle(H, H->cur0);
       }
     }
@@ -421,8 +438,31 @@ int mg_grid_default(mg_grid* g, int dim, int n, int n_coarse) {
   return MG_OK;
 }
 
+namespace {
+
+int setup_impl(const double* phi, const mg_bc_rule* bc, mg_bc_fn fn, void* ctx,
+               const mg_grid* grid, mg_handle_t* out);
+
+}  // namespace
+
 int mg_setup(const double* phi, const mg_bc_rule* bc, const mg_grid* grid, mg_handle_t* out) {
-  if (!phi || !bc || !grid || !out) return MG_EINVAL;
+  if (!bc) return MG_EINVAL;
+  return setup_impl(phi, bc, nullptr, nullptr, grid, out);
+}
+
+int mg_setup_partition(const double* phi, mg_bc_fn fn, void* ctx, const mg_grid* grid,
+                       mg_handle_t* out) {
+  if (!fn) return MG_EINVAL;
+  return setup_impl(phi, nullptr, fn, ctx, grid, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+int setup_impl(const double* phi, const mg_bc_rule* bc, mg_bc_fn fn, void* ctx,
+               const mg_grid* grid, mg_handle_t* out) {
+  if (!phi || !grid || !out) return MG_EINVAL;
   *out = nullptr;
   const mg_grid& G = *grid;
   if ((G.dim != 2 && G.dim != 3) || G.n < 4 || G.n_coarse < 2 || !(G.hi > G.lo) || G.batch < 1 ||
@@ -445,7 +485,9 @@ int mg_setup(const double* phi, const mg_bc_rule* bc, const mg_grid* grid, mg_ha
   mg_handle_s* H = new (std::nothrow) mg_handle_s();
   if (!H) return MG_ENOMEM;
   H->grid = G;
-  H->bc.assign(bc, bc + G.batch);
+  if (bc) H->bc.assign(bc, bc + G.batch);
+  H->bc_fn = fn;
+  H->bc_ctx = ctx;
   H->L = L;
   H->batch = G.batch;
   H->dim = G.dim;
@@ -502,9 +544,15 @@ int mg_setup(const double* phi, const mg_bc_rule* bc, const mg_grid* grid, mg_ha
     mg_free(H);
     return rc;
   }
+  H->bc_fn = nullptr;  // the caller's function is not called after setup
+  H->bc_ctx = nullptr;
   *out = H;
   return MG_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int mg_set_stream(mg_handle_t h, void* hip_stream) {
   if (!h) return MG_EINVAL;
@@ -651,8 +699,9 @@ int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_m
 
 void mg_free(mg_handle_t h) {
   if (!h) return;
-  for (int k = 0; k < 2; ++k)
-    if (h->graph_cycle[k]) (void)hipGraphExecDestroy(h->graph_cycle[k]);
+  for (int c = 0; c < 2; ++c)
+    for (int k = 0; k < 2; ++k)
+      if (h->graph_cycle[c][k]) (void)hipGraphExecDestroy(h->graph_cycle[c][k]);
   if (h->graph_dc) (void)hipGraphExecDestroy(h->graph_dc);
   for (DevLevel& L : h->dev) free_level(L);
   if (h->norms) (void)hipFree(h->norms);

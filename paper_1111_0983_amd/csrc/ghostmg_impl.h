@@ -78,7 +78,11 @@ struct HostLevel {
   // Entry e of a chunk belongs to thread e % kChunkThreads; the updated ghosts come first
   // (at most one per thread).  Chunk c: header bc_hdr[c * kBandHdr ..] = {entries, updated
   // ghosts, offsets into bc_data of: the per-entry arrays, the ghost stencil ids, the ghost
-  // weights and the ghost constants, 0, 0}.  Per-entry arrays (int32 words): node index;
+  // weights, the ghost constants, the interpolation candidates (-1 on the coarsest level)
+  // and the restriction data (-1 on the finest level)}: per entry 2^D coarse
+  // node indices of its interpolation candidates (-1: absent or no unknown; the weight
+  // exponent is in mask bits 28-29), and 2 words: the fine node index of (2x, 2y, 2z) and
+  // the restriction code.  Per-entry arrays (int32 words): node index;
   // phase mask (bit p: updated in phase p; bit 31: owned, written to the output); D words of
   // (minus, plus) int16 local neighbour ids per axis.  Per ghost (tap-major, ghost fastest):
   // Pow3<D> local stencil ids (-1 for taps of zero weight) and FP64 weights; one FP64
@@ -141,6 +145,8 @@ struct DevLevel {
 struct mg_handle_s {
   mg_grid grid;
   std::vector<mg_bc_rule> bc;
+  mg_bc_fn bc_fn = nullptr;            // caller's partition (setup only), else the rules
+  void* bc_ctx = nullptr;
   int L = 0;                          // index of the coarsest level
   int batch = 1;
   int dim = 2;
@@ -152,9 +158,10 @@ struct mg_handle_s {
   double* norms_host = nullptr;       // pinned host mirror
   double* r0 = nullptr;               // per problem ||(f_h, g_h)||_inf (host)
   std::vector<double> history;
-  // one FP64 cycle + defect norm, starting from finest iterate buffer 0 or 1 (a cycle
-  // with an odd number of finest relaxations ends in the other buffer)
-  hipGraphExec_t graph_cycle[2] = {nullptr, nullptr};
+  // one FP64 cycle starting from finest iterate buffer 0 or 1 (a cycle with an odd number
+  // of finest relaxations ends in the other buffer), [c][1] followed by the defect norm of
+  // its result, [c][0] without it
+  hipGraphExec_t graph_cycle[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   hipGraphExec_t graph_dc = nullptr;     // one defect-correction step + defect norm
   int cur0 = 0;                          // buffer holding the finest FP64 iterate
   int cur[ghostmg::kMaxLevels] = {};     // per level current buffer while recording

@@ -36,6 +36,18 @@ struct RelaxArgs {
   int write_all;  // tiles also write band interior and ghost nodes (levels without chunks)
   int nchunks, phases;
   const int32_t *hdr, *data;
+  // interpolation of the coarse correction uc (level with geometry gc and classes clsc)
+  // applied to uin before relaxing (prolong != 0)
+  int prolong;
+  Geo gc;
+  const T* uc;
+  const int8_t* clsc;
+  // restriction of the finer level's defect rf (geometry gf) with this level's codes, into
+  // rhs_w (the level's right-hand side), fused into a relaxation that starts from zero
+  const T* rf;
+  Geo gf;
+  const uint8_t* rcode;
+  T* rhs_w;
 };
 
 // Defect r = rhs - A u: workgroups [0, nechunks) run the extension chunks (Eq. (exp)),
@@ -59,10 +71,14 @@ struct DefectArgs {
 };
 
 // One complete relaxation (Sec. 2.4 step 1 with the boundary sweeps of Sec. 3.2): reads
-// uin, writes every unknown of uout (uin != uout).
+// uin, writes every unknown of uout (uin != uout).  With C, the relaxation starts from
+// uin + the interpolation of the coarse correction uc (Sec. 2.6.1, step 6 of the cycle).
+// With F, the relaxation starts from zero, with the right-hand side restricted from the
+// finer level F's defect rf (Sec. 2.5, steps 4-5 of the cycle), which it also stores in rhs.
 template <int D, typename T>
 void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, const T* rhs,
-                  T* tmp, int batch, hipStream_t s);
+                  T* tmp, int batch, hipStream_t s, const DevLevel* C = nullptr,
+                  const T* uc = nullptr, const DevLevel* F = nullptr, const T* rf = nullptr);
 // Defect of u into r; with_ext also extends it outside Omega_h (Eq. (exp)).  norms, when
 // given, receives the per-problem infinity norms (no extension then).
 template <int D, typename T, typename TO>

@@ -73,22 +73,145 @@ __device__ __forceinline__ double ghost_apply(const GhostRec& r, const double* _
 }
 
 // ---------------------------------------------------------------------------------------
-// relaxation, interior tiles: red-black sweep of Eq. (jac2d), one tile per workgroup
+// interpolation of the coarse error (Sec. 2.6.1): multilinear weights renormalised over the
+// coarse nodes that carry an unknown; shared by the interpolation kernel and the relaxation
+// that takes the correction while it stages its values
 // ---------------------------------------------------------------------------------------
-// The tile and a ring of two nodes of uin are staged in LDS.  Red interior nodes of tile +
-// ring one are relaxed first (they read only black, ghost or outside values, which this
-// pass leaves unchanged), then the black interior nodes of the tile (which read the fresh
-// red values).  The result is the global red sweep followed by the global black sweep;
-// every workgroup writes its own tile of uout: the interior nodes off the boundary band
-// (the relaxation chunks write the band and the ghosts), or, with write_all, every unknown.
+// Candidate m (bit q: upper neighbour along axis q) of fine node j: its coarse coordinates
+// and weight (0 when the candidate does not exist: an even coordinate has one neighbour).
 template <int D, typename T>
-__device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
+__device__ __forceinline__ T prolong_candidate(const int j[3], int m, int jc[3]) {
+  T w = 1;
+  bool skip = false;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const int bit = (m >> q) & 1;
+    if ((j[q] & 1) == 0) {
+      if (bit) skip = true;
+      jc[q] = j[q] >> 1;
+    } else {
+      jc[q] = bit ? (j[q] + 1) >> 1 : (j[q] - 1) >> 1;
+      w *= (T)0.5;
+    }
+  }
+  if (D == 2) jc[2] = 0;
+  return skip ? (T)0 : w;
+}
+
+// u + sum_m w_m e_m / sum_m w_m over the candidates with an unknown (u unchanged if none)
+template <int D, typename T>
+__device__ __forceinline__ T prolong_correct(T u, const T* w, const int8_t* cc, const T* ec) {
+  T num = 0, den = 0;
+#pragma unroll
+  for (int m = 0; m < (1 << D); ++m) {
+    if (w[m] == (T)0 || cc[m] == 0) continue;
+    num += w[m] * ec[m];
+    den += w[m];
+  }
+  return den > (T)0 ? u + num / den : u;
+}
+
+// coarse patch under a tile and its 2-node ring (fused interpolation)
+template <int D>
+struct CPatch {
+  static constexpr int X = Tile<D>::X / 2 + 3, Y = Tile<D>::Y / 2 + 3;
+  static constexpr int Z = D == 3 ? Tile<D>::Z / 2 + 3 : 1;
+};
+
+constexpr int kRelaxPlain = 0, kRelaxProlong = 1, kRelaxRestrict = 2;
+
+// bytes of the tile workgroup's auxiliary LDS area in each mode
+template <int D, typename T, int MODE>
+constexpr size_t tile_aux_bytes() {
+  constexpr int FX = Tile<D>::X + 2, FY = Tile<D>::Y + 2, FZ = D == 3 ? Tile<D>::Z + 2 : 1;
+  constexpr size_t coarse = (size_t)CPatch<D>::X * CPatch<D>::Y * CPatch<D>::Z * sizeof(T);
+  constexpr size_t fine = MODE == kRelaxRestrict
+                              ? (size_t)(2 * FX + 1) * (2 * FY + 1) * sizeof(T) + FZ * FY * FX
+                              : 0;
+  return ((coarse > fine ? coarse : fine) + 15) / 16 * 16;
+}
+
+template <int D, typename T, int MODE>
+constexpr size_t tile_lds() {
   constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
   constexpr int UX = TX + 4, UY = TY + 4, UZ = D == 3 ? TZ + 4 : 1;
   constexpr int FX = TX + 2, FY = TY + 2, FZ = D == 3 ? TZ + 2 : 1;
+  constexpr int NCN = CPatch<D>::X * CPatch<D>::Y * CPatch<D>::Z;
+  return (size_t)(UZ * UY * UX + FZ * FY * FX) * sizeof(T) + tile_aux_bytes<D, T, MODE>() +
+         (size_t)UZ * UY * UX + NCN;
+}
+
+// ---------------------------------------------------------------------------------------
+// restriction of one coarse unknown (Sec. 2.5): the fine defect over the node's box with
+// the tensor weights of Eqs. (restI), (restL), (restR).  rr holds the 3^D fine values around
+// (2x, 2y, 2z) with x slowest; values outside the box get weight 0, which leaves the sum
+// over the box, taken in the same order, unchanged.
+// ---------------------------------------------------------------------------------------
+template <int D, typename T>
+__device__ __forceinline__ T restrict_box(uint8_t c, const T* rr) {
+  constexpr int KT = Pow3<D>::value;
+  const int lx = (c & 1) ? -1 : 0, hx = (c & 2) ? 1 : 0;
+  const int ly = (c & 4) ? -1 : 0, hy = (c & 8) ? 1 : 0;
+  const int lz = D == 3 && (c & 16) ? -1 : 0, hz = D == 3 && (c & 32) ? 1 : 0;
+  T s = 0;
+#pragma unroll
+  for (int q = 0; q < KT; ++q) {
+    const int kx = q / (D == 3 ? 9 : 3) - 1, ky = (q / (D == 3 ? 3 : 1)) % 3 - 1;
+    const int kz = D == 3 ? q % 3 - 1 : 0;
+    const bool inbox = kx >= lx && kx <= hx && ky >= ly && ky <= hy && kz >= lz && kz <= hz;
+    const T w = inbox ? (T)(restrict_w1d(lx, hx, kx) * restrict_w1d(ly, hy, ky) *
+                            (D == 3 ? restrict_w1d(lz, hz, kz) : 1.0))
+                      : (T)0;
+    s += w * rr[q];
+  }
+  return s;
+}
+
+// the 3^D fine values restrict_box reads for the coarse node whose (2x, 2y, 2z) is fine node
+// F0; taps outside the node's box (which may lie outside the grid) read F0 itself
+template <int D, typename T>
+__device__ __forceinline__ void restrict_gather(const T* __restrict__ rf, int64_t F0,
+                                                const Geo& gf, uint8_t c, T* rr) {
+  constexpr int KT = Pow3<D>::value;
+  const int lx = (c & 1) ? -1 : 0, hx = (c & 2) ? 1 : 0;
+  const int ly = (c & 4) ? -1 : 0, hy = (c & 8) ? 1 : 0;
+  const int lz = D == 3 && (c & 16) ? -1 : 0, hz = D == 3 && (c & 32) ? 1 : 0;
+#pragma unroll
+  for (int q = 0; q < KT; ++q) {
+    const int kx = q / (D == 3 ? 9 : 3) - 1, ky = (q / (D == 3 ? 3 : 1)) % 3 - 1;
+    const int kz = D == 3 ? q % 3 - 1 : 0;
+    const bool inbox = kx >= lx && kx <= hx && ky >= ly && ky <= hy && kz >= lz && kz <= hz;
+    rr[q] = rf[inbox ? F0 + kx + gf.st[1] * ky + gf.st[2] * kz : F0];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// relaxation, interior tiles: red-black sweep of Eq. (jac2d), one tile per workgroup
+// ---------------------------------------------------------------------------------------
+// The tile and a ring of two nodes of uin are staged in LDS (with the coarse correction
+// added when the relaxation follows an interpolation).  Red interior nodes of tile + ring
+// one are relaxed first (they read only black, ghost or outside values, which this pass
+// leaves unchanged), then the black interior nodes of the tile (which read the fresh red
+// values).  The result is the global red sweep followed by the global black sweep; every
+// workgroup writes its own tile of uout: the interior nodes off the boundary band (the
+// relaxation chunks write the band and the ghosts), or, with write_all, every unknown.
+template <int D, typename T, int MODE>
+__device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
+  constexpr bool PROLONG = MODE == kRelaxProlong, RESTRICT = MODE == kRelaxRestrict;
+  static_assert(!RESTRICT || D == 2, "the restriction is fused in 2D only");
+  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+  constexpr int UX = TX + 4, UY = TY + 4, UZ = D == 3 ? TZ + 4 : 1;
+  constexpr int FX = TX + 2, FY = TY + 2, FZ = D == 3 ? TZ + 2 : 1;
+  constexpr int CX = CPatch<D>::X, CY = CPatch<D>::Y, CZ = CPatch<D>::Z;
+  constexpr int NUN = UZ * UY * UX, NFN = FZ * FY * FX, NCN = CZ * CY * CX;
   T* su = (T*)lds;
-  T* sf = su + UZ * UY * UX;
-  int8_t* sc = (int8_t*)(sf + FZ * FY * FX);
+  T* sf = su + NUN;
+  // auxiliary area: the coarse patch (interpolation) or the fine defect patch and the
+  // restriction codes (restriction)
+  unsigned char* aux = (unsigned char*)(sf + NFN);
+  T* sce = (T*)aux;
+  int8_t* sc = (int8_t*)(aux + tile_aux_bytes<D, T, MODE>());  // codes of the U region
+  int8_t* scc = sc + NUN;                                      // coarse classes of the patch
   const int tile = xcd_tile(tb, a.nbt);
   if (tile >= a.ntiles) return;
   const Geo& g = a.g;
@@ -97,50 +220,152 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   const int ox = t.y * TX, oy = t.z * TY, oz = t.w * TZ;
   // every global load of the thread is issued before the first is used: positions outside
   // the box read the tile's first node and are replaced by zero afterwards
-  constexpr int NU = (UZ * UY * UX + 255) / 256, NF = (FZ * FY * FX + 255) / 256;
-  T uv[NU], fv[NF];
-  int8_t cv[NF];
-  bool uok[NU], fok[NF];
+  constexpr int NU = (NUN + 255) / 256, NF = (NFN + 255) / 256, NC = (NCN + 255) / 256;
+  // fine defect patch under the F region (restriction): fine x from 2 ox - 3 to 2 ox + 2 TX + 1
+  constexpr int RX = 2 * FX + 1, RY = 2 * FY + 1, NRN = RESTRICT ? RX * RY : 1;
+  constexpr int NR = (NRN + 255) / 256;
+  T uv[NU], fv[NF], ev[NC], rpv[NR];
+  int8_t cv[NU], fc[NF], ccv[NC];
+  uint8_t rcv[NF];
+  bool uok[NU], fok[NF], cok[NC];
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
     const int i = threadIdx.x + 256 * k;
     const int x = i % UX, y = (i / UX) % UY, z = i / (UX * UY);
     const int gx = ox + x - 2, gy = oy + y - 2, gz = D == 3 ? oz + z - 2 : 0;
-    uok[k] = i < UZ * UY * UX && in_box(gx, gy, gz, g.np, D);
-    uv[k] = a.uin[uok[k] ? base + gx + g.st[1] * gy + g.st[2] * gz : base];
+    uok[k] = i < NUN && in_box(gx, gy, gz, g.np, D);
+    const int64_t gi = uok[k] ? base + gx + g.st[1] * gy + g.st[2] * gz : base;
+    uv[k] = RESTRICT ? (T)0 : a.uin[gi];
+    cv[k] = a.rcls[gi];
   }
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
     const int i = threadIdx.x + 256 * k;
     const int x = i % FX, y = (i / FX) % FY, z = i / (FX * FY);
     const int gx = ox + x - 1, gy = oy + y - 1, gz = D == 3 ? oz + z - 1 : 0;
-    fok[k] = i < FZ * FY * FX && in_box(gx, gy, gz, g.np, D);
+    fok[k] = i < NFN && in_box(gx, gy, gz, g.np, D);
     const int64_t gi = fok[k] ? base + gx + g.st[1] * gy + g.st[2] * gz : base;
-    cv[k] = a.rcls[gi];
-    fv[k] = a.rhs[gi];
+    fc[k] = a.rcls[gi];
+    if constexpr (RESTRICT)
+      rcv[k] = a.rcode[gi];
+    else
+      fv[k] = a.rhs[gi];
+  }
+  if constexpr (RESTRICT) {
+    const int64_t fbase = (int64_t)t.x * a.gf.npp;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      const int fx = 2 * ox - 3 + i % RX, fy = 2 * oy - 3 + i / RX;
+      const bool ok = i < NRN && in_box(fx, fy, 0, a.gf.np, 2);
+      rpv[k] = a.rf[ok ? fbase + fx + a.gf.st[1] * fy : fbase];
+    }
+  }
+  if constexpr (PROLONG) {
+    const Geo& gc = a.gc;
+    const int64_t cbase = (int64_t)t.x * gc.npp;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      const int x = i % CX, y = (i / CX) % CY, z = i / (CX * CY);
+      const int cx = ox / 2 - 1 + x, cy = oy / 2 - 1 + y, cz = D == 3 ? oz / 2 - 1 + z : 0;
+      cok[k] = i < NCN && in_box(cx, cy, cz, gc.np, D);
+      const int64_t ci = cok[k] ? cbase + cx + gc.st[1] * cy + gc.st[2] * cz : cbase;
+      ev[k] = a.uc[ci];
+      ccv[k] = a.clsc[ci];
+    }
   }
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
     const int i = threadIdx.x + 256 * k;
-    if (i < UZ * UY * UX) su[i] = uok[k] ? uv[k] : (T)0;
+    if (i < NUN) {
+      su[i] = uok[k] ? uv[k] : (T)0;
+      sc[i] = uok[k] ? cv[k] : (int8_t)0;
+    }
   }
+  if constexpr (RESTRICT) {
+    // restricted right-hand side at every unknown of the F region, from the staged patch
+    T* sr = (T*)aux;
+    uint8_t* src = (uint8_t*)(sr + NRN);
 #pragma unroll
-  for (int k = 0; k < NF; ++k) {
-    const int i = threadIdx.x + 256 * k;
-    if (i < FZ * FY * FX) {
-      const int8_t c = fok[k] ? cv[k] : (int8_t)0;
-      sc[i] = c;
-      sf[i] = (c == 1 || c == 3) ? fv[k] : (T)0;
+    for (int k = 0; k < NR; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < NRN) sr[i] = rpv[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < NFN) src[i] = fok[k] ? rcv[k] : kNoUnknown;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NFN; i += 256) {
+      const uint8_t c = src[i];
+      T v = 0;
+      if (c != kNoUnknown) {
+        const int x = i % FX, y = i / FX;
+        const T* pp = sr + (2 * x + 1) + RX * (2 * y + 1);
+        T rr[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) rr[q] = pp[(q / 3 - 1) + RX * (q % 3 - 1)];
+        v = restrict_box<2, T>(c, rr);
+      }
+      sf[i] = v;
+    }
+    __syncthreads();  // sf is read below at positions other threads computed
+    // the restricted right-hand side of the tile's unknowns, for the level's later launches
+    for (int i = threadIdx.x; i < TX * TY; i += 256) {
+      const int x = i % TX, y = i / TX;
+      const int fi = (x + 1) + FX * (y + 1);
+      if (src[fi] == kNoUnknown) continue;
+      a.rhs_w[base + (ox + x) + g.st[1] * (oy + y)] = sf[fi];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < NFN) {
+        const int8_t c = fok[k] ? fc[k] : (int8_t)0;
+        sf[i] = (c == 1 || c == 3) ? fv[k] : (T)0;
+      }
+    }
+  }
+  if constexpr (PROLONG) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < NCN) {
+        sce[i] = cok[k] ? ev[k] : (T)0;
+        scc[i] = cok[k] ? ccv[k] : (int8_t)0;
+      }
+    }
+    __syncthreads();
+    // u + interpolated correction at every unknown of the U region
+    for (int i = threadIdx.x; i < NUN; i += 256) {
+      if (sc[i] == 0) continue;
+      const int x = i % UX, y = (i / UX) % UY, z = i / (UX * UY);
+      const int j[3] = {ox + x - 2, oy + y - 2, D == 3 ? oz + z - 2 : 0};
+      T w[1 << D], ec[1 << D];
+      int8_t cc[1 << D];
+#pragma unroll
+      for (int m = 0; m < (1 << D); ++m) {
+        int jc[3];
+        w[m] = prolong_candidate<D, T>(j, m, jc);
+        const int li = (jc[0] - (ox / 2 - 1)) + CX * ((jc[1] - (oy / 2 - 1)) +
+                                                      CY * (D == 3 ? jc[2] - (oz / 2 - 1) : 0));
+        cc[m] = w[m] != (T)0 ? scc[li] : (int8_t)0;
+        ec[m] = w[m] != (T)0 ? sce[li] : (T)0;
+      }
+      su[i] = prolong_correct<D, T>(su[i], w, cc, ec);
     }
   }
   __syncthreads();
   constexpr int SY = UX, SZ = UX * UY;
-  for (int i = threadIdx.x; i < FZ * FY * FX; i += 256) {
-    if (sc[i] != 1 && sc[i] != 3) continue;
+  for (int i = threadIdx.x; i < NFN; i += 256) {
     const int x = i % FX, y = (i / FX) % FY, z = i / (FX * FY);
+    const int ui = (x + 1) + SY * (y + 1) + (D == 3 ? SZ * (z + 1) : 0);
+    if (sc[ui] != 1 && sc[ui] != 3) continue;
     const int gx = ox + x - 1, gy = oy + y - 1, gz = D == 3 ? oz + z - 1 : 0;
     if ((gx + gy + gz) & 1) continue;
-    const int ui = (x + 1) + SY * (y + 1) + (D == 3 ? SZ * (z + 1) : 0);
     T nb[2 * D];
     nb[0] = su[ui - 1];
     nb[1] = su[ui + 1];
@@ -156,10 +381,10 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
     const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
     const int fi = (x + 1) + FX * (y + 1) + (D == 3 ? FX * FY * (z + 1) : 0);
-    if (sc[fi] != 1 && sc[fi] != 3) continue;
+    const int ui = (x + 2) + SY * (y + 2) + (D == 3 ? SZ * (z + 2) : 0);
+    if (sc[ui] != 1 && sc[ui] != 3) continue;
     const int gx = ox + x, gy = oy + y, gz = D == 3 ? oz + z : 0;
     if (!((gx + gy + gz) & 1)) continue;
-    const int ui = (x + 2) + SY * (y + 2) + (D == 3 ? SZ * (z + 2) : 0);
     T nb[2 * D];
     nb[0] = su[ui - 1];
     nb[1] = su[ui + 1];
@@ -174,21 +399,13 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   __syncthreads();
   for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
     const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
-    const int fi = (x + 1) + FX * (y + 1) + (D == 3 ? FX * FY * (z + 1) : 0);
-    const int8_t c = sc[fi];
-    if (c == 0 || (c != 1 && !a.write_all)) continue;
     const int ui = (x + 2) + SY * (y + 2) + (D == 3 ? SZ * (z + 2) : 0);
+    const int8_t c = sc[ui];
+    if (c == 0 || (c != 1 && !a.write_all)) continue;
     a.uout[base + (ox + x) + g.st[1] * (oy + y) + g.st[2] * (D == 3 ? oz + z : 0)] = su[ui];
   }
 }
 
-template <int D, typename T>
-constexpr size_t tile_lds() {
-  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
-  constexpr int UX = TX + 4, UY = TY + 4, UZ = D == 3 ? TZ + 4 : 1;
-  constexpr int FX = TX + 2, FY = TY + 2, FZ = D == 3 ? TZ + 2 : 1;
-  return (size_t)(UZ * UY * UX + FZ * FY * FX) * sizeof(T) + (size_t)FZ * FY * FX;
-}
 
 // ---------------------------------------------------------------------------------------
 // relaxation, boundary chunks: the whole relaxation of one chunk's node set
@@ -201,8 +418,9 @@ constexpr size_t tile_lds() {
 // ids, weights and constant); only the node values are shared, in LDS.  Phases are separated
 // by workgroup barriers; a ghost phase computes every new ghost value before any is stored.
 // The owned entries are written to uout.
-template <int D, typename T>
+template <int D, typename T, int MODE>
 __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
+  constexpr bool PROLONG = MODE == kRelaxProlong, RESTRICT = MODE == kRelaxRestrict;
   constexpr int K = Pow3<D>::value;
   constexpr int NK = kChunkPerThread;
   // the header is uniform over the workgroup; every per-entry load below is issued without
@@ -242,12 +460,73 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
     }
     gc = ((const double*)(a.data + hd[5]))[tg];
   }
+  constexpr int NCAND = 1 << D;
+  int32_t pci[NK][NCAND];
+  int32_t rf0[NK], rcd[NK];
+  if constexpr (RESTRICT) {
+    // fine node index of (2x, 2y, 2z) and restriction code of every entry
+    const int32_t* RS = a.data + hd[7];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int e = tid + k * kChunkThreads;
+      const int ec = e < ns ? e : 0;
+      rf0[k] = RS[2 * ec];
+      rcd[k] = RS[2 * ec + 1];
+    }
+  }
+  if constexpr (PROLONG) {
+    // interpolation candidates of every entry, resolved on the host (-1: none)
+    const int32_t* PC = a.data + hd[6];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int e = tid + k * kChunkThreads;
+      const int ec = e < ns ? e : 0;
+#pragma unroll
+      for (int m = 0; m < NCAND; ++m) pci[k][m] = PC[ec * NCAND + m];
+    }
+  }
   T rv[NK], uv[NK];
   T* su = (T*)lds;
+  if constexpr (RESTRICT) {
+    // the relaxation starts from zero with the right-hand side restricted from the finer
+    // level's defect (the tiles store it for the level's later launches)
+    constexpr int KT = Pow3<D>::value;
+    T rr[NK][KT];
 #pragma unroll
-  for (int k = 0; k < NK; ++k) {
-    uv[k] = a.uin[node[k]];
-    rv[k] = a.rhs[node[k]];
+    for (int k = 0; k < NK; ++k)
+      restrict_gather<D, T>(a.rf, rf0[k], a.gf, (uint8_t)rcd[k], rr[k]);
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      uv[k] = 0;
+      rv[k] = restrict_box<D, T>((uint8_t)rcd[k], rr[k]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      uv[k] = a.uin[node[k]];
+      rv[k] = a.rhs[node[k]];
+    }
+  }
+  if constexpr (PROLONG) {
+    T pe[NK][NCAND];
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+#pragma unroll
+      for (int m = 0; m < NCAND; ++m) pe[k][m] = a.uc[pci[k][m] >= 0 ? pci[k][m] : 0];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      T w1 = 1;
+      const int nodd = (int)((mask[k] >> 28) & 3u);
+      for (int q = 0; q < nodd; ++q) w1 *= (T)0.5;
+      T w[NCAND];
+      int8_t cc[NCAND];
+#pragma unroll
+      for (int m = 0; m < NCAND; ++m) {
+        w[m] = pci[k][m] >= 0 ? w1 : (T)0;
+        cc[m] = pci[k][m] >= 0 ? 1 : 0;
+      }
+      uv[k] = prolong_correct<D, T>(uv[k], w, cc, pe[k]);
+    }
   }
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
@@ -292,13 +571,18 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
   }
 }
 
-template <int D, typename T>
+// CHUNKS: the level has relaxation chunks (workgroups [0, nchunks)).  MODE kRelaxProlong:
+// the relaxation starts from the iterate plus the interpolated coarse correction;
+// kRelaxRestrict: it starts from zero with the right-hand side restricted from the finer
+// level's defect (and stores that right-hand side).  Each variant holds only the registers
+// of the paths it runs.
+template <int D, typename T, bool CHUNKS, int MODE>
 __global__ void __launch_bounds__(256) k_relax(RelaxArgs<T> a) {
   extern __shared__ __align__(16) unsigned char relax_smem[];
-  if ((int)blockIdx.x < a.nchunks)
-    relax_chunk<D, T>(a, blockIdx.x, relax_smem);
+  if (CHUNKS && (int)blockIdx.x < a.nchunks)
+    relax_chunk<D, T, MODE>(a, blockIdx.x, relax_smem);
   else
-    relax_tile<D, T>(a, (int)blockIdx.x - a.nchunks, relax_smem);
+    relax_tile<D, T, MODE>(a, (int)blockIdx.x - (CHUNKS ? a.nchunks : 0), relax_smem);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -669,21 +953,7 @@ __global__ void __launch_bounds__(256) k_restrict(const int4* __restrict__ tiles
       uc[X[k]] = (T)0;
       const uint8_t c = cd[k];
       if (c == kNoUnknown) continue;
-      const int lx = (c & 1) ? -1 : 0, hx = (c & 2) ? 1 : 0;
-      const int ly = (c & 4) ? -1 : 0, hy = (c & 8) ? 1 : 0;
-      const int lz = D == 3 && (c & 16) ? -1 : 0, hz = D == 3 && (c & 32) ? 1 : 0;
-      T s = 0;
-#pragma unroll
-      for (int q = 0; q < KT; ++q) {
-        const int kx = q / (D == 3 ? 9 : 3) - 1, ky = (q / (D == 3 ? 3 : 1)) % 3 - 1;
-        const int kz = D == 3 ? q % 3 - 1 : 0;
-        const bool inbox = kx >= lx && kx <= hx && ky >= ly && ky <= hy && kz >= lz && kz <= hz;
-        const T w = inbox ? (T)(restrict_w1d(lx, hx, kx) * restrict_w1d(ly, hy, ky) *
-                                (D == 3 ? restrict_w1d(lz, hz, kz) : 1.0))
-                          : (T)0;
-        s += w * rv[k][q];
-      }
-      rhsc[X[k]] = s;
+      rhsc[X[k]] = restrict_box<D, T>(c, rv[k]);
     }
   }
 }
@@ -699,15 +969,15 @@ __global__ void __launch_bounds__(256) k_prolong(const int4* __restrict__ tiles,
                                                  const T* __restrict__ uc, T* __restrict__ uf) {
   constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
   constexpr int NK = TZ * TY * TX / 256;
-  constexpr int NC = 1 << D;
+  constexpr int NCAND = 1 << D;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntiles) return;
   const int4 t = tiles[tile];
   const int64_t basef = (int64_t)t.x * gf.npp, basec = (int64_t)t.x * gc.npp;
   int64_t P[NK];
   bool ok[NK];
-  int8_t cf[NK], cc[NK][NC];
-  T ufv[NK], ucv[NK][NC], wv[NK][NC];
+  int8_t cf[NK], cc[NK][NCAND];
+  T ufv[NK], ec[NK][NCAND], w[NK][NCAND];
   // all loads first; candidates that do not exist read the first coarse node with weight 0
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
@@ -718,40 +988,18 @@ __global__ void __launch_bounds__(256) k_prolong(const int4* __restrict__ tiles,
     cf[k] = clsf[P[k]];
     ufv[k] = uf[P[k]];
 #pragma unroll
-    for (int m = 0; m < NC; ++m) {
-      bool skip = !ok[k];
-      T w = 1;
-      int64_t X = basec;
-#pragma unroll
-      for (int q = 0; q < D; ++q) {
-        const int bit = (m >> q) & 1;
-        int jc;
-        if ((j[q] & 1) == 0) {
-          if (bit) skip = true;
-          jc = j[q] >> 1;
-        } else {
-          jc = bit ? (j[q] + 1) >> 1 : (j[q] - 1) >> 1;
-          w *= (T)0.5;
-        }
-        X += gc.st[q] * jc;
-      }
-      if (skip) X = basec;
-      wv[k][m] = skip ? (T)0 : w;
+    for (int m = 0; m < NCAND; ++m) {
+      int jc[3];
+      w[k][m] = ok[k] ? prolong_candidate<D, T>(j, m, jc) : (T)0;
+      const int64_t X = w[k][m] != (T)0 ? basec + jc[0] + gc.st[1] * jc[1] + gc.st[2] * jc[2] : basec;
       cc[k][m] = clsc[X];
-      ucv[k][m] = uc[X];
+      ec[k][m] = uc[X];
     }
   }
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     if (!ok[k] || cf[k] == 0) continue;
-    T num = 0, den = 0;
-#pragma unroll
-    for (int m = 0; m < NC; ++m) {
-      if (wv[k][m] == (T)0 || cc[k][m] == 0) continue;
-      num += wv[k][m] * ucv[k][m];
-      den += wv[k][m];
-    }
-    if (den > (T)0) uf[P[k]] = ufv[k] + num / den;
+    uf[P[k]] = prolong_correct<D, T>(ufv[k], w[k], cc[k], ec[k]);
   }
 }
 
@@ -926,7 +1174,16 @@ constexpr int kSingleWgExt = 24576;
 
 template <int D, typename T>
 size_t relax_lds(const DevLevel& L) {
-  return std::max(tile_lds<D, T>(), (size_t)L.bc_smax * sizeof(T));
+  return std::max(tile_lds<D, T, kRelaxProlong>(), (size_t)L.bc_smax * sizeof(T));
+}
+
+template <int D, typename T, int MODE>
+static void launch_relax_kernel(const RelaxArgs<T>& a, int nb, const DevLevel& L, hipStream_t s) {
+  const size_t lds = std::max(tile_lds<D, T, MODE>(), (size_t)L.bc_smax * sizeof(T));
+  if (a.nchunks)
+    hipLaunchKernelGGL((k_relax<D, T, true, MODE>), dim3(nb), dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_relax<D, T, false, MODE>), dim3(nb), dim3(256), lds, s, a);
 }
 
 size_t defect_lds(const DevLevel& L) { return (size_t)L.ec_smax * sizeof(double); }
@@ -978,8 +1235,28 @@ static void launch_band(const DevLevel& L, const mg_grid& G, T* u, const T* rhs,
 
 template <int D, typename T>
 void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, const T* rhs,
-                  T* tmp, int batch, hipStream_t s) {
+                  T* tmp, int batch, hipStream_t s, const DevLevel* C, const T* uc,
+                  const DevLevel* F, const T* rf) {
+  if (F && D != 2) {
+    // the restriction is fused in 2D only: restrict, then relax from the zeroed iterate
+    launch_restrict<D, T>(*F, L, rf, const_cast<T*>(rhs), const_cast<T*>(uin), s);
+    F = nullptr;
+  }
   RelaxArgs<T> a;
+  a.rf = F ? rf : nullptr;
+  a.gf = F ? F->g : L.g;
+  a.rcode = L.rcode;
+  a.rhs_w = const_cast<T*>(rhs);
+  a.prolong = C != nullptr;
+  if (C) {
+    a.gc = C->g;
+    a.uc = uc;
+    a.clsc = C->cls;
+  } else {
+    a.gc = L.g;
+    a.uc = uin;
+    a.clsc = L.cls;
+  }
   a.tiles = L.tiles;
   a.ntiles = L.ntiles;
   a.nbt = L.ntiles ? tile_grid(L.ntiles) : 0;
@@ -996,8 +1273,25 @@ void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, co
   a.hdr = L.bc_hdr;
   a.data = L.bc_data;
   const int nb = a.nchunks + a.nbt;
-  const size_t lds = relax_lds<D, T>(L);
-  if (nb) hipLaunchKernelGGL((k_relax<D, T>), dim3(nb), dim3(256), lds, s, a);
+  if (!L.nchunks && C) {
+    // the per-phase boundary path reads u in place: interpolate first
+    launch_prolong<D, T>(L, *C, uc, const_cast<T*>(uin), s);
+    a.prolong = 0;
+  }
+  bool restrict_ = F != nullptr;
+  if (!L.nchunks && restrict_) {
+    // likewise: restrict (and zero the iterate) first
+    launch_restrict<D, T>(*F, L, rf, const_cast<T*>(rhs), const_cast<T*>(uin), s);
+    restrict_ = false;
+  }
+  if (nb) {
+    if (restrict_)
+      launch_relax_kernel<D, T, D == 2 ? kRelaxRestrict : kRelaxPlain>(a, nb, L, s);
+    else if (a.prolong)
+      launch_relax_kernel<D, T, kRelaxProlong>(a, nb, L, s);
+    else
+      launch_relax_kernel<D, T, kRelaxPlain>(a, nb, L, s);
+  }
   if (!L.nchunks) launch_band<D, T>(L, G, uout, rhs, tmp, batch, s);
 }
 
@@ -1104,7 +1398,8 @@ void launch_dc_update(const DevLevel& L, double* u64, const float* u32, float* u
 
 #define GHOSTMG_INST(D, T)                                                                    \
   template void launch_relax<D, T>(const DevLevel&, const mg_grid&, const T*, T*, const T*, T*, \
-                                   int, hipStream_t);                                         \
+                                   int, hipStream_t, const DevLevel*, const T*,               \
+                                   const DevLevel*, const T*);                                \
   template void launch_defect<D, T, T>(const DevLevel&, const T*, const T*, T*, uint64_t*,    \
                                        bool, int, hipStream_t);                               \
   template void launch_restrict<D, T>(const DevLevel&, const DevLevel&, const T*, T*, T*,     \

@@ -60,11 +60,24 @@ void gradient(const PL& L, const int j[3], double g[3]) {
   }
 }
 
-bool is_dirichlet(const mg_bc_rule& r, int D, const double* B) {
-  double v = r.c;
-  for (int a = 0; a < D; ++a) v += r.a[a] * B[a];
-  return r.strict ? (v > 0.0) : (v >= 0.0);
-}
+// The partition of the boundary into Gamma_D and Gamma_N (Sec. 2.1), evaluated at a closest
+// boundary point: a half-space rule, or the caller's function.
+struct BcPartition {
+  const mg_bc_rule* rule;
+  mg_bc_fn fn;
+  void* ctx;
+  int problem;
+  bool dirichlet(int D, const double* B) const {
+    if (fn) {
+      double b[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < D; ++a) b[a] = B[a];
+      return fn(problem, b, ctx) != 0;
+    }
+    double v = rule->c;
+    for (int a = 0; a < D; ++a) v += rule->a[a] * B[a];
+    return rule->strict ? (v > 0.0) : (v >= 0.0);
+  }
+};
 
 // Does the stencil of the rung (signs s) stay inside the box and on unknowns?
 bool contained(const PL& L, const int jG[3], const int8_t* s, int rung) {
@@ -106,7 +119,7 @@ void row_weights(const GhostRec& g, double inv_h, double* w) {
   ghost_row<D>(g, inv_h, w);
 }
 
-int classify(PL& L, const mg_grid& G, const mg_bc_rule& rule) {
+int classify(PL& L, const mg_grid& G, const BcPartition& part) {
   const int D = L.D;
   L.cls.assign(L.nn, OUT);
   int64_t nin = 0;
@@ -158,7 +171,7 @@ int classify(PL& L, const mg_grid& G, const mg_bc_rule& rule) {
     GhostRec r;
     std::memset(&r, 0, sizeof(r));
     r.node = (int32_t)Gi;
-    r.type = is_dirichlet(rule, D, B) ? 1 : 0;
+    r.type = part.dirichlet(D, B) ? 1 : 0;
     // upwind signs of Eq. (St_G); a tie goes to the side of the smaller-phi neighbour
     int8_t pref[3] = {1, 1, 1};
     int tiedax[3], ntied = 0;
@@ -255,7 +268,7 @@ struct Ext {
 // (Sec. 2.6): every outside non-ghost node of F in the 3^D neighbourhood of a ghost of C,
 // processed once in increasing phi, each averaging its available upwind neighbours
 // Q_a = P - sgn(n_a) e_a with weights |n_a| (the steady state of Eq. (exp)).
-int extension(PL& F, const PL& C, const mg_grid& G, const mg_bc_rule& rule,
+int extension(PL& F, const PL& C, const mg_grid& G, const BcPartition& part,
               std::vector<Ext>& out) {
   const int D = F.D;
   std::vector<int64_t> rank(F.nn, -1);
@@ -312,7 +325,7 @@ int extension(PL& F, const PL& C, const mg_grid& G, const mg_bc_rule& rule,
     }
     double Bp[3] = {0, 0, 0};
     for (int a = 0; a < D; ++a) Bp[a] = (F.lo + F.h * (double)j[a]) - gr[a] / nrm * F.phi[P];
-    F.lab[P] = is_dirichlet(rule, D, Bp) ? 1 : 0;
+    F.lab[P] = part.dirichlet(D, Bp) ? 1 : 0;
     int nsame = 0;
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1 && (!G.split || nsame > 0)) break;
@@ -480,6 +493,7 @@ int build_hierarchy(mg_handle_s* H, const double* phi) {
   int64_t nn0 = 1;
   for (int a = 0; a < D; ++a) nn0 *= np0;
   for (int p = 0; p < batch; ++p) {
+    const BcPartition part{H->bc_fn ? nullptr : &H->bc[p], H->bc_fn, H->bc_ctx, p};
     std::vector<PL> lev(L + 1);
     for (int l = 0; l <= L; ++l) {
       PL& V = lev[l];
@@ -504,7 +518,7 @@ int build_hierarchy(mg_handle_s* H, const double* phi) {
         if (!std::isfinite(v)) return MG_EINVAL;
         V.phi[i] = v;
       }
-      int rc = classify(V, G, H->bc[p]);
+      int rc = classify(V, G, part);
       if (rc) return rc;
     }
     for (int l = 0; l <= L; ++l) {
@@ -572,7 +586,7 @@ int build_hierarchy(mg_handle_s* H, const double* phi) {
       HostLevel& HF = H->host[l];
       HostLevel& HC = H->host[l + 1];
       std::vector<Ext> ext;
-      int rc = extension(F, C, G, H->bc[p], ext);
+      int rc = extension(F, C, G, part, ext);
       if (rc) return rc;
       const Geo& gf = HF.g;
       const int64_t basef = (int64_t)p * gf.npp;
@@ -794,7 +808,7 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
   HL.bc_smax = 0;
   HL.bc_entries = 0;
   HL.bc_nown = 0;
-  if (P > 31) return false;
+  if (P > 28) return false;  // mask bits 28-29 hold the interpolation weight exponent
   // role of a node: 1 red band, 2 black band, 3 ghost, 4 red interior off the band,
   // 5 black interior off the band
   std::vector<int8_t> role(nn, 0);
@@ -918,6 +932,41 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
         const int hi = relaxed && lid[v + g.st[a2]] >= 0 ? lid[v + g.st[a2]] : 0;
         Dv.push_back(pack16(lo, hi));
       }
+    // interpolation candidates of every entry (Sec. 2.6.1): candidate m (bit q: upper
+    // neighbour along axis q) as a coarse node index, or -1 where it does not exist or
+    // carries no unknown; the weight 2^-(odd coordinates) goes into mask bits 28-29
+    const int32_t pc_off = (int32_t)Dv.size();
+    if (l < H->L) {
+      const HostLevel& HC = H->host[l + 1];
+      const int NC = 1 << D;
+      for (int i = 0; i < ns; ++i) {
+        int64_t p;
+        int j[3];
+        node_coords(g, D, touched[i], &p, j);
+        int nodd = 0;
+        for (int q = 0; q < D; ++q) nodd += j[q] & 1;
+        Dv[off + ns + i] |= (int32_t)((uint32_t)nodd << 28);
+        for (int m = 0; m < NC; ++m) {
+          bool exists = true;
+          int jc[3] = {0, 0, 0};
+          for (int q = 0; q < D; ++q) {
+            const int bit = (m >> q) & 1;
+            if ((j[q] & 1) == 0) {
+              if (bit) exists = false;
+              jc[q] = j[q] >> 1;
+            } else {
+              jc[q] = bit ? (j[q] + 1) >> 1 : (j[q] - 1) >> 1;
+            }
+          }
+          int32_t X = -1;
+          if (exists) {
+            const int64_t c = p * HC.g.npp + jc[0] + HC.g.st[1] * jc[1] + HC.g.st[2] * jc[2];
+            if (HC.cls[c] != 0) X = (int32_t)c;
+          }
+          Dv.push_back(X);
+        }
+      }
+    }
     const int32_t gid_off = (int32_t)Dv.size();
     for (int t = 0; t < K; ++t)
       for (int j = 0; j < ng; ++j) {
@@ -934,7 +983,21 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     wv.clear();
     for (int j = 0; j < ng; ++j) wv.push_back(HL.ghosts[gidx[touched[j]]].type ? H->grid.cD : cNh);
     put_doubles(Dv, wv);
-    const int32_t hdr[kBandHdr] = {ns, ng, off, gid_off, gw_off, gc_off, 0, 0};
+    // restriction data of every entry (levels fed by a finer level): the fine node index
+    // of (2x, 2y, 2z) and the node's restriction code
+    const int32_t rs_off = (int32_t)Dv.size();
+    if (l > 0) {
+      const HostLevel& HF = H->host[l - 1];
+      for (int i = 0; i < ns; ++i) {
+        int64_t p;
+        int j[3];
+        node_coords(g, D, touched[i], &p, j);
+        Dv.push_back((int32_t)(p * HF.g.npp + 2 * j[0] + HF.g.st[1] * 2 * j[1] + HF.g.st[2] * 2 * j[2]));
+        Dv.push_back((int32_t)HL.rcode[touched[i]]);
+      }
+    }
+    const int32_t hdr[kBandHdr] = {ns, ng, off, gid_off, gw_off, gc_off, l < H->L ? pc_off : -1,
+                                   l > 0 ? rs_off : -1};
     HL.bc_hdr.insert(HL.bc_hdr.end(), hdr, hdr + kBandHdr);
     ++HL.bc_nchunks;
     HL.bc_entries += ns;

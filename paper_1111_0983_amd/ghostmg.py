@@ -39,6 +39,11 @@ class mg_stats(ctypes.Structure):
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int)]
 
 
+# partition of the boundary: (problem, B[3], ctx) -> nonzero on Gamma_D
+MG_BC_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                            ctypes.c_void_p)
+
+
 class GhostMGError(RuntimeError):
     def __init__(self, code, what):
         self.code = code
@@ -53,6 +58,8 @@ def _load():
     lib.mg_grid_default.argtypes = [ctypes.POINTER(mg_grid), ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.mg_setup.argtypes = [vp, ctypes.POINTER(mg_bc_rule), ctypes.POINTER(mg_grid),
                              ctypes.POINTER(vp)]
+    lib.mg_setup_partition.argtypes = [vp, MG_BC_FN, vp, ctypes.POINTER(mg_grid),
+                                       ctypes.POINTER(vp)]
     lib.mg_set_stream.argtypes = [vp, vp]
     lib.mg_query_level.argtypes = [vp, ctypes.c_int, vp]
     lib.mg_query_ghosts.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64p, vp, vp, vp, vp, vp]
@@ -115,9 +122,10 @@ def _ptr(t):
 
 class Solver:
     """One mg_setup handle.  phi: torch tensor (device or host) or numpy array of
-    batch * (n+1)^dim FP64 values; rules: one dict per problem (see mg_bc_rule)."""
+    batch * (n+1)^dim FP64 values; rules: one dict per problem (see mg_bc_rule), or
+    partition: a function (problem, B) -> bool (True on Gamma_D) called during setup."""
 
-    def __init__(self, phi, rules, grid: mg_grid):
+    def __init__(self, phi, rules, grid: mg_grid, partition=None):
         import torch
 
         if isinstance(phi, torch.Tensor):
@@ -127,8 +135,13 @@ class Solver:
         self.grid = grid
         self.dim, self.n, self.batch = grid.dim, grid.n, grid.batch
         h = ctypes.c_void_p()
-        _check(_lib.mg_setup(_ptr(phi), _rules(rules), ctypes.byref(grid), ctypes.byref(h)),
-               "mg_setup")
+        if partition is not None:
+            cb = MG_BC_FN(lambda p, B, ctx: int(bool(partition(p, (B[0], B[1], B[2])))))
+            _check(_lib.mg_setup_partition(_ptr(phi), cb, None, ctypes.byref(grid),
+                                           ctypes.byref(h)), "mg_setup_partition")
+        else:
+            _check(_lib.mg_setup(_ptr(phi), _rules(rules), ctypes.byref(grid), ctypes.byref(h)),
+                   "mg_setup")
         self._h = h
         self.nlev = int(self.level(0)["levels"])
         self._phi_keep = None

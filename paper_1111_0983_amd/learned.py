@@ -149,7 +149,7 @@ def generate(n_samples: int, seed0: int = 0, batch: int = 64, device="cuda:0", l
         fmax = f.reshape(B0, -1).abs().max(dim=1).values.cpu().numpy()
         good = torch.from_numpy(norms <= 1e-8 * np.maximum(fmax, 1e-300)).to(f.device)
         x, scale, (B, H, W) = cnn.features(solver, LEVEL, f, g)
-        tgt, mask = cnn.target(solver, LEVEL, u, scale)
+        tgt, mask = cnn.target(solver, LEVEL, u, scale / cnn.GuessNet.GAIN)
         rejected += int(B0 - good.sum().item())
         xs.append(x.reshape(B, H * W * 8)[good])
         ts.append(tgt.reshape(B, H * W)[good])
@@ -176,7 +176,8 @@ def train(net: cnn.GuessNet, data: dict, steps: int, batch: int = 64, lr: float 
         x = data["x"][idx].reshape(-1)
         t = data["t"][idx].reshape(-1)
         m = data["m"][idx].reshape(-1)
-        lr_t = lr * 0.5 * (1 + np.cos(np.pi * step / steps))
+        warm = min(1.0, (step + 1) / 100.0)
+        lr_t = lr * warm * 0.5 * (1 + np.cos(np.pi * step / steps))
         pred = net.forward(x, batch, H, W)
         out, dy = cnn.loss(pred, t, m)
         net.adam(net.backward(dy, batch, H, W), lr=lr_t)
@@ -267,7 +268,83 @@ def evaluate(net: cnn.GuessNet | None, seeds, tol: float = 1e-10, device="cuda:0
     out["unknowns"] = unknowns
     s64.close()
     sdc.close()
+    out["per_problem"] = evaluate_each(net, probs, f, g, tol=tol, device=device, reps=reps)
     return out
+
+
+def evaluate_each(net, probs, f, g, tol=1e-10, device="cuda:0", reps=3):
+    """Cycles and time to the tolerance of every problem solved on its own (a batch solve
+    runs until its slowest problem converges): FP64 and FP32 defect correction from the zero
+    guess, FP32 defect correction and FP64 from the learned guess (network inference
+    included in the time).  Returns per-problem lists and their means / medians."""
+    from workloads import ellipses as el
+
+    nn = (N_FINE + 1) ** 2
+    rows = {k: [] for k in ("zero64_cycles", "zero64_ms", "zero_dc_cycles", "zero_dc_ms",
+                            "learned_dc_cycles", "learned_dc_ms", "learned64_cycles",
+                            "learned64_ms", "guess_rel_error")}
+    for i, p in enumerate(probs):
+        phi = el.nodal_phi(p, N_FINE, device=device)
+        fi = f[i * nn:(i + 1) * nn].contiguous()
+        gi = g[i * nn:(i + 1) * nn].contiguous()
+        s64 = gm.Solver(phi, [p.rule], gm.mg_grid_default(2, N_FINE, N_COARSE, max_cycles=400))
+        sdc = gm.Solver(phi, [p.rule], gm.mg_grid_default(2, N_FINE, N_COARSE, max_cycles=400,
+                                                          precision=gm.MG_FP32_DC))
+        u = torch.zeros_like(fi)
+
+        def timed(fn):
+            best, info = None, None
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = fn()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            return info, best
+
+        def zero64():
+            u.zero_()
+            return s64.solve(fi, gi, u, tol=tol)
+
+        info, dt = timed(zero64)
+        ref = u.clone()
+        rows["zero64_cycles"].append(info["cycles"])
+        rows["zero64_ms"].append(1e3 * dt)
+
+        def zero_dc():
+            u.zero_()
+            return sdc.solve(fi, gi, u, tol=tol)
+
+        info, dt = timed(zero_dc)
+        rows["zero_dc_cycles"].append(info["cycles"])
+        rows["zero_dc_ms"].append(1e3 * dt)
+        if net is not None:
+            def learned_dc():
+                cnn.guess(net, sdc, LEVEL, fi, gi, u)
+                return sdc.solve(fi, gi, u, tol=tol)
+
+            info, dt = timed(learned_dc)
+            rows["learned_dc_cycles"].append(info["cycles"])
+            rows["learned_dc_ms"].append(1e3 * dt)
+
+            def learned64():
+                cnn.guess(net, s64, LEVEL, fi, gi, u)
+                return s64.solve(fi, gi, u, tol=tol)
+
+            info, dt = timed(learned64)
+            rows["learned64_cycles"].append(info["cycles"])
+            rows["learned64_ms"].append(1e3 * dt)
+            u0 = torch.zeros_like(u)
+            cnn.guess(net, s64, LEVEL, fi, gi, u0)
+            rows["guess_rel_error"].append(((u0 - ref).abs().max() / ref.abs().max()).item())
+        s64.close()
+        sdc.close()
+    res = {k: v for k, v in rows.items() if v}
+    for k, v in list(res.items()):
+        res[k + "_mean"] = float(np.mean(v))
+        res[k + "_median"] = float(np.median(v))
+    return res
 
 
 def main(argv=None):

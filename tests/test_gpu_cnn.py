@@ -56,6 +56,12 @@ def test_network_loss_and_gradients_match_reference():
     rng = np.random.default_rng(3)
     B, H, W = 2, 21, 23
     net = cnn.GuessNet(seed=4, device=DEV)
+    # the output layer starts at zero (which zeroes every upstream gradient): give it random
+    # weights so that every layer's gradient is exercised
+    cin, cout, _ = net.layers[-1]
+    net.w[-1].copy_(torch.from_numpy(rng.normal(0.0, (2.0 / (9 * cin)) ** 0.5,
+                                                size=cout * 9 * cin).astype(np.float32)))
+    net.repack()
     x = _rounded(rng.normal(size=(B, H, W, 4)))
     tgt = rng.normal(size=(B, H, W))
     mask = (rng.uniform(size=(B, H, W)) > 0.2).astype(np.float64)

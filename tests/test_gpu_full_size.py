@@ -1,0 +1,105 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch configuration the
+benchmark times: the oracle evaluates the defect of the GPU solution (an independent
+evaluation of the rows of Eq. (discr)), which must meet the 1e-10 target; where the oracle's
+own solve takes seconds (2D) the two solutions are also compared."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+from oracle import Oracle, default_grid  # noqa: E402
+from workloads import geometry as geo, problems as pr  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _gm():
+    from paper_1111_0983_amd import ghostmg as gm
+    return gm
+
+
+def _oracle_rel(o, u, rhs):
+    """max(||r||_inf over Omega_h, over Gamma_h) / ||(f_h, g_h)||_inf, by the oracle."""
+    _, (ni, ng) = o.defect(0, u, rhs)
+    c, _ = o.cls(0)
+    return max(ni, ng) / np.abs(rhs[c > 0]).max()
+
+
+def _solve(w, dim, n, nc, prec, tol=1e-10):
+    gm = _gm()
+    phi = w.domain.nodal_phi(n)
+    s = gm.Solver(torch.from_numpy(phi).to(DEV), [w.rule],
+                  gm.mg_grid_default(dim, n, nc, precision=prec, inner_cycles=2))
+    c = s.classes()
+    G = s.ghosts()
+    P = geo.grid_points(dim, n)
+    f = np.where(c == 1, w.solution.f(P), 0.0)
+    g = pr.rhs_from_ghosts(dim, n, c, G["node"], G["B"], G["type"], w.solution, w.domain)
+    u = torch.zeros(f.size, dtype=torch.float64, device=DEV)
+    info = s.solve(torch.from_numpy(f).to(DEV), torch.from_numpy(g).to(DEV), u, tol=tol)
+    assert info["status"] == 0 and info["rel"] <= tol
+    s.close()
+    return phi, u.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32dc"])
+def test_flower_2048(prec):
+    gm = _gm()
+    w = pr.flower(2048, 32)
+    phi, u, info = _solve(w, 2, 2048, 32, gm.MG_FP64 if prec == "fp64" else gm.MG_FP32_DC)
+    o = Oracle(phi, default_grid(2, 2048, 32), w.rule)
+    c, _ = o.cls(0)
+    G = o.ghosts(0)
+    rhs = pr.rhs_from_ghosts(2, 2048, c, G["node"], G["B"], G["type"], w.solution, w.domain)
+    assert _oracle_rel(o, u, rhs) <= 1.01e-10
+    st, uo, _ = o.solve(rhs, tol=1e-10, max_cycles=80)
+    assert st == 0
+    assert np.abs(u - uo).max() <= 1e-9 * np.abs(uo).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32dc"])
+def test_torus_256(prec):
+    gm = _gm()
+    w = pr.torus(256, 16)
+    phi, u, info = _solve(w, 3, 256, 16, gm.MG_FP64 if prec == "fp64" else gm.MG_FP32_DC)
+    o = Oracle(phi, default_grid(3, 256, 16), w.rule)
+    c, _ = o.cls(0)
+    G = o.ghosts(0)
+    rhs = pr.rhs_from_ghosts(3, 256, c, G["node"], G["B"], G["type"], w.solution, w.domain)
+    assert _oracle_rel(o, u, rhs) <= 1.01e-10
+    assert np.all(u[c == 0] == 0.0)
+
+
+def test_ellipse_batch_512():
+    """The learned-guess workload: 64 seeded ellipse-union problems at 512^2 solved as one
+    batch in FP32 defect correction; the oracle checks the defect of four of them."""
+    gm = _gm()
+    from paper_1111_0983_amd import learned
+
+    seeds = list(range(1_000_000, 1_000_000 + 160))
+    s, f, g, probs = learned.build_batch(seeds, precision=gm.MG_FP32_DC, screen=False)
+    if len(probs) > 64:
+        s.close()
+        s, f, g, probs = learned.build_batch([p.seed for p in probs[:64]],
+                                             precision=gm.MG_FP32_DC, screen=False)
+    assert len(probs) >= 32
+    u = torch.zeros_like(f)
+    info = s.solve(f, g, u, tol=1e-10, check=False)
+    assert info["status"] in (gm.MG_OK, gm.MG_ENOCONV)
+    from workloads import ellipses as el
+
+    nn = 513 * 513
+    fa, ua = f.cpu().numpy(), u.cpu().numpy()
+    rels = s.residual(f, g, u).max(axis=1)
+    for i in (0, len(probs) // 3, 2 * len(probs) // 3, len(probs) - 1):
+        p = probs[i]
+        phi = el.nodal_phi(p, 512, device=DEV).cpu().numpy()
+        o = Oracle(phi, default_grid(2, 512, 32), p.rule)
+        c, _ = o.cls(0)
+        rhs = np.where(c == 1, fa[i * nn:(i + 1) * nn], 0.0)  # g = 0 on every ghost
+        rel_o = _oracle_rel(o, ua[i * nn:(i + 1) * nn], rhs)
+        rel_g = rels[i] / np.abs(rhs).max()
+        assert abs(rel_o - rel_g) <= 1e-3 * rel_g + 1e-15, (i, rel_o, rel_g)
+        if info["status"] == gm.MG_OK:
+            assert rel_o <= 1.01e-10

@@ -471,3 +471,54 @@ def test_rho_1d_matches_lfa_scale():
     r2 = _rho(dom, 1, 64, 8, 1, 1, 2, 0, rule)
     r3 = _rho(dom, 1, 64, 8, 2, 1, 2, 0, rule)
     assert 0.02 < r2 < 0.185 + 0.03 and 0.02 < r3 < 0.122 + 0.03 and r3 < r2
+
+
+# ---------------------------------------------------------------------------------------
+# arbitrary partitions of the boundary into Gamma_D and Gamma_N (Sec. 2.1)
+# ---------------------------------------------------------------------------------------
+def _halfspace(rule):
+    a = list(rule.get("a", (0.0, 0.0, 0.0))) + [0.0] * 3
+
+    def f(B):
+        v = rule.get("c", 0.0) + sum(a[k] * B[k] for k in range(3))
+        return v > 0.0 if rule.get("strict", 1) else v >= 0.0
+    return f
+
+
+def test_partition_function_equals_half_space_rule():
+    """A partition function that evaluates the half-space rule builds exactly the
+    hierarchy and the iterates of the rule itself."""
+    w = pr.flower(256, 32)
+    phi = w.domain.nodal_phi(256)
+    o1 = Oracle(phi, default_grid(2, 256, 32), w.rule)
+    o2 = Oracle(phi, default_grid(2, 256, 32), partition=_halfspace(w.rule))
+    for l in range(o1.nlev):
+        g1, g2 = o1.ghosts(l), o2.ghosts(l)
+        for k in g1:
+            assert np.array_equal(g1[k], g2[k]), (l, k)
+    rhs = _rhs(o1, 0, w.domain, w.solution)
+    u1, u2 = np.zeros_like(rhs), np.zeros_like(rhs)
+    for _ in range(3):
+        o1.cycle(u1, rhs)
+        o2.cycle(u2, rhs)
+    assert np.abs(u1).max() > 0 and np.array_equal(u1, u2)
+
+
+def test_two_arc_partition_second_order():
+    """Dirichlet on the two arcs |y_B| > 0.3 of the disk, Neumann on the two arcs between
+    them (four D/N junctions, no half-space describes it): the solution stays second-order
+    accurate."""
+    w = pr.disk64()
+    errs = []
+    for n in (64, 128, 256):
+        o = Oracle(w.domain.nodal_phi(n), default_grid(2, n, 4),
+                   partition=lambda B: abs(B[1]) > 0.3)
+        G = o.ghosts(0)
+        assert 0 < G["type"].sum() < len(G["type"])
+        rhs = _rhs(o, 0, w.domain, w.solution)
+        st, u, _ = o.solve(rhs, tol=1e-11, max_cycles=80)
+        assert st == 0
+        c, _ = o.cls(0)
+        errs.append(np.abs(u - w.solution.u(geo.grid_points(2, n)))[c == 1].max())
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    assert all(2.5 < r < 6.0 for r in ratios), (errs, ratios)

@@ -314,45 +314,3 @@ class Torus(Domain):
         return v / np.sqrt((v ** 2).sum(axis=1))[:, None]
 
 
-class Ellipsoid(Domain):
-    """Axis-aligned ellipsoid; SDF by the closest-point condition
-    x_i = p_i a_i^2 / (a_i^2 + t), solved for t by bisection (outside) or by a bracketed
-    Newton iteration (inside)."""
-    dim = 3
-
-    def __init__(self, center=(0.0, 0.0, 0.0), axes=(0.8, 0.6, 0.5)):
-        self.c = np.asarray(center, dtype=np.float64)
-        self.a = np.asarray(axes, dtype=np.float64)
-
-    def _closest(self, P):
-        p = np.abs(P - self.c)
-        a2 = self.a ** 2
-        g = lambda t: ((self.a * p / (a2 + t)) ** 2).sum(axis=1) - 1.0
-        lo = np.full(len(p), -a2.min()) + 1e-300
-        lo = -a2.min() + np.zeros(len(p))
-        hi = np.maximum(np.sqrt((p ** 2).sum(axis=1)) * self.a.max(), 1e-12) + 0.0
-        # g is decreasing on (-min a^2, inf); bisection on [lo, hi]
-        lo = lo + 1e-15
-        for _ in range(200):
-            mid = 0.5 * (lo + hi)
-            v = g(mid)
-            lo = np.where(v > 0, mid, lo)
-            hi = np.where(v > 0, hi, mid)
-        t = 0.5 * (lo + hi)
-        x = p * a2 / (a2 + t)
-        return x, t
-
-    def phi(self, P):
-        p = np.abs(P - self.c)
-        x, _ = self._closest(P)
-        d = np.sqrt(((x - p) ** 2).sum(axis=1))
-        ins = ((p / self.a) ** 2).sum(axis=1) < 1.0
-        return np.where(ins, -d, d)
-
-    def normal(self, P):
-        s = np.sign(P - self.c)
-        s[s == 0] = 1.0
-        x, _ = self._closest(P)
-        n = x / self.a ** 2
-        n = n / np.sqrt((n ** 2).sum(axis=1))[:, None]
-        return n * s
