@@ -186,10 +186,13 @@ def main():
     roof = {"bound": "hbm", "kernel": "k_relax<2,double> (finest level)", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None, "avg_us": round(k_ms * 1e3, 2), "bytes_per_launch": k_bytes}
+    # the launches of one V(2,1) cycle on every level (microseconds): the first
+    # pre-relaxation restricts (coarse levels), the first post-relaxation interpolates
     per_level = {}
     for lev in range(s.nlev - 1):
         row = {}
-        for name in ("relax", "defect", "restrict", "prolong"):
+        names = ["relax_restrict" if lev > 0 else "relax", "relax", "defect", "relax_prolong"]
+        for name in dict.fromkeys(names):
             ms_k, _ = s.time_kernel(name, lev, 20)
             row[name] = round(ms_k * 1e3, 2)
         per_level[str(lev)] = row

@@ -148,8 +148,13 @@ int mg_residual(mg_handle_t h, const double* f, const double* g, const double* u
  * reps times after one warm-up; kernel 0 = one relaxation (red-black interior sweep with the
  * ghost relaxation and the lambda boundary sweeps of Sec. 3.2; one launch on levels with
  * relaxation chunks), 1 = defect with its extension, Eq. (exp), 2 = restriction,
- * 3 = interpolation + correction, 4 = defect with its norms (the stopping test).  The level's
- * iterate, defect and coarse arrays are overwritten.  avg_ms: mean duration; bytes: the
+ * 3 = interpolation + correction, 4 = defect with its norms (the stopping test), 5 = a
+ * relaxation that first takes the interpolated correction of level + 1 (the cycle's first
+ * post-relaxation), 6 = a relaxation from zero with the right-hand side restricted from
+ * level - 1 (the cycle's first pre-relaxation on a coarse level; 2D, else a restriction
+ * launch followed by a relaxation).  level runs from 0 to the level above the coarsest (6:
+ * from 1), else MG_EINVAL; the coarsest level is solved directly.  The level's iterate,
+ * defect and coarse arrays are overwritten; a later mg_solve is unaffected.  avg_ms: mean duration; bytes: the
  * algorithmic HBM bytes per launch (every array element it must read or write once: per
  * unknown the iterate read and written, the right-hand side and the node code; per ghost
  * its row weights; per extension node its value and weights). */

@@ -406,6 +406,18 @@ void time_launch(mg_handle_s* h, int kernel, int level, int i, hipStream_t s) {
       launch_prolong<D, T>(L, C, Arr<T>::u(C, 0), u, s);
       break;
     }
+    case 5: {  // relaxation taking the interpolated correction of level + 1
+      DevLevel& C = h->dev[level + 1];
+      launch_relax<D, T>(L, h->grid, u, Arr<T>::u(L, 1 - (i & 1)), Arr<T>::rhs(L), Arr<T>::tmp(L),
+                         h->batch, s, &C, Arr<T>::u(C, 0));
+      break;
+    }
+    case 6: {  // relaxation from zero with the right-hand side restricted from level - 1
+      DevLevel& F = h->dev[level - 1];
+      launch_relax<D, T>(L, h->grid, u, Arr<T>::u(L, 1 - (i & 1)), Arr<T>::rhs(L), Arr<T>::tmp(L),
+                         h->batch, s, nullptr, nullptr, &F, Arr<T>::r(F));
+      break;
+    }
     default:
       launch_defect<D, T, T>(L, u, Arr<T>::rhs(L), Arr<T>::r(L), h->norms, false, h->batch, s);
   }
@@ -653,8 +665,9 @@ int mg_residual(mg_handle_t h, const double* f, const double* g, const double* u
 }
 
 int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_ms, double* bytes) {
-  if (!h || level < 0 || level > h->L || reps < 1 || kernel < 0 || kernel > 4) return MG_EINVAL;
-  if ((kernel == 2 || kernel == 3) && level >= h->L) return MG_EINVAL;
+  // the coarsest level is solved directly: none of these kernels runs there
+  if (!h || level < 0 || level >= h->L || reps < 1 || kernel < 0 || kernel > 6) return MG_EINVAL;
+  if (kernel == 6 && level == 0) return MG_EINVAL;
   hipStream_t s = stream_of(h);
   DevLevel& L = h->dev[level];
   const HostLevel& S = h->host[level];
@@ -682,6 +695,16 @@ int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_m
     const double K = h->dim == 2 ? 9.0 : 27.0;
     double b = 0.0;
     if (kernel == 0) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0;
+    if (kernel == 5) {
+      const HostLevel& C = h->host[level + 1];
+      b = nu * (3.0 * sz + 1.0) + ng * K * 8.0 + (double)(C.nint + C.nghost) * (sz + 1.0);
+    }
+    if (kernel == 6) {
+      // no iterate read; the right-hand side is written; the finer defect is read
+      const HostLevel& F = h->host[level - 1];
+      b = nu * (2.0 * sz + 2.0) + ng * K * 8.0 +
+          ((double)F.nint + (double)F.nghost + (double)F.ext.size()) * sz;
+    }
     if (kernel == 1) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0 + (double)S.ext.size() * (sz + 24.0);
     if (kernel == 4) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0;
     if (kernel == 2) {

@@ -19,6 +19,7 @@ constexpr int kExtHdr = 8;
 constexpr int kChunkThreads = 256;     // workgroup size of every chunk kernel
 constexpr int kChunkPerThread = 4;     // chunk entries owned by one thread
 constexpr int kChunkMaxEntries = kChunkPerThread * kChunkThreads;
+constexpr int kExtMaxTerms = 6 * kChunkThreads;  // composed extension terms per chunk
 
 // Tile shapes of the node-parallel kernels: 64 x 16 nodes in 2D, 16 x 8 x 8 in 3D.
 template <int D>
@@ -91,14 +92,17 @@ struct HostLevel {
   std::vector<int32_t> bc_data;
   int bc_nchunks = 0, bc_smax = 0, bc_nown = 0;
   int64_t bc_entries = 0;               // sum of chunk sizes (redundant work included)
-  // Extension chunks: each chunk owns a run of extension nodes, carries the extension
-  // nodes they depend on and evaluates the ghost defects they read (ghost sources first, at
-  // most one per thread).  Chunk c: header ec_hdr[c * kExtHdr ..] = {entries, ghost sources,
-  // offsets into ec_data of: the per-entry arrays, the source id pairs, the source weights,
-  // the ghost stencil nodes, the ghost weights; DAG levels}.  Per entry: node index; DAG level
-  // (0 for ghost sources; bit 31: owned); 2 words of int16 local source ids (-1 absent);
-  // 3 FP64 source weights (source-major).  Per ghost source (tap-major): Pow3<D> stencil node
-  // indices and FP64 row weights.
+  // Extension chunks.  The steady state of Eq. (exp) on the upwind graph is linear in the
+  // ghost defects: every extension value is a fixed combination of the defects of the ghost
+  // nodes its upwind paths start from, with weights composed on the host.  Each chunk owns a
+  // run of extension nodes (at most kChunkMaxEntries) and evaluates the defects of the ghost
+  // sources they need (at most kChunkThreads, one per thread).  Chunk c: header
+  // ec_hdr[c * kExtHdr ..] = {extension nodes, ghost sources, offsets into ec_data of: the node
+  // indices (ghost sources, then extension nodes), the term offsets (per extension node and
+  // one past the end, relative to the chunk's first term), the term source ids (local ghost
+  // ids), the term weights (FP64), the ghost stencil nodes (tap-major), the ghost row
+  // weights (FP64, tap-major)}; at most kExtMaxTerms terms.  ec_smax: the largest chunk's LDS
+  // in doubles (ghost values, term weights, term ids).
   std::vector<int32_t> ec_hdr;
   std::vector<int32_t> ec_data;
   int ec_nchunks = 0, ec_smax = 0;

@@ -534,40 +534,53 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
     if (e < ns) su[e] = uv[k];
   }
   __syncthreads();
+  // Only the owning thread writes an entry's slot, so uv[] stays the entry's current value.
+  // No update of a phase reads a value the same phase writes (red reads black and ghosts,
+  // black reads red and ghosts, the ghosts read the values before their phase), so each
+  // phase issues all its LDS reads before any of its writes; inactive entries read their
+  // own slot.
   for (int p = 0; p < a.phases; ++p) {
     if (p % 3 != 2) {
+      bool act[NK];
+      T nv[NK][2 * D];
 #pragma unroll
       for (int k = 0; k < NK; ++k) {
-        if (!((mask[k] >> p) & 1u)) continue;
-        const int e = tid + k * kChunkThreads;
-        T nv[2 * D];
+        act[k] = (mask[k] >> p) & 1u;
+        const int self = act[k] ? tid + k * kChunkThreads : 0;
 #pragma unroll
         for (int q = 0; q < D; ++q) {
-          nv[2 * q] = su[(int16_t)(nbw[k][q] & 0xffff)];
-          nv[2 * q + 1] = su[(int16_t)((uint32_t)nbw[k][q] >> 16)];
+          nv[k][2 * q] = su[act[k] ? (int)(int16_t)(nbw[k][q] & 0xffff) : self];
+          nv[k][2 * q + 1] = su[act[k] ? (int)(int16_t)((uint32_t)nbw[k][q] >> 16) : self];
         }
-        su[e] = interior_update<D, T>(su[e], nv, rv[k], a.h2, a.inv2d);
+      }
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        if (!act[k]) continue;
+        uv[k] = interior_update<D, T>(uv[k], nv[k], rv[k], a.h2, a.inv2d);
+        su[tid + k * kChunkThreads] = uv[k];
       }
       __syncthreads();
     } else {
       const bool upd = ghost && ((mask[0] >> p) & 1u);
-      T gnew = 0;
       if (upd) {
+        T gv[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) gv[q] = su[gid[q] >= 0 ? gid[q] : tid];
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < K; ++q)
-          if (gid[q] >= 0) acc += gwt[q] * (double)su[gid[q]];
-        gnew = ghost_update<T>(su[tid], rv[0], acc, gc);
+          if (gid[q] >= 0) acc += gwt[q] * (double)gv[q];
+        uv[0] = ghost_update<T>(uv[0], rv[0], acc, gc);
       }
       __syncthreads();
-      if (upd) su[tid] = gnew;
+      if (upd) su[tid] = uv[0];
       __syncthreads();
     }
   }
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     const int e = tid + k * kChunkThreads;
-    if (e < ns && (mask[k] >> 31)) a.uout[node[k]] = su[e];
+    if (e < ns && (mask[k] >> 31)) a.uout[node[k]] = uv[k];
   }
 }
 
@@ -678,46 +691,55 @@ __device__ __forceinline__ void extend_one(const ExtRec& e, T* __restrict__ r) {
   r[e.node] = (T)(den > 0.0 ? num / den : 0.0);
 }
 
-// Extension chunk: the ghost defects the chunk reads are evaluated from u (the same
-// arithmetic as the ghost rows of the defect), then its extension nodes are computed DAG
-// level by DAG level (each value rounded to the defect's type, as when it is stored) and the
-// owned ones are written to r.  Each thread owns up to kChunkPerThread entries and keeps
-// their node index, DAG level, source ids and weights in registers; only the values are
-// shared, in LDS.
+// Extension chunk: the chunk's terms are staged in LDS while the defects of its ghost
+// sources are evaluated from u (the same arithmetic as the ghost rows of the defect, rounded
+// to the defect's type as when stored), one per thread; then every owned extension node
+// takes its composed combination of them (FP64, terms in ascending ghost order) and is
+// written to r.
 template <int D, typename T, typename TO>
 __device__ void extend_chunk(const DefectArgs<T, TO>& a, int c, unsigned char* lds) {
   constexpr int K = Pow3<D>::value;
   constexpr int NK = kChunkPerThread;
+  constexpr int NT = kExtMaxTerms / kChunkThreads;
   const int cu = __builtin_amdgcn_readfirstlane(c);
   int32_t hd[kExtHdr];
 #pragma unroll
   for (int q = 0; q < kExtHdr; ++q) hd[q] = a.hdr[(int64_t)cu * kExtHdr + q];
-  const int nt = hd[0], ngs = hd[1], nlvl = hd[7];
-  const int32_t* E = a.data + hd[2];
-  const int32_t* S = a.data + hd[3];
-  const double* W = (const double*)(a.data + hd[4]);
+  const int ne = hd[0], ngs = hd[1];
+  const int32_t* N = a.data + hd[2];
+  const int32_t* TOF = a.data + hd[3];
+  const int32_t* TS = a.data + hd[4];
+  const double* TW = (const double*)(a.data + hd[5]);
+  const int nterms = TOF[ne];
   const int tid = threadIdx.x;
-  int32_t node[NK], src[NK][2];
-  uint32_t meta[NK];
-  double w[NK][3];
+  double* sv = (double*)lds;
+  double* lw = sv + ngs;
+  int32_t* ls = (int32_t*)(lw + nterms);
+  // every global load of the chunk is issued before the first use
+  int32_t node[NK], t0[NK], t1[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     const int e = tid + k * kChunkThreads;
-    const int ec = e < nt ? e : 0;
-    node[k] = E[ec];
-    const uint32_t mt = (uint32_t)E[nt + ec];
-    meta[k] = e < nt ? mt : 0u;
-    src[k][0] = S[2 * ec];
-    src[k][1] = S[2 * ec + 1];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) w[k][q] = W[q * nt + ec];
+    const int ec = e < ne ? e : 0;
+    node[k] = N[ngs + ec];
+    t0[k] = TOF[ec];
+    t1[k] = e < ne ? TOF[ec + 1] : t0[k];
   }
-  double* sv = (double*)lds;
+  double tw[NT];
+  int32_t ts[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int i = tid + j * kChunkThreads;
+    const int ic = i < nterms ? i : 0;
+    tw[j] = TW[ic];
+    ts[j] = TS[ic];
+  }
+  const bool gsrc = tid < ngs;
+  const int tg = gsrc ? tid : 0;
+  double gv = 0.0;
   if (ngs > 0) {
-    const bool gsrc = tid < ngs;
-    const int tg = gsrc ? tid : 0;
-    const int32_t* gn = a.data + hd[5];
-    const double* gw = (const double*)(a.data + hd[6]);
+    const int32_t* gn = a.data + hd[6];
+    const double* gw = (const double*)(a.data + hd[7]);
     int32_t gnode[K];
     double gwt[K];
 #pragma unroll
@@ -725,36 +747,34 @@ __device__ void extend_chunk(const DefectArgs<T, TO>& a, int c, unsigned char* l
       gnode[q] = gn[q * ngs + tg];
       gwt[q] = gw[q * ngs + tg];
     }
+    const int32_t self = N[tg];
     double uq[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) uq[q] = (double)a.u[gnode[q]];
-    const double rG = (double)a.rhs[node[0]];
+    const double rG = (double)a.rhs[self];
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < K; ++q)
       if (gwt[q] != 0.0) acc += gwt[q] * uq[q];
-    if (gsrc) sv[tid] = (double)(TO)(rG - acc);
+    gv = (double)(TO)(rG - acc);
+  }
+  if (gsrc) sv[tid] = gv;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int i = tid + j * kChunkThreads;
+    if (i < nterms) {
+      lw[i] = tw[j];
+      ls[i] = ts[j];
+    }
   }
   __syncthreads();
-  for (int d = 1; d <= nlvl; ++d) {
 #pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      if ((int)(meta[k] & 0xffff) != d) continue;
-      double num = 0.0, den = 0.0;
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const int s = q < 2 ? (int16_t)((uint32_t)src[k][0] >> (16 * q)) : (int16_t)(src[k][1] & 0xffff);
-        if (s < 0) continue;
-        num += w[k][q] * sv[s];
-        den += w[k][q];
-      }
-      sv[tid + k * kChunkThreads] = (double)(TO)(den > 0.0 ? num / den : 0.0);
-    }
-    __syncthreads();
+  for (int k = 0; k < NK; ++k) {
+    if (tid + k * kChunkThreads >= ne) continue;
+    double v = 0.0;
+    for (int t = t0[k]; t < t1[k]; ++t) v += lw[t] * sv[ls[t]];
+    a.r[node[k]] = (TO)v;
   }
-#pragma unroll
-  for (int k = 0; k < NK; ++k)
-    if (meta[k] >> 31) a.r[node[k]] = (TO)sv[tid + k * kChunkThreads];
 }
 
 // One launch: extension chunks, then the active tiles (interior rows), then the ghost

@@ -1013,11 +1013,56 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
   return true;
 }
 
-// Extension chunks of level l: each chunk owns a Morton-ordered run of extension nodes,
-// carries every extension node they depend on (transitively through their upwind sources)
-// and the ghost nodes among the sources, whose defects it evaluates itself.  A chunk with
-// more than kChunkMaxEntries entries or kChunkThreads ghost sources is split in two;
-// returns false when a single node is still too large.
+// Composed extension weights of level l.  The records are stored in DAG order per problem,
+// so every source that is an extension node has its weights already: a record's weights are
+// those of its sources, each scaled by its normalised upwind weight wt_a / sum(wt), merged by
+// ghost node (ascending).  A record without sources has no terms (its value is 0).
+void compose_extension(const HostLevel& HL, const std::vector<int32_t>& eid,
+                       std::vector<int32_t>& off, std::vector<int32_t>& src,
+                       std::vector<double>& wt) {
+  const size_t ne = HL.ext.size();
+  off.assign(ne + 1, 0);
+  src.clear();
+  wt.clear();
+  std::vector<std::pair<int32_t, double>> m;
+  for (size_t i = 0; i < ne; ++i) {
+    const ExtRec& r = HL.ext[i];
+    double den = 0.0;
+    for (int a = 0; a < 3; ++a)
+      if (r.src[a] >= 0) den += r.wt[a];
+    m.clear();
+    for (int a = 0; a < 3 && den > 0.0; ++a) {
+      const int32_t q = r.src[a];
+      if (q < 0) continue;
+      const double f = r.wt[a] / den;
+      if (eid[q] < 0) {
+        m.push_back({q, f});
+        continue;
+      }
+      const int32_t j = eid[q];
+      for (int32_t t = off[j]; t < off[j + 1]; ++t) m.push_back({src[t], f * wt[t]});
+    }
+    std::stable_sort(m.begin(), m.end(),
+                     [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+                       return x.first < y.first;
+                     });
+    for (size_t k = 0; k < m.size(); ++k) {
+      if (k > 0 && m[k].first == m[k - 1].first) {
+        wt.back() += m[k].second;
+      } else {
+        src.push_back(m[k].first);
+        wt.push_back(m[k].second);
+      }
+    }
+    off[i + 1] = (int32_t)src.size();
+  }
+}
+
+// Extension chunks of level l: each chunk owns a Morton-ordered run of extension nodes and
+// the ghost nodes their composed weights name.  A chunk with more than kChunkMaxEntries
+// extension nodes, kChunkThreads ghost sources or kExtMaxTerms terms is split in two;
+// returns false when a single node is still too large, or a source is neither extension
+// node nor ghost.
 bool build_ext_chunks(mg_handle_s* H, int l, int own_target) {
   HostLevel& HL = H->host[l];
   const int D = H->dim;
@@ -1032,50 +1077,34 @@ bool build_ext_chunks(mg_handle_s* H, int l, int own_target) {
   std::vector<int32_t> eid(nn, -1), gidx(nn, -1);
   for (size_t i = 0; i < HL.ext.size(); ++i) eid[HL.ext[i].node] = (int32_t)i;
   for (size_t i = 0; i < HL.ghosts.size(); ++i) gidx[HL.ghosts[i].node] = (int32_t)i;
-  // DAG level of each extension record (ghost sources are level 0)
-  std::vector<int> dag(HL.ext.size(), 1);
-  for (size_t i = 0; i < HL.ext.size(); ++i)  // records are stored in DAG order per problem
-    for (int a = 0; a < 3; ++a) {
-      const int32_t q = HL.ext[i].src[a];
-      if (q >= 0 && eid[q] >= 0) dag[i] = std::max(dag[i], dag[eid[q]] + 1);
-    }
+  for (const ExtRec& r : HL.ext)
+    for (int a = 0; a < 3; ++a)
+      if (r.src[a] >= 0 && eid[r.src[a]] < 0 && gidx[r.src[a]] < 0) return false;
+  std::vector<int32_t> toff, tsrc;
+  std::vector<double> twt;
+  compose_extension(HL, eid, toff, tsrc, twt);
   std::vector<std::pair<uint64_t, int32_t>> U;
   for (size_t i = 0; i < HL.ext.size(); ++i)
     U.push_back({morton_key(g, D, HL.ext[i].node), (int32_t)i});
   std::sort(U.begin(), U.end());
   std::vector<std::pair<size_t, size_t>> pending = initial_runs(U, own_target);
   std::vector<int32_t> lid(nn, -1);
-  std::vector<char> in(HL.ext.size(), 0), own(HL.ext.size(), 0);
   while (!pending.empty()) {
     const auto [a, b] = pending.back();
     pending.pop_back();
-    std::vector<int32_t> ext_e, ghosts_e;
+    std::vector<int32_t> ghosts_e;
     for (size_t i = a; i < b; ++i) {
-      ext_e.push_back(U[i].second);
-      in[U[i].second] = 1;
-      own[U[i].second] = 1;
-    }
-    for (size_t k = 0; k < ext_e.size(); ++k)
-      for (int c = 0; c < 3; ++c) {
-        const int32_t q = HL.ext[ext_e[k]].src[c];
-        if (q < 0 || eid[q] < 0 || in[eid[q]]) continue;
-        in[eid[q]] = 1;
-        ext_e.push_back(eid[q]);
-      }
-    bool ok = true;
-    for (int32_t e : ext_e)
-      for (int c = 0; c < 3; ++c) {
-        const int32_t q = HL.ext[e].src[c];
-        if (q >= 0 && eid[q] < 0 && lid[q] == -1) {
-          if (gidx[q] < 0) ok = false;  // a source that is neither extension node nor ghost
-          lid[q] = -2;
-          ghosts_e.push_back(q);
+      const int32_t e = U[i].second;
+      for (int32_t t = toff[e]; t < toff[e + 1]; ++t)
+        if (lid[tsrc[t]] == -1) {
+          lid[tsrc[t]] = -2;
+          ghosts_e.push_back(tsrc[t]);
         }
-      }
-    const int ne = (int)ext_e.size(), ngs = (int)ghosts_e.size(), nt = ne + ngs;
-    ok = ok && nt <= kChunkMaxEntries && ngs <= kChunkThreads;
-    if (!ok) {
-      for (int32_t e : ext_e) in[e] = own[e] = 0;
+    }
+    const int ne = (int)(b - a), ngs = (int)ghosts_e.size();
+    int64_t nt = 0;
+    for (size_t i = a; i < b; ++i) nt += toff[U[i].second + 1] - toff[U[i].second];
+    if (ne > kChunkMaxEntries || ngs > kChunkThreads || nt > kExtMaxTerms) {
       for (int32_t q : ghosts_e) lid[q] = -1;
       if (b - a <= 1) return false;
       const size_t m = a + (b - a) / 2;
@@ -1083,43 +1112,34 @@ bool build_ext_chunks(mg_handle_s* H, int l, int own_target) {
       pending.push_back({a, m});
       continue;
     }
-    // entries: ghost sources (one per thread), then the extension nodes
     int k = 0;
     for (int32_t q : ghosts_e) lid[q] = k++;
-    for (int32_t e : ext_e) lid[HL.ext[e].node] = k++;
-    int nlvl = 0;
-    for (int32_t e : ext_e) nlvl = std::max(nlvl, dag[e]);
     std::vector<int32_t>& Dv = HL.ec_data;
     pad_even(Dv);
     const int32_t off = (int32_t)Dv.size();
     for (int32_t q : ghosts_e) Dv.push_back(q);
-    for (int32_t e : ext_e) Dv.push_back(HL.ext[e].node);
-    for (int j = 0; j < ngs; ++j) Dv.push_back(0);
-    for (int32_t e : ext_e) Dv.push_back((int32_t)((uint32_t)dag[e] | (own[e] ? 0x80000000u : 0u)));
-    const int32_t src_off = (int32_t)Dv.size();
-    for (int j = 0; j < ngs; ++j) {
-      Dv.push_back(pack16(-1, -1));
-      Dv.push_back(pack16(-1, -1));
+    for (size_t i = a; i < b; ++i) Dv.push_back(HL.ext[U[i].second].node);
+    const int32_t to_off = (int32_t)Dv.size();
+    int32_t nterms = 0;
+    for (size_t i = a; i < b; ++i) {
+      Dv.push_back(nterms);
+      nterms += toff[U[i].second + 1] - toff[U[i].second];
     }
-    for (int32_t e : ext_e) {
-      const ExtRec& r = HL.ext[e];
-      int s[3];
-      for (int c = 0; c < 3; ++c) s[c] = r.src[c] >= 0 ? lid[r.src[c]] : -1;
-      Dv.push_back(pack16(s[0], s[1]));
-      Dv.push_back(pack16(s[2], -1));
-    }
-    pad_even(Dv);
-    const int32_t w_off = (int32_t)Dv.size();
+    Dv.push_back(nterms);
+    const int32_t ts_off = (int32_t)Dv.size();
     std::vector<double> wv;
-    for (int c = 0; c < 3; ++c) {
-      for (int j = 0; j < ngs; ++j) wv.push_back(0.0);
-      for (int32_t e : ext_e) wv.push_back(HL.ext[e].wt[c]);
-    }
+    for (size_t i = a; i < b; ++i)
+      for (int32_t t = toff[U[i].second]; t < toff[U[i].second + 1]; ++t) {
+        Dv.push_back(lid[tsrc[t]]);
+        wv.push_back(twt[t]);
+      }
+    pad_even(Dv);
+    const int32_t tw_off = (int32_t)Dv.size();
     put_doubles(Dv, wv);
     const int32_t gn_off = (int32_t)Dv.size();
     for (int t = 0; t < K; ++t)
       for (int32_t q : ghosts_e) {
-        // taps of zero weight are skipped by the kernel; they name the ghost itself
+        // taps of zero weight name the ghost itself
         const GhostRec& r = HL.ghosts[gidx[q]];
         const bool used = HL.gw[(size_t)gidx[q] * K + t] != 0.0;
         const int64_t o = D == 2 ? template_offset<2>(t, r.s, g.st) : template_offset<3>(t, r.s, g.st);
@@ -1131,14 +1151,10 @@ bool build_ext_chunks(mg_handle_s* H, int l, int own_target) {
     for (int t = 0; t < K; ++t)
       for (int32_t q : ghosts_e) wv.push_back(HL.gw[(size_t)gidx[q] * K + t]);
     put_doubles(Dv, wv);
-    const int32_t hdr[kExtHdr] = {nt, ngs, off, src_off, w_off, gn_off, gw_off, nlvl};
+    const int32_t hdr[kExtHdr] = {ne, ngs, off, to_off, ts_off, tw_off, gn_off, gw_off};
     HL.ec_hdr.insert(HL.ec_hdr.end(), hdr, hdr + kExtHdr);
     ++HL.ec_nchunks;
-    HL.ec_smax = std::max(HL.ec_smax, nt);
-    for (int32_t e : ext_e) {
-      lid[HL.ext[e].node] = -1;
-      in[e] = own[e] = 0;
-    }
+    HL.ec_smax = std::max(HL.ec_smax, ngs + nterms + (nterms + 1) / 2);
     for (int32_t q : ghosts_e) lid[q] = -1;
   }
   return true;

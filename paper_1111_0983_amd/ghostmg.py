@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libghostmg.so")
 
 MG_OK, MG_EINVAL, MG_ENOMEM, MG_EHIP, MG_EGEOM, MG_ENOCONV, MG_EDIVERGED = 0, -1, -2, -3, -4, -5, -6
 MG_FP64, MG_FP32_DC = 0, 1
-KERNELS = {"relax": 0, "defect": 1, "restrict": 2, "prolong": 3, "residual": 4}
+KERNELS = {"relax": 0, "defect": 1, "restrict": 2, "prolong": 3, "residual": 4,
+           "relax_prolong": 5, "relax_restrict": 6}
 
 
 class mg_grid(ctypes.Structure):
@@ -53,6 +54,11 @@ class GhostMGError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # torch (and its HIP runtime) is loaded first, so that the library binds to the runtime
+    # that owns the tensors it is given; with the library loaded before torch, its HIP calls
+    # reported that no device was present
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
     lib.mg_grid_default.argtypes = [ctypes.POINTER(mg_grid), ctypes.c_int, ctypes.c_int, ctypes.c_int]

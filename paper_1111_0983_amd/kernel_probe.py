@@ -19,7 +19,8 @@ import sys
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--kernel", default="relax",
-                    choices=["relax", "defect", "restrict", "prolong", "residual"])
+                    choices=["relax", "defect", "restrict", "prolong", "residual",
+                             "relax_prolong", "relax_restrict"])
     ap.add_argument("--level", type=int, default=0)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--n", type=int, default=2048)

@@ -230,3 +230,26 @@ def test_repeat_solves_are_bitwise_identical():
         outs.append((u.cpu().numpy(), info["history"]))
     assert np.array_equal(outs[0][0], outs[1][0])
     assert outs[0][1] == outs[1][1]
+
+
+@pytest.mark.parametrize("name", ["flower256", "torus32"])
+def test_kernel_timing_leaves_solves_unchanged(name):
+    """mg_time_kernel launches every kernel of the cycle in isolation on every level (also the
+    fused relaxations); a solve afterwards is bitwise the solve of a fresh handle, and the
+    calls outside a kernel's valid levels are rejected."""
+    gm = _gm()
+    s, o, dom, dim, n, rule, sol = _build(name)
+    f, g = _rhs_gpu(s, dom, dim, n, sol)
+    u0 = torch.zeros(f.size, dtype=torch.float64, device=DEV)
+    ref = s.solve(_t(f), _t(g), u0, tol=1e-10)
+    for lev in range(s.nlev):
+        for k in gm.KERNELS:
+            if lev == s.nlev - 1 or (k == "relax_restrict" and lev == 0):
+                with pytest.raises(gm.GhostMGError):
+                    s.time_kernel(k, lev, 2)
+                continue
+            ms, nbytes = s.time_kernel(k, lev, 2)
+            assert ms > 0 and nbytes > 0, (k, lev)
+    u1 = torch.zeros_like(u0)
+    info = s.solve(_t(f), _t(g), u1, tol=1e-10)
+    assert torch.equal(u0, u1) and info["history"] == ref["history"]
