@@ -116,6 +116,24 @@ def step_fg(solver, uu, f, g):
     return solver.solve(f, g, uu, tol=1e-10)
 
 
+def measured_traffic(summary: str):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter summary (each
+    scaled by what the counter reads for a copy of known size), or None when the summary is
+    missing or the kernel sources changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    rec = json.loads(open(path).read().strip().splitlines()[-1])
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "setup.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_1111_0983_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != rec.get("source_sha"):
+        return None
+    return rec["traffic_bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,7 +203,8 @@ def main():
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": "k_relax<2,double> (finest level)", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "avg_us": round(k_ms * 1e3, 2), "bytes_per_launch": k_bytes}
+            "traffic": measured_traffic("k_relax_flower2048_level0_counters.txt"),
+            "avg_us": round(k_ms * 1e3, 2), "bytes_per_launch": k_bytes}
     # the launches of one V(2,1) cycle on every level (microseconds): the first
     # pre-relaxation restricts (coarse levels), the first post-relaxation interpolates
     per_level = {}

@@ -20,6 +20,11 @@ constexpr int kChunkThreads = 256;     // workgroup size of every chunk kernel
 constexpr int kChunkPerThread = 4;     // chunk entries owned by one thread
 constexpr int kChunkMaxEntries = kChunkPerThread * kChunkThreads;
 constexpr int kExtMaxTerms = 6 * kChunkThreads;  // composed extension terms per chunk
+// relaxation chunks: per thread one updated ghost, kBandColourSlots red and as many black
+// entries, kBandHaloSlots entries that are read but never updated
+constexpr int kBandColourSlots = 2;
+constexpr int kBandHaloSlots = 1;
+constexpr int kBandMaxEntries = (1 + 2 * kBandColourSlots + kBandHaloSlots) * kChunkThreads;
 
 // Tile shapes of the node-parallel kernels: 64 x 16 nodes in 2D, 16 x 8 x 8 in 3D.
 template <int D>
@@ -76,18 +81,23 @@ struct HostLevel {
   // Relaxation chunks: each chunk owns band and ghost nodes and carries every node that
   // their values after the whole relaxation depend on, through its 3 + 3 lambda phases
   // (red interior, black interior, ghosts; lambda times red band, black band, ghosts).
-  // Entry e of a chunk belongs to thread e % kChunkThreads; the updated ghosts come first
-  // (at most one per thread).  Chunk c: header bc_hdr[c * kBandHdr ..] = {entries, updated
-  // ghosts, offsets into bc_data of: the per-entry arrays, the ghost stencil ids, the ghost
+  // Entries come in four runs: the updated ghosts (at most kChunkThreads), the entries the
+  // red phases update, those the black phases update (at most kBandColourSlots *
+  // kChunkThreads each), and the entries only read (at most kBandHaloSlots * kChunkThreads);
+  // entry i of a run belongs to thread i % kChunkThreads.  Chunk c: header
+  // bc_hdr[c * kBandHdr ..] = {entries, updated ghosts | red << 10 | black << 20, offsets
+  // into bc_data of: the per-entry arrays, the ghost stencil ids, the ghost
   // weights, the ghost constants, the interpolation candidates (-1 on the coarsest level)
-  // and the restriction data (-1 on the finest level)}: per entry 2^D coarse
-  // node indices of its interpolation candidates (-1: absent or no unknown; the weight
-  // exponent is in mask bits 28-29), and 2 words: the fine node index of (2x, 2y, 2z) and
-  // the restriction code.  Per-entry arrays (int32 words): node index;
-  // phase mask (bit p: updated in phase p; bit 31: owned, written to the output); D words of
+  // and the restriction data (-1 on the finest level)}: per entry the coarse node index of
+  // its interpolation candidate 0 (candidate m adds the coarse stride of each axis q with bit
+  // q of m), and 2 words: the fine node index of (2x, 2y, 2z) and the restriction code.
+  // Per-entry arrays (int32 words): node index; mask (bit p < P: updated in phase p of the
+  // P = 3 + 3 lambda; bits [P, P + D): odd coordinates; bits [P + D, P + D + 2^D):
+  // interpolation candidate m exists and carries an unknown; bit 31: owned, written to the
+  // output); D words of
   // (minus, plus) int16 local neighbour ids per axis.  Per ghost (tap-major, ghost fastest):
-  // Pow3<D> local stencil ids (-1 for taps of zero weight) and FP64 weights; one FP64
-  // constant c_G.
+  // Pow3<D> local stencil ids (the ghost's own id for taps of zero weight) and FP64 weights
+  // (0 for those taps); one FP64 constant c_G.
   std::vector<int32_t> bc_hdr;
   std::vector<int32_t> bc_data;
   int bc_nchunks = 0, bc_smax = 0, bc_nown = 0;

@@ -412,40 +412,140 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
 // ---------------------------------------------------------------------------------------
 // The chunk's node set is closed under the dependencies of its owned nodes (band and
 // ghost nodes) through the 3 + 3 lambda phases (red interior, black interior, ghosts; then
-// lambda times red band, black band, ghosts, Sec. 3.2).  Each thread owns up to
-// kChunkPerThread entries and keeps their node index, phase mask, neighbour ids and
-// right-hand side in registers (the thread owning an updated ghost also keeps its stencil
-// ids, weights and constant); only the node values are shared, in LDS.  Phases are separated
-// by workgroup barriers; a ghost phase computes every new ghost value before any is stored.
-// The owned entries are written to uout.
+// lambda times red band, black band, ghosts, Sec. 3.2).  Its entries come in runs: updated
+// ghosts, red-updated, black-updated, read-only; a thread holds one ghost, kBandColourSlots
+// red and black entries and kBandHaloSlots read-only entries (slot s of a run: entry
+// tid + s * kChunkThreads of the run), with their node index, phase mask, neighbour ids,
+// right-hand side and current value in registers (the ghost also its stencil ids, weights
+// and constant); only the values are shared, in LDS.  A phase updates at most
+// kBandColourSlots entries per thread (one ghost in a ghost phase) and issues all its LDS
+// reads before its writes: no update reads a value of its own phase (red reads black and
+// ghosts, black reads red and ghosts, the ghosts read the values before their phase).
+// Phases are separated by workgroup barriers; a ghost phase computes every new ghost value
+// before any is stored.  The owned entries are written to uout.
 template <int D, typename T, int MODE>
 __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
   constexpr bool PROLONG = MODE == kRelaxProlong, RESTRICT = MODE == kRelaxRestrict;
   constexpr int K = Pow3<D>::value;
-  constexpr int NK = kChunkPerThread;
-  // the header is uniform over the workgroup; every per-entry load below is issued without
-  // a branch (entries past the end read entry 0 and are masked off)
+  constexpr int NC = kBandColourSlots, NH = kBandHaloSlots;
+  constexpr int NS = 1 + 2 * NC + NH;  // slots: ghost, red, black, read-only
+  constexpr int NCAND = 1 << D;
   const int cu = __builtin_amdgcn_readfirstlane(c);
   int32_t hd[kBandHdr];
 #pragma unroll
   for (int q = 0; q < kBandHdr; ++q) hd[q] = a.hdr[(int64_t)cu * kBandHdr + q];
-  const int ns = hd[0], ng = hd[1];
+  const int ns = hd[0], ng = hd[1] & 1023, nr = (hd[1] >> 10) & 1023, nb = (hd[1] >> 20) & 1023;
   const int32_t* E = a.data + hd[2];
   const int tid = threadIdx.x;
-  int32_t node[NK];
-  uint32_t mask[NK];
-  int32_t nbw[NK][D];
+  // slot s: its run start and length
+  int e_of[NS];
+  bool ok_of[NS];
 #pragma unroll
-  for (int k = 0; k < NK; ++k) {
-    const int e = tid + k * kChunkThreads;
-    const int ec = e < ns ? e : 0;
-    node[k] = E[ec];
-    const uint32_t mk = (uint32_t)E[ns + ec];
-    mask[k] = e < ns ? mk : 0u;
-#pragma unroll
-    for (int q = 0; q < D; ++q) nbw[k][q] = E[2 * ns + ec * D + q];
+  for (int s = 0; s < NS; ++s) {
+    int start, len, j;
+    if (s == 0) {
+      start = 0, len = ng, j = 0;
+    } else if (s <= NC) {
+      start = ng, len = nr, j = s - 1;
+    } else if (s <= 2 * NC) {
+      start = ng + nr, len = nb, j = s - 1 - NC;
+    } else {
+      start = ng + nr + nb, len = ns - ng - nr - nb, j = s - 1 - 2 * NC;
+    }
+    const int i = tid + j * kChunkThreads;
+    ok_of[s] = i < len;
+    e_of[s] = ok_of[s] ? start + i : 0;
   }
-  const bool ghost = tid < ng;
+  int32_t node[NS];
+  uint32_t mask[NS];
+  int32_t nbw[NS][D];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int ec = e_of[s];
+    node[s] = E[ec];
+    const uint32_t mk = (uint32_t)E[ns + ec];
+    mask[s] = ok_of[s] ? mk : 0u;
+    if (s >= 1 && s <= 2 * NC) {
+#pragma unroll
+      for (int q = 0; q < D; ++q) nbw[s][q] = E[2 * ns + ec * D + q];
+    }
+  }
+  const bool ghost = ok_of[0];
+  int32_t pcb[NS];
+  int32_t rf0[NS], rcd[NS];
+  if constexpr (RESTRICT) {
+    // fine node index of (2x, 2y, 2z) and restriction code of every updated entry
+    const int32_t* RS = a.data + hd[7];
+#pragma unroll
+    for (int s = 0; s < NS - NH; ++s) {
+      rf0[s] = RS[2 * e_of[s]];
+      rcd[s] = RS[2 * e_of[s] + 1];
+    }
+  }
+  if constexpr (PROLONG) {
+    // coarse index of every entry's interpolation candidate 0
+    const int32_t* PC = a.data + hd[6];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) pcb[s] = PC[e_of[s]];
+  }
+  T rv[NS], uv[NS];
+  T* su = (T*)lds;
+  if constexpr (RESTRICT) {
+    // the relaxation starts from zero with the right-hand side restricted from the finer
+    // level's defect (the tiles store it for the level's later launches)
+    constexpr int KT = Pow3<D>::value;
+    T rr[NS - NH][KT];
+#pragma unroll
+    for (int s = 0; s < NS - NH; ++s)
+      restrict_gather<D, T>(a.rf, rf0[s], a.gf, (uint8_t)rcd[s], rr[s]);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      uv[s] = 0;
+      rv[s] = s < NS - NH ? restrict_box<D, T>((uint8_t)rcd[s], rr[s]) : (T)0;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      uv[s] = a.uin[node[s]];
+      rv[s] = s < NS - NH ? a.rhs[node[s]] : (T)0;
+    }
+  }
+  if constexpr (PROLONG) {
+    // candidate bits from the mask (odd coordinates, candidates with an unknown)
+    const int P = a.phases;
+    T pe[NS][NCAND];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const uint32_t cb = mask[s] >> (P + D);
+#pragma unroll
+      for (int m = 0; m < NCAND; ++m) {
+        int idx = pcb[s];
+#pragma unroll
+        for (int q = 0; q < D; ++q)
+          if ((m >> q) & 1) idx += (int)a.gc.st[q];
+        pe[s][m] = a.uc[(cb >> m) & 1u ? idx : 0];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      T w1 = 1;
+      const int nodd = __popc((mask[s] >> P) & ((1u << D) - 1u));
+      for (int q = 0; q < nodd; ++q) w1 *= (T)0.5;
+      const uint32_t cb = mask[s] >> (P + D);
+      T w[NCAND];
+      int8_t cc[NCAND];
+#pragma unroll
+      for (int m = 0; m < NCAND; ++m) {
+        w[m] = (cb >> m) & 1u ? w1 : (T)0;
+        cc[m] = (cb >> m) & 1u ? 1 : 0;
+      }
+      uv[s] = prolong_correct<D, T>(uv[s], w, cc, pe[s]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+    if (ok_of[s]) su[e_of[s]] = uv[s];
+  // the ghost rows are first needed in phase 2: loaded after the values (registers)
   int32_t gid[K];
   double gwt[K];
   double gc = 0.0;
@@ -460,116 +560,40 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
     }
     gc = ((const double*)(a.data + hd[5]))[tg];
   }
-  constexpr int NCAND = 1 << D;
-  int32_t pci[NK][NCAND];
-  int32_t rf0[NK], rcd[NK];
-  if constexpr (RESTRICT) {
-    // fine node index of (2x, 2y, 2z) and restriction code of every entry
-    const int32_t* RS = a.data + hd[7];
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      const int e = tid + k * kChunkThreads;
-      const int ec = e < ns ? e : 0;
-      rf0[k] = RS[2 * ec];
-      rcd[k] = RS[2 * ec + 1];
-    }
-  }
-  if constexpr (PROLONG) {
-    // interpolation candidates of every entry, resolved on the host (-1: none)
-    const int32_t* PC = a.data + hd[6];
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      const int e = tid + k * kChunkThreads;
-      const int ec = e < ns ? e : 0;
-#pragma unroll
-      for (int m = 0; m < NCAND; ++m) pci[k][m] = PC[ec * NCAND + m];
-    }
-  }
-  T rv[NK], uv[NK];
-  T* su = (T*)lds;
-  if constexpr (RESTRICT) {
-    // the relaxation starts from zero with the right-hand side restricted from the finer
-    // level's defect (the tiles store it for the level's later launches)
-    constexpr int KT = Pow3<D>::value;
-    T rr[NK][KT];
-#pragma unroll
-    for (int k = 0; k < NK; ++k)
-      restrict_gather<D, T>(a.rf, rf0[k], a.gf, (uint8_t)rcd[k], rr[k]);
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      uv[k] = 0;
-      rv[k] = restrict_box<D, T>((uint8_t)rcd[k], rr[k]);
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      uv[k] = a.uin[node[k]];
-      rv[k] = a.rhs[node[k]];
-    }
-  }
-  if constexpr (PROLONG) {
-    T pe[NK][NCAND];
-#pragma unroll
-    for (int k = 0; k < NK; ++k)
-#pragma unroll
-      for (int m = 0; m < NCAND; ++m) pe[k][m] = a.uc[pci[k][m] >= 0 ? pci[k][m] : 0];
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      T w1 = 1;
-      const int nodd = (int)((mask[k] >> 28) & 3u);
-      for (int q = 0; q < nodd; ++q) w1 *= (T)0.5;
-      T w[NCAND];
-      int8_t cc[NCAND];
-#pragma unroll
-      for (int m = 0; m < NCAND; ++m) {
-        w[m] = pci[k][m] >= 0 ? w1 : (T)0;
-        cc[m] = pci[k][m] >= 0 ? 1 : 0;
-      }
-      uv[k] = prolong_correct<D, T>(uv[k], w, cc, pe[k]);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < NK; ++k) {
-    const int e = tid + k * kChunkThreads;
-    if (e < ns) su[e] = uv[k];
-  }
   __syncthreads();
-  // Only the owning thread writes an entry's slot, so uv[] stays the entry's current value.
-  // No update of a phase reads a value the same phase writes (red reads black and ghosts,
-  // black reads red and ghosts, the ghosts read the values before their phase), so each
-  // phase issues all its LDS reads before any of its writes; inactive entries read their
-  // own slot.
   for (int p = 0; p < a.phases; ++p) {
-    if (p % 3 != 2) {
-      bool act[NK];
-      T nv[NK][2 * D];
+    const int colour = p % 3;  // 0 red, 1 black, 2 ghosts
+    if (colour != 2) {
+      const int s0 = colour == 0 ? 1 : 1 + NC;
+      bool act[NC];
+      T nv[NC][2 * D];
 #pragma unroll
-      for (int k = 0; k < NK; ++k) {
-        act[k] = (mask[k] >> p) & 1u;
-        const int self = act[k] ? tid + k * kChunkThreads : 0;
+      for (int j = 0; j < NC; ++j) {
+        act[j] = (mask[s0 + j] >> p) & 1u;
 #pragma unroll
         for (int q = 0; q < D; ++q) {
-          nv[k][2 * q] = su[act[k] ? (int)(int16_t)(nbw[k][q] & 0xffff) : self];
-          nv[k][2 * q + 1] = su[act[k] ? (int)(int16_t)((uint32_t)nbw[k][q] >> 16) : self];
+          const uint32_t w = (uint32_t)nbw[s0 + j][q];
+          nv[j][2 * q] = su[act[j] ? (int)(int16_t)(w & 0xffff) : 0];
+          nv[j][2 * q + 1] = su[act[j] ? (int)(int16_t)(w >> 16) : 0];
         }
       }
 #pragma unroll
-      for (int k = 0; k < NK; ++k) {
-        if (!act[k]) continue;
-        uv[k] = interior_update<D, T>(uv[k], nv[k], rv[k], a.h2, a.inv2d);
-        su[tid + k * kChunkThreads] = uv[k];
+      for (int j = 0; j < NC; ++j) {
+        if (!act[j]) continue;
+        uv[s0 + j] = interior_update<D, T>(uv[s0 + j], nv[j], rv[s0 + j], a.h2, a.inv2d);
+        su[e_of[s0 + j]] = uv[s0 + j];
       }
       __syncthreads();
     } else {
       const bool upd = ghost && ((mask[0] >> p) & 1u);
       if (upd) {
+        // taps of zero weight name the ghost itself
         T gv[K];
 #pragma unroll
-        for (int q = 0; q < K; ++q) gv[q] = su[gid[q] >= 0 ? gid[q] : tid];
+        for (int q = 0; q < K; ++q) gv[q] = su[gid[q]];
         double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < K; ++q)
-          if (gid[q] >= 0) acc += gwt[q] * (double)gv[q];
+        for (int q = 0; q < K; ++q) acc += gwt[q] * (double)gv[q];
         uv[0] = ghost_update<T>(uv[0], rv[0], acc, gc);
       }
       __syncthreads();
@@ -578,10 +602,8 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
     }
   }
 #pragma unroll
-  for (int k = 0; k < NK; ++k) {
-    const int e = tid + k * kChunkThreads;
-    if (e < ns && (mask[k] >> 31)) a.uout[node[k]] = uv[k];
-  }
+  for (int s = 0; s < NS - NH; ++s)
+    if (mask[s] >> 31) a.uout[node[s]] = uv[s];
 }
 
 // CHUNKS: the level has relaxation chunks (workgroups [0, nchunks)).  MODE kRelaxProlong:

@@ -790,8 +790,8 @@ std::vector<std::pair<size_t, size_t>> initial_runs(const std::vector<std::pair<
 // band), 3k + 2 (ghosts).  The nodes written by the boundary part (band and ghost nodes) are
 // split into Morton-ordered runs; each run's node set S is closed backwards over the phases:
 // a node whose value after phase t is needed, and which phase t updates, needs the values
-// after phase t - 1 of every node it reads.  A chunk with more than kChunkMaxEntries nodes or
-// kChunkThreads updated ghosts is split in two.  Returns false when a small run is still too
+// after phase t - 1 of every node it reads.  A chunk with more updated ghosts, red or black
+// entries or read-only entries than its threads hold is split in two.  Returns false when a small run is still too
 // large, when the phases do not fit the 31 bits of a phase mask, or when the redundant work
 // exceeds max_redundancy times the owned nodes (the level then relaxes its boundary part
 // with one launch per phase).
@@ -808,7 +808,8 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
   HL.bc_smax = 0;
   HL.bc_entries = 0;
   HL.bc_nown = 0;
-  if (P > 28) return false;  // mask bits 28-29 hold the interpolation weight exponent
+  // mask bits: P phases, then D + 2^D interpolation bits, bit 31 owned
+  if (P + D + (1 << D) > 31) return false;
   // role of a node: 1 red band, 2 black band, 3 ghost, 4 red interior off the band,
   // 5 black interior off the band
   std::vector<int8_t> role(nn, 0);
@@ -879,16 +880,27 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
         }
       }
     }
-    // entries: the updated ghosts (one per thread), then every other node, by node index
+    // entries: the updated ghosts, the red-updated, the black-updated, the read-only nodes;
+    // each run by node index
+    auto run_of = [&](int32_t v) {
+      if (role[v] == 3 && need[v] >= 2) return 0;
+      if ((role[v] == 1 || role[v] == 4) && need[v] >= 0) return 1;
+      if ((role[v] == 2 || role[v] == 5) && need[v] >= 1) return 2;
+      return 3;
+    };
     std::sort(touched.begin(), touched.end(), [&](int32_t x, int32_t y) {
-      const bool gx = role[x] == 3 && need[x] >= 2, gy = role[y] == 3 && need[y] >= 2;
-      if (gx != gy) return gx;
+      const int rx = run_of(x), ry = run_of(y);
+      if (rx != ry) return rx < ry;
       return x < y;
     });
     const int ns = (int)touched.size();
-    int ng = 0;
-    while (ng < ns && role[touched[ng]] == 3 && need[touched[ng]] >= 2) ++ng;
-    bool ok = ns <= kChunkMaxEntries && ng <= kChunkThreads;
+    int cnt[4] = {0, 0, 0, 0};
+    for (int32_t v : touched) ++cnt[run_of(v)];
+    const int ng = cnt[0], nr = cnt[1], nbk = cnt[2];
+    bool ok = ng <= kChunkThreads && nr <= kBandColourSlots * kChunkThreads &&
+              nbk <= kBandColourSlots * kChunkThreads && cnt[3] <= kBandHaloSlots * kChunkThreads;
+    for (int32_t v : touched)
+      if (owned[v] && run_of(v) == 3) ok = false;  // an owned node is always updated
     if (ok) {
       for (int i = 0; i < ns; ++i) lid[touched[i]] = i;
       for (int i = 0; i < ns && ok; ++i) {
@@ -932,9 +944,10 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
         const int hi = relaxed && lid[v + g.st[a2]] >= 0 ? lid[v + g.st[a2]] : 0;
         Dv.push_back(pack16(lo, hi));
       }
-    // interpolation candidates of every entry (Sec. 2.6.1): candidate m (bit q: upper
-    // neighbour along axis q) as a coarse node index, or -1 where it does not exist or
-    // carries no unknown; the weight 2^-(odd coordinates) goes into mask bits 28-29
+    // interpolation candidates of every entry (Sec. 2.6.1): one word, the coarse node index
+    // of candidate 0 (candidate m adds the coarse stride of every axis q with bit q of m);
+    // mask bits [P, P + D): the odd coordinates (weight 2^-count), bits [P + D, P + D + 2^D):
+    // candidate m exists and carries an unknown
     const int32_t pc_off = (int32_t)Dv.size();
     if (l < H->L) {
       const HostLevel& HC = H->host[l + 1];
@@ -943,35 +956,32 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
         int64_t p;
         int j[3];
         node_coords(g, D, touched[i], &p, j);
-        int nodd = 0;
-        for (int q = 0; q < D; ++q) nodd += j[q] & 1;
-        Dv[off + ns + i] |= (int32_t)((uint32_t)nodd << 28);
+        uint32_t bits = 0;
+        int jb[3] = {0, 0, 0};
+        for (int q = 0; q < D; ++q) {
+          if (j[q] & 1) bits |= 1u << q;
+          jb[q] = (j[q] & 1) ? (j[q] - 1) >> 1 : j[q] >> 1;
+        }
         for (int m = 0; m < NC; ++m) {
           bool exists = true;
-          int jc[3] = {0, 0, 0};
+          int jc[3] = {jb[0], jb[1], jb[2]};
           for (int q = 0; q < D; ++q) {
             const int bit = (m >> q) & 1;
-            if ((j[q] & 1) == 0) {
-              if (bit) exists = false;
-              jc[q] = j[q] >> 1;
-            } else {
-              jc[q] = bit ? (j[q] + 1) >> 1 : (j[q] - 1) >> 1;
-            }
+            if (bit && (j[q] & 1) == 0) exists = false;
+            jc[q] += bit;
           }
-          int32_t X = -1;
-          if (exists) {
-            const int64_t c = p * HC.g.npp + jc[0] + HC.g.st[1] * jc[1] + HC.g.st[2] * jc[2];
-            if (HC.cls[c] != 0) X = (int32_t)c;
-          }
-          Dv.push_back(X);
+          if (exists && HC.cls[p * HC.g.npp + jc[0] + HC.g.st[1] * jc[1] + HC.g.st[2] * jc[2]] != 0)
+            bits |= 1u << (D + m);
         }
+        Dv[off + ns + i] |= (int32_t)(bits << P);
+        Dv.push_back((int32_t)(p * HC.g.npp + jb[0] + HC.g.st[1] * jb[1] + HC.g.st[2] * jb[2]));
       }
     }
     const int32_t gid_off = (int32_t)Dv.size();
     for (int t = 0; t < K; ++t)
       for (int j = 0; j < ng; ++j) {
         const double w = HL.gw[(size_t)gidx[touched[j]] * K + t];
-        Dv.push_back(w != 0.0 ? lid[tap_node(touched[j], t)] : -1);
+        Dv.push_back(w != 0.0 ? lid[tap_node(touched[j], t)] : j);
       }
     pad_even(Dv);
     const int32_t gw_off = (int32_t)Dv.size();
@@ -996,8 +1006,8 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
         Dv.push_back((int32_t)HL.rcode[touched[i]]);
       }
     }
-    const int32_t hdr[kBandHdr] = {ns, ng, off, gid_off, gw_off, gc_off, l < H->L ? pc_off : -1,
-                                   l > 0 ? rs_off : -1};
+    const int32_t hdr[kBandHdr] = {ns, ng | (nr << 10) | (nbk << 20), off, gid_off, gw_off, gc_off,
+                                   l < H->L ? pc_off : -1, l > 0 ? rs_off : -1};
     HL.bc_hdr.insert(HL.bc_hdr.end(), hdr, hdr + kBandHdr);
     ++HL.bc_nchunks;
     HL.bc_entries += ns;
