@@ -3,7 +3,8 @@
 Workload (the single-GPU headline configuration): 2D flower r < 0.5 + 0.15 sin(5 theta)
 on [-1, 1]^2 with 2048 x 2048 intervals, Dirichlet where x > 0 and Neumann elsewhere,
 manufactured u = sin(3x) cos(2y) + x y, V(2,1) cycles with lambda = 5 boundary sweeps down
-to a 32 x 32 coarsest grid, zero initial guess, until ||r||_inf / ||(f_h, g_h)||_inf <= 1e-10.
+to a 128 x 128 coarsest grid (5 levels; --nc), zero initial guess, until
+||r||_inf / ||(f_h, g_h)||_inf <= 1e-10.
 One step = one complete solve (mg_solve) with inputs resident in HBM.
 
 Prints one JSON line on stdout.  Extra fields: the FP32-in-FP64 defect-correction solve of
@@ -140,6 +141,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--nc", type=int, default=128, help="coarsest grid (intervals per axis)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dc", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
@@ -164,7 +166,7 @@ def main():
     t0 = time.time()
     phi = w.domain.nodal_phi(n)
     log(f"[bench] phi {n}^2 in {time.time() - t0:.1f}s")
-    grid = gm.mg_grid_default(2, n, 32)
+    grid = gm.mg_grid_default(2, n, args.nc)
     t0 = time.time()
     s = gm.Solver(torch.from_numpy(phi).to(dev), [w.rule], grid)
     setup_s = time.time() - t0
@@ -215,12 +217,16 @@ def main():
             ms_k, _ = s.time_kernel(name, lev, 20)
             row[name] = round(ms_k * 1e3, 2)
         per_level[str(lev)] = row
+    # the coarsest level: the restriction into it and the solve with the inverse
+    per_level[str(s.nlev - 1)] = {
+        "restrict_into": round(s.time_kernel("restrict", s.nlev - 2, 20)[0] * 1e3, 2),
+        "coarse": round(s.time_kernel("coarse", s.nlev - 1, 20)[0] * 1e3, 2)}
     roof["launch_us_by_level"] = per_level
     log(f"[bench] k_relax level 0: {k_ms * 1e3:.2f} us, {achieved:.0f} GB/s; per level {per_level}")
 
     extra = {}
     if not args.no_dc:
-        gdc = gm.mg_grid_default(2, n, 32, precision=gm.MG_FP32_DC, inner_cycles=2)
+        gdc = gm.mg_grid_default(2, n, args.nc, precision=gm.MG_FP32_DC, inner_cycles=2)
         sdc = gm.Solver(torch.from_numpy(phi).to(dev), [w.rule], gdc)
         udc = torch.zeros_like(f)
         for _ in range(args.warmup):
@@ -250,7 +256,7 @@ def main():
         from oracle import Oracle, default_grid
 
         t0 = time.perf_counter()
-        o = Oracle(phi, default_grid(2, n, 32), w.rule)
+        o = Oracle(phi, default_grid(2, n, args.nc), w.rule)
         oc, _ = o.cls(0)
         OG = o.ghosts(0)
         rhs = pr.rhs_from_ghosts(2, n, oc, OG["node"], OG["B"], OG["type"], w.solution, w.domain)
@@ -269,7 +275,7 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
-           "config": {"workload": f"flower-{n} 2D FP64 V(2,1) lambda=5 Nc=32 tol=1e-10 zero guess",
+           "config": {"workload": f"flower-{n} 2D FP64 V(2,1) lambda=5 Nc={args.nc} tol=1e-10 zero guess",
                       "n": n, "unknowns": unknowns, "cycles": info["cycles"],
                       "rel_residual": info["rel"], "max_error_vs_exact": err,
                       "setup_s": round(setup_s, 3), "parallelism": "single GPU"},

@@ -418,6 +418,9 @@ void time_launch(mg_handle_s* h, int kernel, int level, int i, hipStream_t s) {
                          h->batch, s, nullptr, nullptr, &F, Arr<T>::r(F));
       break;
     }
+    case 7:
+      launch_coarse<T>(L, Arr<T>::rhs(L), Arr<T>::u(L, 0), h->batch, s);
+      break;
     default:
       launch_defect<D, T, T>(L, u, Arr<T>::rhs(L), Arr<T>::r(L), h->norms, false, h->batch, s);
   }
@@ -665,8 +668,9 @@ int mg_residual(mg_handle_t h, const double* f, const double* g, const double* u
 }
 
 int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_ms, double* bytes) {
-  // the coarsest level is solved directly: none of these kernels runs there
-  if (!h || level < 0 || level >= h->L || reps < 1 || kernel < 0 || kernel > 6) return MG_EINVAL;
+  // the coarsest level is solved directly (kernel 7 only), the others relax
+  if (!h || level < 0 || level > h->L || reps < 1 || kernel < 0 || kernel > 7) return MG_EINVAL;
+  if ((kernel == 7) != (level == h->L)) return MG_EINVAL;
   if (kernel == 6 && level == 0) return MG_EINVAL;
   hipStream_t s = stream_of(h);
   DevLevel& L = h->dev[level];
@@ -706,6 +710,14 @@ int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_m
           ((double)F.nint + (double)F.nghost + (double)F.ext.size()) * sz;
     }
     if (kernel == 1) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0 + (double)S.ext.size() * (sz + 24.0);
+    if (kernel == 7) {
+      // the FP64 inverse of every problem, plus its right-hand side gathered and u written
+      b = 0.0;
+      for (int p = 0; p < h->batch; ++p) {
+        const double m = (double)(S.umap_off[p + 1] - S.umap_off[p]);
+        b += 8.0 * m * m + m * (2.0 * sz + 8.0);
+      }
+    }
     if (kernel == 4) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0;
     if (kernel == 2) {
       const HostLevel& C = h->host[level + 1];

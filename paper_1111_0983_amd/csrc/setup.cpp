@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "ghostmg_impl.h"
 
@@ -417,9 +418,18 @@ uint8_t box_code(const PL& F, const int jf[3], bool inside, int lab) {
 
 // Explicit inverse of the coarsest system by LU with partial pivoting (FP64).
 int invert(std::vector<double>& A, int n, std::vector<double>& inv) {
+  // LU with partial pivoting, then the inverse column by column.  The rows of the coarsest
+  // system couple nodes a few grid rows apart, so the factors are banded: every loop runs
+  // over the nonzero span of its row only (the same operations as the dense loops, minus
+  // those on zeros), and the columns of the inverse are solved on several threads.
   std::vector<int> piv(n);
   double amax = 0.0;
   for (double v : A) amax = std::max(amax, std::fabs(v));
+  auto last_nz = [&](int r) {
+    int j = n - 1;
+    while (j > r && A[(size_t)r * n + j] == 0.0) --j;
+    return j;
+  };
   for (int k = 0; k < n; ++k) {
     int p = k;
     double pv = std::fabs(A[(size_t)k * n + k]);
@@ -433,31 +443,52 @@ int invert(std::vector<double>& A, int n, std::vector<double>& inv) {
     if (p != k)
       for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
     const double d = A[(size_t)k * n + k];
+    const int ub = last_nz(k);
     for (int i = k + 1; i < n; ++i) {
+      if (A[(size_t)i * n + k] == 0.0) continue;
       const double m = A[(size_t)i * n + k] / d;
       A[(size_t)i * n + k] = m;
-      if (m != 0.0)
-        for (int j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= m * A[(size_t)k * n + j];
+      double* ri = &A[(size_t)i * n];
+      const double* rk = &A[(size_t)k * n];
+      for (int j = k + 1; j <= ub; ++j) ri[j] -= m * rk[j];
     }
   }
+  // spans of the factors: L row i from lo[i], U row i up to hi[i]
+  std::vector<int> lo(n), hi(n);
+  for (int i = 0; i < n; ++i) {
+    int j = 0;
+    while (j < i && A[(size_t)i * n + j] == 0.0) ++j;
+    lo[i] = j;
+    hi[i] = last_nz(i);
+  }
   inv.assign((size_t)n * n, 0.0);
-  std::vector<double> x(n);
-  for (int c = 0; c < n; ++c) {
-    for (int i = 0; i < n; ++i) x[i] = 0.0;
-    x[c] = 1.0;
-    for (int k = 0; k < n; ++k)
-      if (piv[k] != k) std::swap(x[k], x[piv[k]]);
-    for (int i = 0; i < n; ++i) {
-      double s = x[i];
-      for (int j = 0; j < i; ++j) s -= A[(size_t)i * n + j] * x[j];
-      x[i] = s;
+  auto solve_cols = [&](int c0, int c1) {
+    std::vector<double> x(n);
+    for (int c = c0; c < c1; ++c) {
+      for (int i = 0; i < n; ++i) x[i] = 0.0;
+      x[c] = 1.0;
+      for (int k = 0; k < n; ++k)
+        if (piv[k] != k) std::swap(x[k], x[piv[k]]);
+      for (int i = 0; i < n; ++i) {
+        double s = x[i];
+        for (int j = lo[i]; j < i; ++j) s -= A[(size_t)i * n + j] * x[j];
+        x[i] = s;
+      }
+      for (int i = n - 1; i >= 0; --i) {
+        double s = x[i];
+        for (int j = i + 1; j <= hi[i]; ++j) s -= A[(size_t)i * n + j] * x[j];
+        x[i] = s / A[(size_t)i * n + i];
+      }
+      for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = x[i];
     }
-    for (int i = n - 1; i >= 0; --i) {
-      double s = x[i];
-      for (int j = i + 1; j < n; ++j) s -= A[(size_t)i * n + j] * x[j];
-      x[i] = s / A[(size_t)i * n + i];
-    }
-    for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = x[i];
+  };
+  const int nt = n < 512 ? 1 : (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (nt == 1) {
+    solve_cols(0, n);
+  } else {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(solve_cols, (int)((int64_t)n * t / nt), (int)((int64_t)n * (t + 1) / nt));
+    for (auto& x : th) x.join();
   }
   return MG_OK;
 }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libghostmg.so")
 MG_OK, MG_EINVAL, MG_ENOMEM, MG_EHIP, MG_EGEOM, MG_ENOCONV, MG_EDIVERGED = 0, -1, -2, -3, -4, -5, -6
 MG_FP64, MG_FP32_DC = 0, 1
 KERNELS = {"relax": 0, "defect": 1, "restrict": 2, "prolong": 3, "residual": 4,
-           "relax_prolong": 5, "relax_restrict": 6}
+           "relax_prolong": 5, "relax_restrict": 6, "coarse": 7}
 
 
 class mg_grid(ctypes.Structure):

@@ -20,10 +20,11 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--kernel", default="relax",
                     choices=["relax", "defect", "restrict", "prolong", "residual",
-                             "relax_prolong", "relax_restrict"])
+                             "relax_prolong", "relax_restrict", "coarse"])
     ap.add_argument("--level", type=int, default=0)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--nc", type=int, default=32)
     ap.add_argument("--fp32", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=2048)
     args = ap.parse_args(argv)
@@ -34,9 +35,9 @@ def main(argv=None):
     from paper_1111_0983_amd import ghostmg as gm
     from workloads import problems as pr
 
-    w = pr.flower(args.n, 32)
+    w = pr.flower(args.n, args.nc)
     phi = w.domain.nodal_phi(args.n)
-    grid = gm.mg_grid_default(2, args.n, 32,
+    grid = gm.mg_grid_default(2, args.n, args.nc,
                               precision=gm.MG_FP32_DC if args.fp32 else gm.MG_FP64)
     s = gm.Solver(torch.from_numpy(phi).cuda(), [w.rule], grid)
     ms, nbytes = s.time_kernel(args.kernel, args.level, args.reps)

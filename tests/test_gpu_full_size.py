@@ -43,12 +43,13 @@ def _solve(w, dim, n, nc, prec, tol=1e-10):
     return phi, u.cpu().numpy(), info
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32dc"])
-def test_flower_2048(prec):
+@pytest.mark.parametrize("prec,nc", [("fp64", 32), ("fp32dc", 32), ("fp64", 128), ("fp32dc", 128)])
+def test_flower_2048(prec, nc):
+    """Coarsest grids of 32 (7 levels) and of 128 (5 levels, the benchmark's)."""
     gm = _gm()
-    w = pr.flower(2048, 32)
-    phi, u, info = _solve(w, 2, 2048, 32, gm.MG_FP64 if prec == "fp64" else gm.MG_FP32_DC)
-    o = Oracle(phi, default_grid(2, 2048, 32), w.rule)
+    w = pr.flower(2048, nc)
+    phi, u, info = _solve(w, 2, 2048, nc, gm.MG_FP64 if prec == "fp64" else gm.MG_FP32_DC)
+    o = Oracle(phi, default_grid(2, 2048, nc), w.rule)
     c, _ = o.cls(0)
     G = o.ghosts(0)
     rhs = pr.rhs_from_ghosts(2, 2048, c, G["node"], G["B"], G["type"], w.solution, w.domain)
