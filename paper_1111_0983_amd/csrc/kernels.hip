@@ -298,18 +298,24 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
       if (i < NFN) src[i] = fok[k] ? rcv[k] : kNoUnknown;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < NFN; i += 256) {
-      const uint8_t c = src[i];
-      T v = 0;
-      if (c != kNoUnknown) {
-        const int x = i % FX, y = i / FX;
-        const T* pp = sr + (2 * x + 1) + RX * (2 * y + 1);
-        T rr[9];
+    // two nodes per pass, every patch read issued before the first use (the 3 x 3 fine
+    // neighbourhood of each F node lies inside the patch)
+    for (int i0 = threadIdx.x; i0 < NFN; i0 += 512) {
+      uint8_t c[2];
+      T rr[2][9];
+      int ii[2];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) rr[q] = pp[(q / 3 - 1) + RX * (q % 3 - 1)];
-        v = restrict_box<2, T>(c, rr);
+      for (int h = 0; h < 2; ++h) {
+        ii[h] = i0 + 256 * h < NFN ? i0 + 256 * h : i0;
+        c[h] = i0 + 256 * h < NFN ? src[ii[h]] : kNoUnknown;
+        const int x = ii[h] % FX, y = ii[h] / FX;
+        const T* pp = sr + (2 * x + 1) + RX * (2 * y + 1);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) rr[h][q] = pp[(q / 3 - 1) + RX * (q % 3 - 1)];
       }
-      sf[i] = v;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (i0 + 256 * h < NFN) sf[ii[h]] = c[h] != kNoUnknown ? restrict_box<2, T>(c[h], rr[h]) : (T)0;
     }
     __syncthreads();  // sf is read below at positions other threads computed
     // the restricted right-hand side of the tile's unknowns, for the level's later launches
@@ -339,33 +345,76 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
       }
     }
     __syncthreads();
-    // u + interpolated correction at every unknown of the U region
-    for (int i = threadIdx.x; i < NUN; i += 256) {
-      if (sc[i] == 0) continue;
-      const int x = i % UX, y = (i / UX) % UY, z = i / (UX * UY);
-      const int j[3] = {ox + x - 2, oy + y - 2, D == 3 ? oz + z - 2 : 0};
-      T w[1 << D], ec[1 << D];
-      int8_t cc[1 << D];
+    // u + interpolated correction at every unknown of the U region.  Node j takes the coarse
+    // nodes floor(j / 2) and, along each odd coordinate, the next one up (weight 2^-(odd
+    // coordinates) each), over those that carry an unknown (Sec. 2.6.1); tile origins are even.
+    // Two nodes per pass; each node reads its 2^D candidate codes and values (the patch
+    // covers every candidate position, absent ones included) before any use.
+    constexpr int CS[3] = {1, CX, CX * CY};
+    constexpr int NCD = 1 << D;
+    for (int i0 = threadIdx.x; i0 < NUN; i0 += 512) {
+      int ii[2], lb[2], nodd[2];
+      bool odd[2][3], live[2];
+      int8_t cc[2][NCD];
+      T ce[2][NCD], uo[2];
 #pragma unroll
-      for (int m = 0; m < (1 << D); ++m) {
-        int jc[3];
-        w[m] = prolong_candidate<D, T>(j, m, jc);
-        const int li = (jc[0] - (ox / 2 - 1)) + CX * ((jc[1] - (oy / 2 - 1)) +
-                                                      CY * (D == 3 ? jc[2] - (oz / 2 - 1) : 0));
-        cc[m] = w[m] != (T)0 ? scc[li] : (int8_t)0;
-        ec[m] = w[m] != (T)0 ? sce[li] : (T)0;
+      for (int h = 0; h < 2; ++h) {
+        const int i = i0 + 256 * h;
+        ii[h] = i < NUN ? i : i0;
+        const int x = ii[h] % UX, y = (ii[h] / UX) % UY, z = ii[h] / (UX * UY);
+        const int jr[3] = {x, y, z};  // j - o + 2 (o even): the parity of j
+        lb[h] = 0;
+        nodd[h] = 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) odd[h][q] = q < D && (jr[q] & 1);
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          nodd[h] += odd[h][q];
+          lb[h] += (jr[q] >> 1) * CS[q];  // (j >> 1) - (o / 2 - 1)
+        }
+        live[h] = i < NUN && sc[ii[h]] != 0;
+        uo[h] = su[ii[h]];
+#pragma unroll
+        for (int m = 0; m < NCD; ++m) {
+          int li = lb[h];
+#pragma unroll
+          for (int q = 0; q < D; ++q)
+            if ((m >> q) & 1) li += CS[q];
+          cc[h][m] = scc[li];
+          ce[h][m] = sce[li];
+        }
       }
-      su[i] = prolong_correct<D, T>(su[i], w, cc, ec);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        T w1 = 1;
+        for (int q = 0; q < nodd[h]; ++q) w1 *= (T)0.5;
+        T num = 0, den = 0;
+#pragma unroll
+        for (int m = 0; m < NCD; ++m) {
+          bool ex = cc[h][m] != 0;
+#pragma unroll
+          for (int q = 0; q < D; ++q)
+            if ((m >> q) & 1) ex = ex && odd[h][q];
+          if (!ex) continue;
+          num += w1 * ce[h][m];
+          den += w1;
+        }
+        // den == 1 when every candidate carries an unknown: num / den == num exactly
+        if (live[h] && den > (T)0) su[ii[h]] = uo[h] + (den == (T)1 ? num : num / den);
+      }
     }
   }
   __syncthreads();
   constexpr int SY = UX, SZ = UX * UY;
-  for (int i = threadIdx.x; i < NFN; i += 256) {
-    const int x = i % FX, y = (i / FX) % FY, z = i / (FX * FY);
+  // red nodes of the F region only (tile origins are even: node x of row (y, z) is red when
+  // x + y + z + D is even), FX / 2 per row
+  constexpr int FXH = FX / 2;
+  for (int r = threadIdx.x; r < FXH * FY * FZ; r += 256) {
+    const int row = r / FXH, y = row % FY, z = row / FY;
+    const int x = 2 * (r % FXH) + ((y + z + D) & 1);
+    const int i = x + FX * (y + FY * z);
     const int ui = (x + 1) + SY * (y + 1) + (D == 3 ? SZ * (z + 1) : 0);
     if (sc[ui] != 1 && sc[ui] != 3) continue;
-    const int gx = ox + x - 1, gy = oy + y - 1, gz = D == 3 ? oz + z - 1 : 0;
-    if ((gx + gy + gz) & 1) continue;
     T nb[2 * D];
     nb[0] = su[ui - 1];
     nb[1] = su[ui + 1];
@@ -378,13 +427,14 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
     su[ui] = interior_update<D, T>(su[ui], nb, sf[i], a.h2, a.inv2d);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
-    const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
+  // black nodes of the tile only: x + y + z odd, TX / 2 per row
+  constexpr int TXH = TX / 2;
+  for (int r = threadIdx.x; r < TXH * TY * TZ; r += 256) {
+    const int row = r / TXH, y = row % TY, z = row / TY;
+    const int x = 2 * (r % TXH) + ((y + z + 1) & 1);
     const int fi = (x + 1) + FX * (y + 1) + (D == 3 ? FX * FY * (z + 1) : 0);
     const int ui = (x + 2) + SY * (y + 2) + (D == 3 ? SZ * (z + 2) : 0);
     if (sc[ui] != 1 && sc[ui] != 3) continue;
-    const int gx = ox + x, gy = oy + y, gz = D == 3 ? oz + z : 0;
-    if (!((gx + gy + gz) & 1)) continue;
     T nb[2 * D];
     nb[0] = su[ui - 1];
     nb[1] = su[ui + 1];
@@ -423,6 +473,31 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
 // ghosts, black reads red and ghosts, the ghosts read the values before their phase).
 // Phases are separated by workgroup barriers; a ghost phase computes every new ghost value
 // before any is stored.  The owned entries are written to uout.
+// One red or black phase of a relaxation chunk over the NC slots from S0: every active slot
+// reads its neighbours (all reads before any write), then updates and stores its value.
+template <int D, typename T, int NC, int S0, int NS>
+__device__ __forceinline__ void band_colour_phase(int p, const uint32_t (&mask)[NS],
+                                                  const int (&nbi)[NS][2 * D],
+                                                  const int (&e_of)[NS], T (&uv)[NS],
+                                                  const T (&rv)[NS], T* su, T h2, T inv2d) {
+  bool act[NC];
+  T nv[NC][2 * D];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    act[j] = (mask[S0 + j] >> p) & 1u;
+    if (act[j]) {
+#pragma unroll
+      for (int q = 0; q < 2 * D; ++q) nv[j][q] = su[nbi[S0 + j][q]];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    if (!act[j]) continue;
+    uv[S0 + j] = interior_update<D, T>(uv[S0 + j], nv[j], rv[S0 + j], h2, inv2d);
+    su[e_of[S0 + j]] = uv[S0 + j];
+  }
+}
+
 template <int D, typename T, int MODE>
 __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
   constexpr bool PROLONG = MODE == kRelaxProlong, RESTRICT = MODE == kRelaxRestrict;
@@ -561,45 +636,36 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
     gc = ((const double*)(a.data + hd[5]))[tg];
   }
   __syncthreads();
-  for (int p = 0; p < a.phases; ++p) {
-    const int colour = p % 3;  // 0 red, 1 black, 2 ghosts
-    if (colour != 2) {
-      const int s0 = colour == 0 ? 1 : 1 + NC;
-      bool act[NC];
-      T nv[NC][2 * D];
+  // neighbour ids of the red and black slots, decoded once
+  int nbi[NS][2 * D];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        act[j] = (mask[s0 + j] >> p) & 1u;
+  for (int s = 1; s <= 2 * NC; ++s)
 #pragma unroll
-        for (int q = 0; q < D; ++q) {
-          const uint32_t w = (uint32_t)nbw[s0 + j][q];
-          nv[j][2 * q] = su[act[j] ? (int)(int16_t)(w & 0xffff) : 0];
-          nv[j][2 * q + 1] = su[act[j] ? (int)(int16_t)(w >> 16) : 0];
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        if (!act[j]) continue;
-        uv[s0 + j] = interior_update<D, T>(uv[s0 + j], nv[j], rv[s0 + j], a.h2, a.inv2d);
-        su[e_of[s0 + j]] = uv[s0 + j];
-      }
-      __syncthreads();
-    } else {
-      const bool upd = ghost && ((mask[0] >> p) & 1u);
-      if (upd) {
-        // taps of zero weight name the ghost itself
-        T gv[K];
-#pragma unroll
-        for (int q = 0; q < K; ++q) gv[q] = su[gid[q]];
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < K; ++q) acc += gwt[q] * (double)gv[q];
-        uv[0] = ghost_update<T>(uv[0], rv[0], acc, gc);
-      }
-      __syncthreads();
-      if (upd) su[tid] = uv[0];
-      __syncthreads();
+    for (int q = 0; q < D; ++q) {
+      nbi[s][2 * q] = (int)(int16_t)((uint32_t)nbw[s][q] & 0xffffu);
+      nbi[s][2 * q + 1] = (int)(int16_t)((uint32_t)nbw[s][q] >> 16);
     }
+  // phases p, p + 1, p + 2 of every sweep: red, black, ghosts (the colour of a phase is
+  // fixed, so every slot index below is a compile-time constant)
+  for (int p = 0; p < a.phases; p += 3) {
+    band_colour_phase<D, T, NC, 1, NS>(p, mask, nbi, e_of, uv, rv, su, a.h2, a.inv2d);
+    __syncthreads();
+    band_colour_phase<D, T, NC, 1 + NC, NS>(p + 1, mask, nbi, e_of, uv, rv, su, a.h2, a.inv2d);
+    __syncthreads();
+    const bool upd = ghost && ((mask[0] >> (p + 2)) & 1u);
+    if (upd) {
+      // taps of zero weight name the ghost itself
+      T gv[K];
+#pragma unroll
+      for (int q = 0; q < K; ++q) gv[q] = su[gid[q]];
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < K; ++q) acc += gwt[q] * (double)gv[q];
+      uv[0] = ghost_update<T>(uv[0], rv[0], acc, gc);
+    }
+    __syncthreads();
+    if (upd) su[tid] = uv[0];
+    __syncthreads();
   }
 #pragma unroll
   for (int s = 0; s < NS - NH; ++s)
