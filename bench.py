@@ -199,6 +199,17 @@ def main():
     log(f"[bench] FP64: {ms:.2f} ms/solve, {info['cycles']} cycles, rel {info['rel']:.2e}, "
         f"error vs exact {err:.2e}")
 
+    # the same number of cycles queued as graph launches with a single read-back at the end:
+    # the cycle itself, without the residual checks of the stopping test
+    uc = torch.zeros_like(u)
+    s.cycles(f, g, uc, info["cycles"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.cycles(f, g, uc, info["cycles"])
+    torch.cuda.synchronize()
+    cycle_us = 1e6 * (time.perf_counter() - t0) / info["cycles"]
+    log(f"[bench] {info['cycles']} cycles queued at once: {cycle_us:.1f} us per cycle")
+
     # roofline of the dominant kernel: the fine-level relaxation (one launch: interior
     # tiles and the boundary chunks); the other launches of the cycle are timed alongside
     k_ms, k_bytes = s.time_kernel("relax", 0, 50)
@@ -279,7 +290,7 @@ def main():
                       "n": n, "unknowns": unknowns, "cycles": info["cycles"],
                       "rel_residual": info["rel"], "max_error_vs_exact": err,
                       "setup_s": round(setup_s, 3), "parallelism": "single GPU"},
-           "roofline": roof, "cpu_baseline": cpu}
+           "roofline": roof, "cpu_baseline": cpu, "cycle_us_without_checks": round(cycle_us, 1)}
     out.update(extra)
     print(json.dumps(out), flush=True)
 

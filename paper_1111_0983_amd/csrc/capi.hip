@@ -328,7 +328,8 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
     // Once the history gives a convergence factor, queue the cycles that the factor says
     // are still needed, minus one, before reading the residual back: the stopping test is
     // unchanged, only host round trips are saved.
-    int k = 1;
+    // a fixed number of cycles is queued at once, with one read-back at the end
+    int k = fixed_cycles >= 0 ? std::max(1, fixed_cycles - steps) : 1;
     if (fixed_cycles < 0 && H->history.size() >= 3) {
       const double r1 = H->history[H->history.size() - 1], r2 = H->history[H->history.size() - 2];
       const double rho = r1 / r2;

@@ -4,7 +4,7 @@
 
 namespace ghostmg {
 
-constexpr int kCoarseRows = 4;  // rows of the coarsest inverse per workgroup (one per wave)
+constexpr int kCoarseRows = 16;  // rows of the coarsest inverse per workgroup (one per wave)
 
 // Per-phase boundary relaxation (levels without relaxation chunks), in place on u.
 template <typename T>

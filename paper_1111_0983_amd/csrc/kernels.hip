@@ -620,6 +620,10 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
 #pragma unroll
   for (int s = 0; s < NS; ++s)
     if (ok_of[s]) su[e_of[s]] = uv[s];
+  // gs: the ghost values before the current ghost phase (the ghost rows read other ghosts
+  // there, so that a ghost phase can store its new values into su without a second barrier)
+  T* gs = su + ns;
+  if (ghost) gs[tid] = uv[0];
   // the ghost rows are first needed in phase 2: loaded after the values (registers)
   int32_t gid[K];
   double gwt[K];
@@ -647,24 +651,29 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
     }
   // phases p, p + 1, p + 2 of every sweep: red, black, ghosts (the colour of a phase is
   // fixed, so every slot index below is a compile-time constant)
+  // taps on ghost entries (ids below ng) read gs, the others su; taps of zero weight name
+  // the ghost itself
+  int gad[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) gad[q] = gid[q] < ng ? ns + gid[q] : gid[q];
   for (int p = 0; p < a.phases; p += 3) {
+    // the previous ghost phase's values become the snapshot (nothing reads gs until the
+    // next ghost phase, two barriers later)
+    if (ghost) gs[tid] = uv[0];
     band_colour_phase<D, T, NC, 1, NS>(p, mask, nbi, e_of, uv, rv, su, a.h2, a.inv2d);
     __syncthreads();
     band_colour_phase<D, T, NC, 1 + NC, NS>(p + 1, mask, nbi, e_of, uv, rv, su, a.h2, a.inv2d);
     __syncthreads();
-    const bool upd = ghost && ((mask[0] >> (p + 2)) & 1u);
-    if (upd) {
-      // taps of zero weight name the ghost itself
+    if (ghost && ((mask[0] >> (p + 2)) & 1u)) {
       T gv[K];
 #pragma unroll
-      for (int q = 0; q < K; ++q) gv[q] = su[gid[q]];
+      for (int q = 0; q < K; ++q) gv[q] = su[gad[q]];
       double acc = 0.0;
 #pragma unroll
       for (int q = 0; q < K; ++q) acc += gwt[q] * (double)gv[q];
       uv[0] = ghost_update<T>(uv[0], rv[0], acc, gc);
+      su[tid] = uv[0];
     }
-    __syncthreads();
-    if (upd) su[tid] = uv[0];
     __syncthreads();
   }
 #pragma unroll
@@ -1115,50 +1124,53 @@ __global__ void __launch_bounds__(256) k_prolong(const int4* __restrict__ tiles,
 // exact solve on the coarsest grid: e = A_c^{-1} r (FP64), several row blocks per problem
 // ---------------------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_coarse(const int32_t* __restrict__ umap,
-                                                const int32_t* __restrict__ umap_off,
-                                                const int64_t* __restrict__ ainv_off,
-                                                const double* __restrict__ ainv,
-                                                const T* __restrict__ rhs, T* __restrict__ u) {
+__global__ void __launch_bounds__(kCoarseRows * 64) k_coarse(const int32_t* __restrict__ umap,
+                                                             const int32_t* __restrict__ umap_off,
+                                                             const int64_t* __restrict__ ainv_off,
+                                                             const double* __restrict__ ainv,
+                                                             const T* __restrict__ rhs,
+                                                             T* __restrict__ u) {
+  constexpr int NT = kCoarseRows * 64;  // one row per wave
+  constexpr int NQ = 16;                // loads of the row in flight per lane
   extern __shared__ double bsh[];
   const int p = blockIdx.y;
   const int a = umap_off[p], nu = umap_off[p + 1] - a;
   const int row0 = blockIdx.x * kCoarseRows;
   if (row0 >= nu) return;
-  // right-hand side in LDS, 8 gathers in flight per thread
-  for (int i0 = 0; i0 < nu; i0 += 8 * 256) {
-    int32_t idx[8];
+  // right-hand side in LDS, 4 gathers in flight per thread
+  for (int i0 = 0; i0 < nu; i0 += 4 * NT) {
+    int32_t idx[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int i = i0 + threadIdx.x + 256 * q;
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + threadIdx.x + NT * q;
       idx[q] = i < nu ? umap[a + i] : umap[a];
     }
-    T v[8];
+    T v[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = rhs[idx[q]];
+    for (int q = 0; q < 4; ++q) v[q] = rhs[idx[q]];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int i = i0 + threadIdx.x + 256 * q;
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + threadIdx.x + NT * q;
       if (i < nu) bsh[i] = (double)v[q];
     }
   }
   __syncthreads();
   const double* A = ainv + ainv_off[p];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r = row0 + w;  // one row per wave
+  const int r = row0 + w;
   if (r >= nu) return;
   const double* Ar = A + (int64_t)r * nu;
   double acc = 0.0;
-  for (int j0 = 0; j0 < nu; j0 += 8 * 64) {
-    double av[8], bv[8];
+  for (int j0 = 0; j0 < nu; j0 += NQ * 64) {
+    double av[NQ], bv[NQ];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int j = j0 + lane + 64 * q;
       av[q] = j < nu ? Ar[j] : 0.0;
       bv[q] = j < nu ? bsh[j] : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc += av[q] * bv[q];
+    for (int q = 0; q < NQ; ++q) acc += av[q] * bv[q];
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if (lane == 0) u[umap[a + r]] = (T)acc;
@@ -1282,12 +1294,12 @@ constexpr int kSingleWgExt = 24576;
 
 template <int D, typename T>
 size_t relax_lds(const DevLevel& L) {
-  return std::max(tile_lds<D, T, kRelaxProlong>(), (size_t)L.bc_smax * sizeof(T));
+  return std::max(tile_lds<D, T, kRelaxProlong>(), (size_t)(L.bc_smax + kChunkThreads) * sizeof(T));
 }
 
 template <int D, typename T, int MODE>
 static void launch_relax_kernel(const RelaxArgs<T>& a, int nb, const DevLevel& L, hipStream_t s) {
-  const size_t lds = std::max(tile_lds<D, T, MODE>(), (size_t)L.bc_smax * sizeof(T));
+  const size_t lds = std::max(tile_lds<D, T, MODE>(), (size_t)(L.bc_smax + kChunkThreads) * sizeof(T));
   if (a.nchunks)
     hipLaunchKernelGGL((k_relax<D, T, true, MODE>), dim3(nb), dim3(256), lds, s, a);
   else
@@ -1471,7 +1483,7 @@ void launch_prolong(const DevLevel& F, const DevLevel& C, const T* uc, T* uf, hi
 template <typename T>
 void launch_coarse(const DevLevel& C, const T* rhs, T* u, int batch, hipStream_t s) {
   const int blocks = (C.nu_max + kCoarseRows - 1) / kCoarseRows;
-  hipLaunchKernelGGL((k_coarse<T>), dim3(blocks, batch), dim3(256), C.nu_max * sizeof(double), s,
+  hipLaunchKernelGGL((k_coarse<T>), dim3(blocks, batch), dim3(kCoarseRows * 64), C.nu_max * sizeof(double), s,
                      C.umap, C.umap_off, C.ainv_off, C.ainv, rhs, u);
 }
 
