@@ -308,7 +308,7 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
   if ((rc = read_rel(H, &rel))) return rc;
   H->history.clear();
   H->history.push_back(rel);
-  int cycles = 0, steps = 0, grew = 0, status = MG_OK;
+  int cycles = 0, steps = 0, grew = 0, status = MG_OK, last_k = 1;
   double prev = rel;
   const int per = dc ? H->grid.inner_cycles : 1;
   for (;;) {
@@ -325,20 +325,22 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
         break;
       }
     }
-    // Once the history gives a convergence factor, queue the cycles that the factor says
-    // are still needed, minus one, before reading the residual back: the stopping test is
-    // unchanged, only host round trips are saved.
-    // a fixed number of cycles is queued at once, with one read-back at the end
+    // Once the history gives a convergence factor per step (the last read-back's reduction
+    // over the steps queued before it), queue the steps that the factor says are still
+    // needed, minus one, before reading the residual back: the stopping test is unchanged,
+    // only host round trips are saved.  A fixed number of cycles is queued at once, with one
+    // read-back at the end.
     int k = fixed_cycles >= 0 ? std::max(1, fixed_cycles - steps) : 1;
     if (fixed_cycles < 0 && H->history.size() >= 3) {
       const double r1 = H->history[H->history.size() - 1], r2 = H->history[H->history.size() - 2];
-      const double rho = r1 / r2;
+      const double rho = std::pow(r1 / r2, 1.0 / last_k);
       if (rho > 0.0 && rho < 0.9 && rel > tol) {
         const int need = (int)std::ceil(std::log(tol / rel) / std::log(rho));
-        k = std::max(1, std::min(need - 1, 8));
+        k = std::max(1, std::min(need - 1, 16));
       }
       k = std::min(k, std::max(1, (H->grid.max_cycles - cycles) / per));
     }
+    last_k = k;
     for (int i = 0; i < k; ++i) {
       if (dc) {
         HIP_TRY(hipGraphLaunch(H->graph_dc, s));
