@@ -48,7 +48,7 @@ constexpr int kMaxCoarse = 8192;
 // entries per owned node) above which a level relaxes its boundary with one launch per
 // phase instead; owned extension nodes per extension chunk
 constexpr int kChunkOwn = 320;
-constexpr double kChunkRedundancy = 4.0;
+constexpr double kChunkRedundancy2D = 4.0, kChunkRedundancy3D = 8.0;
 constexpr int kExtChunkOwn = 512;
 
 int upload_level(mg_handle_s* H, int l) {
@@ -102,9 +102,22 @@ int upload_level(mg_handle_s* H, int l) {
   if (S.bc_nchunks) {
     L.nchunks = S.bc_nchunks;
     L.bc_smax = S.bc_smax;
-    L.bc_phases = 3 + 3 * H->grid.lambda;
+    L.bc_phases = S.bc_range;
+    L.nsub = (int)S.bc_sub.size() - 1;
+    if (L.nsub < 1 || L.nsub > 7) return MG_EINVAL;
+    for (int k = 0; k <= L.nsub; ++k) L.sub[k] = S.bc_sub[k];
     if ((rc = upload(&L.bc_hdr, S.bc_hdr))) return rc;
     if ((rc = upload(&L.bc_data, S.bc_data))) return rc;
+    if (L.nsub > 1) {
+      if (dc ? (rc = alloc_zero(&L.z32, nn)) : (rc = alloc_zero(&L.z64, nn))) return rc;
+      if (!(L.nsub & 1)) {
+        std::vector<int32_t> bl(S.red.begin(), S.red.end());
+        bl.insert(bl.end(), S.black.begin(), S.black.end());
+        for (const GhostRec& gr : S.ghosts) bl.push_back((int32_t)gr.node);
+        L.nband_list = (int)bl.size();
+        if ((rc = upload(&L.band_list, bl))) return rc;
+      }
+    }
   }
   if (S.ec_nchunks) {
     L.nechunks = S.ec_nchunks;
@@ -377,7 +390,7 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
 }
 
 void free_level(DevLevel& L) {
-  void* ptrs[] = {L.bc_hdr, L.bc_data, L.ec_hdr, L.ec_data, L.rcls, L.gw,
+  void* ptrs[] = {L.bc_hdr, L.bc_data, L.z64, L.z32, L.band_list, L.ec_hdr, L.ec_data, L.rcls, L.gw,
                   L.cls, L.phi, L.tiles, L.ghosts, L.ghost_off, L.red, L.black, L.red_off, L.black_off,
                   L.ext, L.ext_merged, L.ext_off, L.dag_off, L.dag_start, L.rcode, L.u64[0],
                   L.u64[1], L.rhs64, L.r64, L.gtmp64, L.u32[0], L.u32[1], L.rhs32, L.r32, L.gtmp32,
@@ -531,10 +544,17 @@ int setup_impl(const double* phi, const mg_bc_rule* bc, mg_bc_fn fn, void* ctx,
   if (!rc)
     for (int l = 0; l < L; ++l) {
       HostLevel& S = H->host[l];
-      if (!build_band_chunks(H, l, kChunkOwn, kChunkRedundancy)) {
+      // the largest number of phases per launch whose chunks fit (all of a relaxation in
+      // one launch where possible)
+      bool built = false;
+      const int P = 3 + 3 * H->grid.lambda;
+      for (int R = P; R >= 3 && !built; R -= 3)
+        if (P % R == 0 && P / R <= 7) built = build_band_chunks(H, l, kChunkOwn, H->dim == 2 ? kChunkRedundancy2D : kChunkRedundancy3D, R);
+      if (!built) {
         S.bc_nchunks = 0;
         S.bc_hdr.clear();
         S.bc_data.clear();
+        S.bc_sub.clear();
       }
       if (!build_ext_chunks(H, l, kExtChunkOwn)) {
         S.ec_nchunks = 0;

@@ -20,11 +20,16 @@ constexpr int kChunkThreads = 256;     // workgroup size of every chunk kernel
 constexpr int kChunkPerThread = 4;     // chunk entries owned by one thread
 constexpr int kChunkMaxEntries = kChunkPerThread * kChunkThreads;
 constexpr int kExtMaxTerms = 6 * kChunkThreads;  // composed extension terms per chunk
+constexpr int kExtMaxGhosts = 2 * kChunkThreads;  // ghost sources per extension chunk
 // relaxation chunks: per thread one updated ghost, kBandColourSlots red and as many black
-// entries, kBandHaloSlots entries that are read but never updated
+// entries, band_halo_slots(D) entries that are read but never updated (more in 3D, where a
+// band patch's closure has more of them)
 constexpr int kBandColourSlots = 2;
-constexpr int kBandHaloSlots = 1;
-constexpr int kBandMaxEntries = (1 + 2 * kBandColourSlots + kBandHaloSlots) * kChunkThreads;
+constexpr int kBandHaloSlots2D = 1, kBandHaloSlots3D = 4;
+constexpr int band_halo_slots(int D) { return D == 2 ? kBandHaloSlots2D : kBandHaloSlots3D; }
+constexpr int band_max_entries(int D) {
+  return (1 + 2 * kBandColourSlots + band_halo_slots(D)) * kChunkThreads;
+}
 
 // Tile shapes of the node-parallel kernels: 64 x 16 nodes in 2D, 16 x 8 x 8 in 3D.
 template <int D>
@@ -79,11 +84,12 @@ struct HostLevel {
   std::vector<int8_t> rcls;
   std::vector<double> gw;               // Pow3<D> row weights per ghost (0 for unused taps)
   // Relaxation chunks: each chunk owns band and ghost nodes and carries every node that
-  // their values after the whole relaxation depend on, through its 3 + 3 lambda phases
-  // (red interior, black interior, ghosts; lambda times red band, black band, ghosts).
+  // their values after a launch's phases depend on; a relaxation is 3 + 3 lambda phases (red
+  // interior, black interior, ghosts; lambda times red band, black band, ghosts), taken
+  // bc_range at a time, with a chunk set per launch.
   // Entries come in four runs: the updated ghosts (at most kChunkThreads), the entries the
   // red phases update, those the black phases update (at most kBandColourSlots *
-  // kChunkThreads each), and the entries only read (at most kBandHaloSlots * kChunkThreads);
+  // kChunkThreads each), and the entries only read (at most band_halo_slots(D) * kChunkThreads);
   // entry i of a run belongs to thread i % kChunkThreads.  Chunk c: header
   // bc_hdr[c * kBandHdr ..] = {entries, updated ghosts | red << 10 | black << 20, offsets
   // into bc_data of: the per-entry arrays, the ghost stencil ids, the ghost
@@ -91,22 +97,26 @@ struct HostLevel {
   // and the restriction data (-1 on the finest level)}: per entry the coarse node index of
   // its interpolation candidate 0 (candidate m adds the coarse stride of each axis q with bit
   // q of m), and 2 words: the fine node index of (2x, 2y, 2z) and the restriction code.
-  // Per-entry arrays (int32 words): node index; mask (bit p < P: updated in phase p of the
-  // P = 3 + 3 lambda; bits [P, P + D): odd coordinates; bits [P + D, P + D + 2^D):
-  // interpolation candidate m exists and carries an unknown; bit 31: owned, written to the
-  // output); D words of
+  // Per-entry arrays (int32 words): node index; mask (bit p < R: updated in phase p of the
+  // launch's R phases; bits [R, R + D): odd coordinates; bits [R + D, R + D + 2^D):
+  // interpolation candidate m exists and carries an unknown; bit 30: band or ghost node;
+  // bit 31: owned, written to the output); D words of
   // (minus, plus) int16 local neighbour ids per axis.  Per ghost (tap-major, ghost fastest):
   // Pow3<D> local stencil ids (the ghost's own id for taps of zero weight) and FP64 weights
   // (0 for those taps); one FP64 constant c_G.
   std::vector<int32_t> bc_hdr;
   std::vector<int32_t> bc_data;
   int bc_nchunks = 0, bc_smax = 0, bc_nown = 0;
+  // phases per launch (whole sweeps dividing 3 + 3 lambda) and the first chunk of each
+  // launch's set (bc_sub[k] .. bc_sub[k + 1])
+  int bc_range = 0;
+  std::vector<int> bc_sub;
   int64_t bc_entries = 0;               // sum of chunk sizes (redundant work included)
   // Extension chunks.  The steady state of Eq. (exp) on the upwind graph is linear in the
   // ghost defects: every extension value is a fixed combination of the defects of the ghost
   // nodes its upwind paths start from, with weights composed on the host.  Each chunk owns a
   // run of extension nodes (at most kChunkMaxEntries) and evaluates the defects of the ghost
-  // sources they need (at most kChunkThreads, one per thread).  Chunk c: header
+  // sources they need (at most kExtMaxGhosts).  Chunk c: header
   // ec_hdr[c * kExtHdr ..] = {extension nodes, ghost sources, offsets into ec_data of: the node
   // indices (ghost sources, then extension nodes), the term offsets (per extension node and
   // one past the end, relative to the chunk's first term), the term source ids (local ghost
@@ -128,6 +138,14 @@ struct DevLevel {
   int ntiles = 0, nghost = 0, nred = 0, nblack = 0, next = 0, ndag = 0;
   int max_gp = 0, max_bandp = 0, max_extp = 0;   // largest per-problem list sizes
   int nchunks = 0, bc_phases = 0, bc_smax = 0;
+  // launches per relaxation (bc_phases each) and their chunk ranges; z64 / z32: the band
+  // values between launches when there is more than one
+  int nsub = 0;
+  int sub[8] = {};
+  double* z64 = nullptr;
+  float* z32 = nullptr;
+  int32_t* band_list = nullptr;  // band and ghost nodes (copied back after an even count)
+  int nband_list = 0;
   int32_t *bc_hdr = nullptr, *bc_data = nullptr;
   int nechunks = 0, ec_smax = 0;
   int32_t *ec_hdr = nullptr, *ec_data = nullptr;

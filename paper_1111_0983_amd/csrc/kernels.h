@@ -32,6 +32,8 @@ struct RelaxArgs {
   const T* uin;
   T* uout;
   const T* rhs;
+  // chunk entries of band and ghost nodes (mask bit 30) start from uband, the others from uin
+  const T* uband;
   T h2, inv2d;
   int write_all;  // tiles also write band interior and ghost nodes (levels without chunks)
   int nchunks, phases;
@@ -110,7 +112,7 @@ size_t relax_lds(const DevLevel& L);
 size_t defect_lds(const DevLevel& L);
 
 int build_hierarchy(mg_handle_s* H, const double* phi);
-bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redundancy);
+bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redundancy, int R);
 bool build_ext_chunks(mg_handle_s* H, int l, int own_target);
 
 }  // namespace ghostmg

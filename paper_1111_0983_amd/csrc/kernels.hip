@@ -464,7 +464,7 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
 // ghost nodes) through the 3 + 3 lambda phases (red interior, black interior, ghosts; then
 // lambda times red band, black band, ghosts, Sec. 3.2).  Its entries come in runs: updated
 // ghosts, red-updated, black-updated, read-only; a thread holds one ghost, kBandColourSlots
-// red and black entries and kBandHaloSlots read-only entries (slot s of a run: entry
+// red and black entries and band_halo_slots(D) read-only entries (slot s of a run: entry
 // tid + s * kChunkThreads of the run), with their node index, phase mask, neighbour ids,
 // right-hand side and current value in registers (the ghost also its stencil ids, weights
 // and constant); only the values are shared, in LDS.  A phase updates at most
@@ -502,7 +502,7 @@ template <int D, typename T, int MODE>
 __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
   constexpr bool PROLONG = MODE == kRelaxProlong, RESTRICT = MODE == kRelaxRestrict;
   constexpr int K = Pow3<D>::value;
-  constexpr int NC = kBandColourSlots, NH = kBandHaloSlots;
+  constexpr int NC = kBandColourSlots, NH = band_halo_slots(D);
   constexpr int NS = 1 + 2 * NC + NH;  // slots: ghost, red, black, read-only
   constexpr int NCAND = 1 << D;
   const int cu = __builtin_amdgcn_readfirstlane(c);
@@ -581,7 +581,7 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
   } else {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      uv[s] = a.uin[node[s]];
+      uv[s] = (((mask[s] >> 30) & 1u) ? a.uband : a.uin)[node[s]];
       rv[s] = s < NS - NH ? a.rhs[node[s]] : (T)0;
     }
   }
@@ -831,10 +831,11 @@ __device__ void extend_chunk(const DefectArgs<T, TO>& a, int c, unsigned char* l
     tw[j] = TW[ic];
     ts[j] = TS[ic];
   }
-  const bool gsrc = tid < ngs;
-  const int tg = gsrc ? tid : 0;
-  double gv = 0.0;
-  if (ngs > 0) {
+  // ghost sources tid, tid + kChunkThreads, ... (a second pass only where a chunk has more
+  // sources than threads)
+  for (int g0 = 0; g0 < ngs; g0 += kChunkThreads) {
+    const bool gsrc = g0 + tid < ngs;
+    const int tg = gsrc ? g0 + tid : 0;
     const int32_t* gn = a.data + hd[6];
     const double* gw = (const double*)(a.data + hd[7]);
     int32_t gnode[K];
@@ -853,9 +854,8 @@ __device__ void extend_chunk(const DefectArgs<T, TO>& a, int c, unsigned char* l
 #pragma unroll
     for (int q = 0; q < K; ++q)
       if (gwt[q] != 0.0) acc += gwt[q] * uq[q];
-    gv = (double)(TO)(rG - acc);
+    if (gsrc) sv[g0 + tid] = (double)(TO)(rG - acc);
   }
-  if (gsrc) sv[tid] = gv;
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
     const int i = tid + j * kChunkThreads;
@@ -1353,6 +1353,24 @@ static void launch_band(const DevLevel& L, const mg_grid& G, T* u, const T* rhs,
   }
 }
 
+template <typename T>
+struct BandBuf;
+template <>
+struct BandBuf<double> {
+  static double* get(const DevLevel& L) { return L.z64; }
+};
+template <>
+struct BandBuf<float> {
+  static float* get(const DevLevel& L) { return L.z32; }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_copy_list(const int32_t* __restrict__ list, int n,
+                                                   const T* __restrict__ src, T* __restrict__ dst) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[list[i]] = src[list[i]];
+}
+
 template <int D, typename T>
 void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, const T* rhs,
                   T* tmp, int batch, hipStream_t s, const DevLevel* C, const T* uc,
@@ -1387,14 +1405,20 @@ void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, co
   a.rhs = rhs;
   a.h2 = (T)(L.g.h * L.g.h);
   a.inv2d = (T)(1.0 / (2.0 * D));
+  a.uband = uin;
   a.write_all = L.nchunks ? 0 : 1;
-  a.nchunks = L.nchunks;
+  // 2D: the tiles and the first launch's chunks share a launch; 3D chunks (which hold the
+  // 27-point ghost rows in registers) get launches of their own, so that the tiles keep
+  // their occupancy
+  const int k0 = D == 2 ? 1 : 0;
+  a.nchunks = L.nchunks && k0 == 1 ? L.sub[1] - L.sub[0] : 0;
   a.phases = L.bc_phases;
   a.hdr = L.bc_hdr;
   a.data = L.bc_data;
   const int nb = a.nchunks + a.nbt;
-  if (!L.nchunks && C) {
-    // the per-phase boundary path reads u in place: interpolate first
+  if ((!L.nchunks || D == 3) && C) {
+    // the per-phase boundary path reads u in place, and 3D chunks hold no interpolation
+    // data in registers: interpolate first
     launch_prolong<D, T>(L, *C, uc, const_cast<T*>(uin), s);
     a.prolong = 0;
   }
@@ -1412,7 +1436,33 @@ void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, co
     else
       launch_relax_kernel<D, T, kRelaxPlain>(a, nb, L, s);
   }
-  if (!L.nchunks) launch_band<D, T>(L, G, uout, rhs, tmp, batch, s);
+  if (!L.nchunks) {
+    launch_band<D, T>(L, G, uout, rhs, tmp, batch, s);
+    return;
+  }
+  // the relaxation's later launches (chunks only): launch k >= 1 reads the band and ghost
+  // values from uout (k odd) or z (k even) and everything else from uout, and writes its
+  // owned nodes to z (k odd) or uout (k even)
+  T* z = BandBuf<T>::get(L);
+  for (int k = k0; k < L.nsub; ++k) {
+    RelaxArgs<T> b = a;
+    b.ntiles = 0;
+    b.nbt = 0;
+    b.prolong = 0;
+    b.rf = nullptr;
+    b.uin = k == 0 ? uin : uout;
+    b.uband = k == 0 ? uin : (k & 1) ? uout : z;
+    b.uout = k == 0 ? uout : (k & 1) ? z : uout;
+    b.nchunks = L.sub[k + 1] - L.sub[k];
+    b.hdr = L.bc_hdr + (size_t)L.sub[k] * kBandHdr;
+    if (b.nchunks) launch_relax_kernel<D, T, kRelaxPlain>(b, b.nchunks, L, s);
+  }
+  if (!(L.nsub & 1)) {
+    // an even number of launches leaves the band and ghost values in z
+    if (L.nband_list)
+      hipLaunchKernelGGL((k_copy_list<T>), dim3(lin_grid(L.nband_list)), dim3(256), 0, s,
+                         L.band_list, L.nband_list, (const T*)z, uout);
+  }
 }
 
 template <typename T>

@@ -819,14 +819,16 @@ std::vector<std::pair<size_t, size_t>> initial_runs(const std::vector<std::pair<
 // Relaxation chunks of level l.  A relaxation is P = 3 + 3 lambda phases: 0 red interior,
 // 1 black interior, 2 ghosts, then for k = 1..lambda phases 3k (red band), 3k + 1 (black
 // band), 3k + 2 (ghosts).  The nodes written by the boundary part (band and ghost nodes) are
-// split into Morton-ordered runs; each run's node set S is closed backwards over the phases:
-// a node whose value after phase t is needed, and which phase t updates, needs the values
-// after phase t - 1 of every node it reads.  A chunk with more updated ghosts, red or black
-// entries or read-only entries than its threads hold is split in two.  Returns false when a small run is still too
-// large, when the phases do not fit the 31 bits of a phase mask, or when the redundant work
-// exceeds max_redundancy times the owned nodes (the level then relaxes its boundary part
-// with one launch per phase).
-bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redundancy) {
+// split into Morton-ordered runs.  The phases are taken R at a time (one launch each, whole
+// sweeps); for every launch each run's node set is closed backwards over the launch's
+// phases: a node whose value after phase t is needed, and which phase t updates, needs the
+// values after phase t - 1 of every node it reads.  A chunk with more updated ghosts, red or
+// black entries or read-only entries than its threads hold is split in two.  Returns false
+// when a small run is still too large, when R does not divide the phases or its mask bits do
+// not fit, or when the redundant work exceeds max_redundancy times the owned nodes per launch
+// (the caller then tries fewer phases per launch, and the level finally relaxes its boundary
+// part with one launch per phase).
+bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redundancy, int R) {
   HostLevel& HL = H->host[l];
   const int D = H->dim, lambda = H->grid.lambda;
   const Geo& g = HL.g;
@@ -839,8 +841,11 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
   HL.bc_smax = 0;
   HL.bc_entries = 0;
   HL.bc_nown = 0;
-  // mask bits: P phases, then D + 2^D interpolation bits, bit 31 owned
-  if (P + D + (1 << D) > 31) return false;
+  HL.bc_range = R;
+  HL.bc_sub.assign(1, 0);
+  // launches of R phases each (whole sweeps); mask bits: R phases, then D + 2^D
+  // interpolation bits, bit 30 band or ghost node, bit 31 owned
+  if (R % 3 != 0 || P % R != 0 || R + D + (1 << D) > 30) return false;
   // role of a node: 1 red band, 2 black band, 3 ghost, 4 red interior off the band,
   // 5 black interior off the band
   std::vector<int8_t> role(nn, 0);
@@ -888,18 +893,20 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
   std::vector<int32_t> lid(nn, -1);
   std::vector<char> owned(nn, 0);
   std::vector<int32_t> touched, rd;
-  std::vector<std::pair<size_t, size_t>> pending = initial_runs(U, own_target);
   const double cNh = H->grid.cN * g.h;
+  for (int p0 = 0; p0 < P; p0 += R) {
+  const int p1 = p0 + R;
+  std::vector<std::pair<size_t, size_t>> pending = initial_runs(U, own_target);
   while (!pending.empty()) {
     const auto [a, b] = pending.back();
     pending.pop_back();
     touched.clear();
     for (size_t i = a; i < b; ++i) {
-      need[U[i].second] = (int16_t)(P - 1);
+      need[U[i].second] = (int16_t)(p1 - 1);
       owned[U[i].second] = 1;
       touched.push_back(U[i].second);
     }
-    for (int p = P - 1; p >= 0; --p) {
+    for (int p = p1 - 1; p >= p0; --p) {
       const size_t nt = touched.size();
       for (size_t i = 0; i < nt; ++i) {
         const int32_t v = touched[i];
@@ -914,9 +921,8 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     // entries: the updated ghosts, the red-updated, the black-updated, the read-only nodes;
     // each run by node index
     auto run_of = [&](int32_t v) {
-      if (role[v] == 3 && need[v] >= 2) return 0;
-      if ((role[v] == 1 || role[v] == 4) && need[v] >= 0) return 1;
-      if ((role[v] == 2 || role[v] == 5) && need[v] >= 1) return 2;
+      for (int p = p0; p < p1; ++p)
+        if (updates(role[v], p) && need[v] >= p) return p % 3 == 2 ? 0 : (p % 3 == 0 ? 1 : 2);
       return 3;
     };
     std::sort(touched.begin(), touched.end(), [&](int32_t x, int32_t y) {
@@ -929,14 +935,14 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     for (int32_t v : touched) ++cnt[run_of(v)];
     const int ng = cnt[0], nr = cnt[1], nbk = cnt[2];
     bool ok = ng <= kChunkThreads && nr <= kBandColourSlots * kChunkThreads &&
-              nbk <= kBandColourSlots * kChunkThreads && cnt[3] <= kBandHaloSlots * kChunkThreads;
+              nbk <= kBandColourSlots * kChunkThreads && cnt[3] <= band_halo_slots(D) * kChunkThreads;
     for (int32_t v : touched)
       if (owned[v] && run_of(v) == 3) ok = false;  // an owned node is always updated
     if (ok) {
       for (int i = 0; i < ns; ++i) lid[touched[i]] = i;
       for (int i = 0; i < ns && ok; ++i) {
         const int32_t v = touched[i];
-        if (role[v] == 3 || need[v] < ((role[v] == 1 || role[v] == 4) ? 0 : 1)) continue;
+        if (role[v] == 3 || run_of(v) == 3) continue;
         for (int a2 = 0; a2 < D; ++a2)
           if (lid[v - g.st[a2]] < 0 || lid[v + g.st[a2]] < 0) ok = false;
       }
@@ -964,8 +970,9 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     for (int32_t v : touched) Dv.push_back(v);
     for (int32_t v : touched) {
       uint32_t m = owned[v] ? 0x80000000u : 0u;
-      for (int p = 0; p < P; ++p)
-        if (updates(role[v], p) && need[v] >= p) m |= 1u << p;
+      if (role[v] >= 1 && role[v] <= 3) m |= 0x40000000u;
+      for (int p = p0; p < p1; ++p)
+        if (updates(role[v], p) && need[v] >= p) m |= 1u << (p - p0);
       Dv.push_back((int32_t)m);
     }
     for (int32_t v : touched)
@@ -1004,7 +1011,7 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
           if (exists && HC.cls[p * HC.g.npp + jc[0] + HC.g.st[1] * jc[1] + HC.g.st[2] * jc[2]] != 0)
             bits |= 1u << (D + m);
         }
-        Dv[off + ns + i] |= (int32_t)(bits << P);
+        Dv[off + ns + i] |= (int32_t)(bits << R);
         Dv.push_back((int32_t)(p * HC.g.npp + jb[0] + HC.g.st[1] * jb[1] + HC.g.st[2] * jb[2]));
       }
     }
@@ -1050,7 +1057,11 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
       owned[v] = 0;
     }
   }
-  if (!U.empty() && (double)HL.bc_entries > max_redundancy * (double)U.size()) return false;
+  HL.bc_sub.push_back(HL.bc_nchunks);
+  }
+  const int S = P / R;
+  if (!U.empty() && (double)HL.bc_entries > max_redundancy * (double)S * (double)U.size())
+    return false;
   return true;
 }
 
@@ -1101,7 +1112,7 @@ void compose_extension(const HostLevel& HL, const std::vector<int32_t>& eid,
 
 // Extension chunks of level l: each chunk owns a Morton-ordered run of extension nodes and
 // the ghost nodes their composed weights name.  A chunk with more than kChunkMaxEntries
-// extension nodes, kChunkThreads ghost sources or kExtMaxTerms terms is split in two;
+// extension nodes, kExtMaxGhosts ghost sources or kExtMaxTerms terms is split in two;
 // returns false when a single node is still too large, or a source is neither extension
 // node nor ghost.
 bool build_ext_chunks(mg_handle_s* H, int l, int own_target) {
@@ -1145,7 +1156,7 @@ bool build_ext_chunks(mg_handle_s* H, int l, int own_target) {
     const int ne = (int)(b - a), ngs = (int)ghosts_e.size();
     int64_t nt = 0;
     for (size_t i = a; i < b; ++i) nt += toff[U[i].second + 1] - toff[U[i].second];
-    if (ne > kChunkMaxEntries || ngs > kChunkThreads || nt > kExtMaxTerms) {
+    if (ne > kChunkMaxEntries || ngs > kExtMaxGhosts || nt > kExtMaxTerms) {
       for (int32_t q : ghosts_e) lid[q] = -1;
       if (b - a <= 1) return false;
       const size_t m = a + (b - a) / 2;
