@@ -119,6 +119,13 @@ int upload_level(mg_handle_s* H, int l) {
       }
     }
   }
+  if (!S.et_node.empty()) {
+    L.net = (int)S.et_node.size();
+    if ((rc = upload(&L.et_node, S.et_node))) return rc;
+    if ((rc = upload(&L.et_off, S.et_off))) return rc;
+    if ((rc = upload(&L.et_src, S.et_src))) return rc;
+    if ((rc = upload(&L.et_wt, S.et_wt))) return rc;
+  }
   if (S.ec_nchunks) {
     L.nechunks = S.ec_nchunks;
     L.ec_smax = S.ec_smax;
@@ -390,7 +397,8 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
 }
 
 void free_level(DevLevel& L) {
-  void* ptrs[] = {L.bc_hdr, L.bc_data, L.z64, L.z32, L.band_list, L.ec_hdr, L.ec_data, L.rcls, L.gw,
+  void* ptrs[] = {L.bc_hdr, L.bc_data, L.z64, L.z32, L.band_list, L.ec_hdr, L.ec_data,
+                  L.et_node, L.et_off, L.et_src, L.et_wt, L.rcls, L.gw,
                   L.cls, L.phi, L.tiles, L.ghosts, L.ghost_off, L.red, L.black, L.red_off, L.black_off,
                   L.ext, L.ext_merged, L.ext_off, L.dag_off, L.dag_start, L.rcode, L.u64[0],
                   L.u64[1], L.rhs64, L.r64, L.gtmp64, L.u32[0], L.u32[1], L.rhs32, L.r32, L.gtmp32,
@@ -556,10 +564,13 @@ int setup_impl(const double* phi, const mg_bc_rule* bc, mg_bc_fn fn, void* ctx,
         S.bc_data.clear();
         S.bc_sub.clear();
       }
+      // extension chunks (each evaluates the ghost defects it needs); where they cannot be
+      // built, a gather of the ghost defects the defect launch has written
       if (!build_ext_chunks(H, l, kExtChunkOwn)) {
         S.ec_nchunks = 0;
         S.ec_hdr.clear();
         S.ec_data.clear();
+        build_ext_terms(H, l);
       }
     }
   // the coarsest right-hand side of one problem is staged in 64 KB of LDS

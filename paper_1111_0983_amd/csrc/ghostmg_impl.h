@@ -126,6 +126,11 @@ struct HostLevel {
   std::vector<int32_t> ec_hdr;
   std::vector<int32_t> ec_data;
   int ec_nchunks = 0, ec_smax = 0;
+  // the same composed terms as flat arrays (3D: a gather after the defect, which has already
+  // written the ghost defects): extension node, term offsets (records + 1), ghost node and
+  // weight of every term
+  std::vector<int32_t> et_node, et_off, et_src;
+  std::vector<double> et_wt;
   // coarsest level
   std::vector<int32_t> umap;            // unknown node indices, by problem
   std::vector<int32_t> umap_off;        // batch + 1
@@ -149,6 +154,9 @@ struct DevLevel {
   int32_t *bc_hdr = nullptr, *bc_data = nullptr;
   int nechunks = 0, ec_smax = 0;
   int32_t *ec_hdr = nullptr, *ec_data = nullptr;
+  int net = 0;
+  int32_t *et_node = nullptr, *et_off = nullptr, *et_src = nullptr;
+  double* et_wt = nullptr;
   int8_t* rcls = nullptr;
   double* gw = nullptr;
   int8_t* cls = nullptr;

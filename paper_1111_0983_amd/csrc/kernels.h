@@ -114,5 +114,6 @@ size_t defect_lds(const DevLevel& L);
 int build_hierarchy(mg_handle_s* H, const double* phi);
 bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redundancy, int R);
 bool build_ext_chunks(mg_handle_s* H, int l, int own_target);
+bool build_ext_terms(mg_handle_s* H, int l);
 
 }  // namespace ghostmg

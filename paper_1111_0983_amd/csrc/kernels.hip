@@ -63,12 +63,18 @@ template <int D, typename T>
 __device__ __forceinline__ double ghost_apply(const GhostRec& r, const double* __restrict__ w,
                                               const Geo& g, const T* __restrict__ u) {
   constexpr int K = Pow3<D>::value;
+  // all weights, then all values (taps of zero weight read the ghost itself), then the sum
+  double wv[K];
+  T uv[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) wv[t] = w[t];
+#pragma unroll
+  for (int t = 0; t < K; ++t)
+    uv[t] = u[wv[t] != 0.0 ? r.node + template_offset<D>(t, r.s, g.st) : r.node];
   double acc = 0.0;
 #pragma unroll
-  for (int t = 0; t < K; ++t) {
-    const double wt = w[t];
-    if (wt != 0.0) acc += wt * (double)u[r.node + template_offset<D>(t, r.s, g.st)];
-  }
+  for (int t = 0; t < K; ++t)
+    if (wv[t] != 0.0) acc += wv[t] * (double)uv[t];
   return acc;
 }
 
@@ -1481,6 +1487,33 @@ static void launch_extend(const DevLevel& L, T* r, int batch, hipStream_t s) {
   }
 }
 
+// every extension node takes its composed combination of the ghost defects in r (FP64,
+// terms in ascending ghost order, the same arithmetic as the extension chunks)
+template <typename TO>
+__global__ void __launch_bounds__(256) k_ext_terms(int n, const int32_t* __restrict__ node,
+                                                   const int32_t* __restrict__ off,
+                                                   const int32_t* __restrict__ src,
+                                                   const double* __restrict__ wt, TO* r) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int t0 = off[i], t1 = off[i + 1];
+  double v = 0.0;
+  int t = t0;
+  // four terms in flight per pass
+  for (; t + 4 <= t1; t += 4) {
+    double w[4], x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      w[q] = wt[t + q];
+      x[q] = (double)r[src[t + q]];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v += w[q] * x[q];
+  }
+  for (; t < t1; ++t) v += wt[t] * (double)r[src[t]];
+  r[node[i]] = (TO)v;
+}
+
 template <int D, typename T, typename TO>
 void launch_defect(const DevLevel& L, const T* u, const T* rhs, TO* r, uint64_t* norms,
                    bool with_ext, int batch, hipStream_t s) {
@@ -1505,7 +1538,13 @@ void launch_defect(const DevLevel& L, const T* u, const T* rhs, TO* r, uint64_t*
   if (nb)
     hipLaunchKernelGGL((k_defect<D, T, TO>), dim3(nb), dim3(256),
                        a.nechunks ? defect_lds(L) : 0, s, a);
-  if (with_ext && !a.nechunks) launch_extend<TO>(L, r, batch, s);
+  if (with_ext && !a.nechunks) {
+    if (L.net)
+      hipLaunchKernelGGL((k_ext_terms<TO>), dim3(lin_grid(L.net)), dim3(256), 0, s, L.net,
+                         L.et_node, L.et_off, L.et_src, L.et_wt, r);
+    else
+      launch_extend<TO>(L, r, batch, s);
+  }
 }
 
 template <int D>

@@ -1110,6 +1110,29 @@ void compose_extension(const HostLevel& HL, const std::vector<int32_t>& eid,
   }
 }
 
+// Composed extension terms of level l as flat arrays, for a gather launch after the defect
+// (the ghost defects are then read from r): per extension record its node and term range,
+// per term the ghost node and weight.  Returns false when a source is neither extension
+// node nor ghost.
+bool build_ext_terms(mg_handle_s* H, int l) {
+  HostLevel& HL = H->host[l];
+  HL.et_node.clear();
+  HL.et_off.clear();
+  HL.et_src.clear();
+  HL.et_wt.clear();
+  if (HL.ext.empty()) return true;
+  const size_t nn = HL.cls.size();
+  std::vector<int32_t> eid(nn, -1), gidx(nn, -1);
+  for (size_t i = 0; i < HL.ext.size(); ++i) eid[HL.ext[i].node] = (int32_t)i;
+  for (size_t i = 0; i < HL.ghosts.size(); ++i) gidx[HL.ghosts[i].node] = (int32_t)i;
+  for (const ExtRec& r : HL.ext)
+    for (int a = 0; a < 3; ++a)
+      if (r.src[a] >= 0 && eid[r.src[a]] < 0 && gidx[r.src[a]] < 0) return false;
+  compose_extension(HL, eid, HL.et_off, HL.et_src, HL.et_wt);
+  for (const ExtRec& r : HL.ext) HL.et_node.push_back(r.node);
+  return true;
+}
+
 // Extension chunks of level l: each chunk owns a Morton-ordered run of extension nodes and
 // the ghost nodes their composed weights name.  A chunk with more than kChunkMaxEntries
 // extension nodes, kExtMaxGhosts ghost sources or kExtMaxTerms terms is split in two;
