@@ -564,9 +564,10 @@ int setup_impl(const double* phi, const mg_bc_rule* bc, mg_bc_fn fn, void* ctx,
         S.bc_data.clear();
         S.bc_sub.clear();
       }
-      // extension chunks (each evaluates the ghost defects it needs); where they cannot be
-      // built, a gather of the ghost defects the defect launch has written
-      if (!build_ext_chunks(H, l, kExtChunkOwn)) {
+      // 2D: extension chunks (each evaluates the few ghost defects it needs); 3D (an
+      // extension node's terms reach hundreds of 27-tap ghost rows) and where chunks cannot
+      // be built: a gather of the ghost defects the defect launch has written
+      if (H->dim == 3 || !build_ext_chunks(H, l, kExtChunkOwn)) {
         S.ec_nchunks = 0;
         S.ec_hdr.clear();
         S.ec_data.clear();

@@ -1487,31 +1487,35 @@ static void launch_extend(const DevLevel& L, T* r, int batch, hipStream_t s) {
   }
 }
 
-// every extension node takes its composed combination of the ghost defects in r (FP64,
-// terms in ascending ghost order, the same arithmetic as the extension chunks)
+// every extension node takes its composed combination of the ghost defects in r: the
+// kExtLanes lanes of a node take every kExtLanes-th term (FP64, four loads in flight each),
+// then their partial sums are added pairwise across the lanes
+constexpr int kExtLanes = 16;
 template <typename TO>
 __global__ void __launch_bounds__(256) k_ext_terms(int n, const int32_t* __restrict__ node,
                                                    const int32_t* __restrict__ off,
                                                    const int32_t* __restrict__ src,
                                                    const double* __restrict__ wt, TO* r) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const int t0 = off[i], t1 = off[i + 1];
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  const int i = gid / kExtLanes, lane = gid % kExtLanes;
+  const int ic = i < n ? i : n - 1;
+  const int t0 = off[ic], t1 = i < n ? off[ic + 1] : t0;
   double v = 0.0;
-  int t = t0;
-  // four terms in flight per pass
-  for (; t + 4 <= t1; t += 4) {
+  int t = t0 + lane;
+  for (; t + 3 * kExtLanes < t1; t += 4 * kExtLanes) {
     double w[4], x[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      w[q] = wt[t + q];
-      x[q] = (double)r[src[t + q]];
+      w[q] = wt[t + q * kExtLanes];
+      x[q] = (double)r[src[t + q * kExtLanes]];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) v += w[q] * x[q];
   }
-  for (; t < t1; ++t) v += wt[t] * (double)r[src[t]];
-  r[node[i]] = (TO)v;
+  for (; t < t1; t += kExtLanes) v += wt[t] * (double)r[src[t]];
+#pragma unroll
+  for (int o = kExtLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kExtLanes);
+  if (i < n && lane == 0) r[node[i]] = (TO)v;
 }
 
 template <int D, typename T, typename TO>
@@ -1540,7 +1544,7 @@ void launch_defect(const DevLevel& L, const T* u, const T* rhs, TO* r, uint64_t*
                        a.nechunks ? defect_lds(L) : 0, s, a);
   if (with_ext && !a.nechunks) {
     if (L.net)
-      hipLaunchKernelGGL((k_ext_terms<TO>), dim3(lin_grid(L.net)), dim3(256), 0, s, L.net,
+      hipLaunchKernelGGL((k_ext_terms<TO>), dim3(lin_grid((int64_t)L.net * kExtLanes)), dim3(256), 0, s, L.net,
                          L.et_node, L.et_off, L.et_src, L.et_wt, r);
     else
       launch_extend<TO>(L, r, batch, s);
