@@ -156,18 +156,22 @@ constexpr size_t tile_lds() {
 template <int D, typename T>
 __device__ __forceinline__ T restrict_box(uint8_t c, const T* rr) {
   constexpr int KT = Pow3<D>::value;
-  const int lx = (c & 1) ? -1 : 0, hx = (c & 2) ? 1 : 0;
-  const int ly = (c & 4) ? -1 : 0, hy = (c & 8) ? 1 : 0;
-  const int lz = D == 3 && (c & 16) ? -1 : 0, hz = D == 3 && (c & 32) ? 1 : 0;
+  // per axis the 1D factors of offsets -1, 0, +1 (0 outside the box): the same exact
+  // products of (1,2,1)/4, (2,2)/4 or 1 as the box rule, in the same summation order
+  T f[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const bool lo = a < D && (c >> (2 * a)) & 1, hi = a < D && (c >> (2 * a + 1)) & 1;
+    f[a][0] = lo ? (hi ? (T)0.25 : (T)0.5) : (T)0;
+    f[a][1] = lo && hi ? (T)0.5 : (lo || hi ? (T)0.5 : (T)1);
+    f[a][2] = hi ? (lo ? (T)0.25 : (T)0.5) : (T)0;
+  }
   T s = 0;
 #pragma unroll
   for (int q = 0; q < KT; ++q) {
-    const int kx = q / (D == 3 ? 9 : 3) - 1, ky = (q / (D == 3 ? 3 : 1)) % 3 - 1;
-    const int kz = D == 3 ? q % 3 - 1 : 0;
-    const bool inbox = kx >= lx && kx <= hx && ky >= ly && ky <= hy && kz >= lz && kz <= hz;
-    const T w = inbox ? (T)(restrict_w1d(lx, hx, kx) * restrict_w1d(ly, hy, ky) *
-                            (D == 3 ? restrict_w1d(lz, hz, kz) : 1.0))
-                      : (T)0;
+    const int kx = q / (D == 3 ? 9 : 3), ky = (q / (D == 3 ? 3 : 1)) % 3;
+    const int kz = D == 3 ? q % 3 : 1;
+    const T w = D == 3 ? f[0][kx] * f[1][ky] * f[2][kz] : f[0][kx] * f[1][ky];
     s += w * rr[q];
   }
   return s;
@@ -392,8 +396,8 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
       }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        T w1 = 1;
-        for (int q = 0; q < nodd[h]; ++q) w1 *= (T)0.5;
+        // 2^-(odd coordinates), exactly
+        const T w1 = nodd[h] == 0 ? (T)1 : nodd[h] == 1 ? (T)0.5 : nodd[h] == 2 ? (T)0.25 : (T)0.125;
         T num = 0, den = 0;
 #pragma unroll
         for (int m = 0; m < NCD; ++m) {
@@ -401,12 +405,13 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
 #pragma unroll
           for (int q = 0; q < D; ++q)
             if ((m >> q) & 1) ex = ex && odd[h][q];
-          if (!ex) continue;
-          num += w1 * ce[h][m];
-          den += w1;
+          num += ex ? w1 * ce[h][m] : (T)0;
+          den += ex ? w1 : (T)0;
         }
-        // den == 1 when every candidate carries an unknown: num / den == num exactly
-        if (live[h] && den > (T)0) su[ii[h]] = uo[h] + (den == (T)1 ? num : num / den);
+        // den == 1 when every candidate carries an unknown: num / den == num exactly, and the
+        // division is left to the nodes next to the boundary
+        if (den != (T)1 && den > (T)0) num = num / den;
+        if (live[h] && den > (T)0) su[ii[h]] = uo[h] + num;
       }
     }
   }
