@@ -21,14 +21,16 @@ constexpr int kChunkPerThread = 4;     // chunk entries owned by one thread
 constexpr int kChunkMaxEntries = kChunkPerThread * kChunkThreads;
 constexpr int kExtMaxTerms = 6 * kChunkThreads;  // composed extension terms per chunk
 constexpr int kExtMaxGhosts = 2 * kChunkThreads;  // ghost sources per extension chunk
-// relaxation chunks: per thread one updated ghost, kBandColourSlots red and as many black
-// entries, band_halo_slots(D) entries that are read but never updated (more in 3D, where a
-// band patch's closure has more of them)
-constexpr int kBandColourSlots = 2;
+// relaxation chunks: per thread one updated ghost, band_colour_slots(D) red and as many
+// black entries, band_halo_slots(D) entries that are read but never updated (more in 3D,
+// where a band patch's closure has more of them).  In 2D a thread updates one entry per
+// colour phase (short phases, more chunks); in 3D two (the level-0 chunk work is large and
+// more chunks would add redundant entries)
+constexpr int band_colour_slots(int D) { return D == 2 ? 1 : 2; }
 constexpr int kBandHaloSlots2D = 1, kBandHaloSlots3D = 4;
 constexpr int band_halo_slots(int D) { return D == 2 ? kBandHaloSlots2D : kBandHaloSlots3D; }
 constexpr int band_max_entries(int D) {
-  return (1 + 2 * kBandColourSlots + band_halo_slots(D)) * kChunkThreads;
+  return (1 + 2 * band_colour_slots(D) + band_halo_slots(D)) * kChunkThreads;
 }
 
 // Tile shapes of the node-parallel kernels: 64 x 16 nodes in 2D, 16 x 8 x 8 in 3D.
@@ -88,8 +90,8 @@ struct HostLevel {
   // interior, black interior, ghosts; lambda times red band, black band, ghosts), taken
   // bc_range at a time, with a chunk set per launch.
   // Entries come in four runs: the updated ghosts (at most kChunkThreads), the entries the
-  // red phases update, those the black phases update (at most kBandColourSlots *
-  // kChunkThreads each), and the entries only read (at most band_halo_slots(D) * kChunkThreads);
+  // red phases update, those the black phases update (at most band_colour_slots(D)
+  // * kChunkThreads each), and the entries only read (at most band_halo_slots(D) * kChunkThreads);
   // entry i of a run belongs to thread i % kChunkThreads.  Chunk c: header
   // bc_hdr[c * kBandHdr ..] = {entries, updated ghosts | red << 10 | black << 20, offsets
   // into bc_data of: the per-entry arrays, the ghost stencil ids, the ghost

@@ -474,12 +474,12 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
 // The chunk's node set is closed under the dependencies of its owned nodes (band and
 // ghost nodes) through the 3 + 3 lambda phases (red interior, black interior, ghosts; then
 // lambda times red band, black band, ghosts, Sec. 3.2).  Its entries come in runs: updated
-// ghosts, red-updated, black-updated, read-only; a thread holds one ghost, kBandColourSlots
+// ghosts, red-updated, black-updated, read-only; a thread holds one ghost, band_colour_slots(D)
 // red and black entries and band_halo_slots(D) read-only entries (slot s of a run: entry
 // tid + s * kChunkThreads of the run), with their node index, phase mask, neighbour ids,
 // right-hand side and current value in registers (the ghost also its stencil ids, weights
 // and constant); only the values are shared, in LDS.  A phase updates at most
-// kBandColourSlots entries per thread (one ghost in a ghost phase) and issues all its LDS
+// band_colour_slots(D) entries per thread (one ghost in a ghost phase) and issues all its LDS
 // reads before its writes: no update reads a value of its own phase (red reads black and
 // ghosts, black reads red and ghosts, the ghosts read the values before their phase).
 // Phases are separated by workgroup barriers; a ghost phase computes every new ghost value
@@ -513,7 +513,7 @@ template <int D, typename T, int MODE>
 __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
   constexpr bool PROLONG = MODE == kRelaxProlong, RESTRICT = MODE == kRelaxRestrict;
   constexpr int K = Pow3<D>::value;
-  constexpr int NC = kBandColourSlots, NH = band_halo_slots(D);
+  constexpr int NC = band_colour_slots(D), NH = band_halo_slots(D);
   constexpr int NS = 1 + 2 * NC + NH;  // slots: ghost, red, black, read-only
   constexpr int NCAND = 1 << D;
   const int cu = __builtin_amdgcn_readfirstlane(c);

@@ -934,8 +934,8 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     int cnt[4] = {0, 0, 0, 0};
     for (int32_t v : touched) ++cnt[run_of(v)];
     const int ng = cnt[0], nr = cnt[1], nbk = cnt[2];
-    bool ok = ng <= kChunkThreads && nr <= kBandColourSlots * kChunkThreads &&
-              nbk <= kBandColourSlots * kChunkThreads && cnt[3] <= band_halo_slots(D) * kChunkThreads;
+    bool ok = ng <= kChunkThreads && nr <= band_colour_slots(D) * kChunkThreads &&
+              nbk <= band_colour_slots(D) * kChunkThreads && cnt[3] <= band_halo_slots(D) * kChunkThreads;
     for (int32_t v : touched)
       if (owned[v] && run_of(v) == 3) ok = false;  // an owned node is always updated
     if (ok) {
