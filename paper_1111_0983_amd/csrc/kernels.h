@@ -106,9 +106,7 @@ template <int D>
 void launch_dc_update(const DevLevel& L, double* u64, const float* u32, float* u32_zero,
                       hipStream_t s);
 
-// dynamic LDS bytes of launch_relax / launch_defect for a level
-template <int D, typename T>
-size_t relax_lds(const DevLevel& L);
+// dynamic LDS bytes of launch_defect for a level
 size_t defect_lds(const DevLevel& L);
 
 int build_hierarchy(mg_handle_s* H, const double* phi);

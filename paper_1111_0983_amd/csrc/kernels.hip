@@ -118,32 +118,45 @@ __device__ __forceinline__ T prolong_correct(T u, const T* w, const int8_t* cc, 
 }
 
 // coarse patch under a tile and its 2-node ring (fused interpolation)
-template <int D>
+// The block of nodes one relaxation workgroup takes: a whole tile (SUB = 1) or, on levels
+// with few tiles, one of the SUB^D parts of a tile halved along every axis (more workgroups,
+// each with fewer serial passes; part origins stay even)
+template <int D, int SUB>
+struct RTile {
+  static constexpr int X = Tile<D>::X / SUB, Y = Tile<D>::Y / SUB;
+  static constexpr int Z = D == 3 ? Tile<D>::Z / SUB : 1;
+  static constexpr int N = D == 3 ? SUB * SUB * SUB : SUB * SUB;  // parts per tile
+};
+
+// the coarse nodes the interpolation into a block (and its two-node ring) reads
+template <int D, int SUB>
 struct CPatch {
-  static constexpr int X = Tile<D>::X / 2 + 3, Y = Tile<D>::Y / 2 + 3;
-  static constexpr int Z = D == 3 ? Tile<D>::Z / 2 + 3 : 1;
+  static constexpr int X = RTile<D, SUB>::X / 2 + 3, Y = RTile<D, SUB>::Y / 2 + 3;
+  static constexpr int Z = D == 3 ? RTile<D, SUB>::Z / 2 + 3 : 1;
 };
 
 constexpr int kRelaxPlain = 0, kRelaxProlong = 1, kRelaxRestrict = 2;
 
 // bytes of the tile workgroup's auxiliary LDS area in each mode
-template <int D, typename T, int MODE>
+template <int D, typename T, int MODE, int SUB>
 constexpr size_t tile_aux_bytes() {
-  constexpr int FX = Tile<D>::X + 2, FY = Tile<D>::Y + 2, FZ = D == 3 ? Tile<D>::Z + 2 : 1;
-  constexpr size_t coarse = (size_t)CPatch<D>::X * CPatch<D>::Y * CPatch<D>::Z * sizeof(T);
+  using B = RTile<D, SUB>;
+  constexpr int FX = B::X + 2, FY = B::Y + 2, FZ = D == 3 ? B::Z + 2 : 1;
+  using CP = CPatch<D, SUB>;
+  constexpr size_t coarse = (size_t)CP::X * CP::Y * CP::Z * sizeof(T);
   constexpr size_t fine = MODE == kRelaxRestrict
                               ? (size_t)(2 * FX + 1) * (2 * FY + 1) * sizeof(T) + FZ * FY * FX
                               : 0;
   return ((coarse > fine ? coarse : fine) + 15) / 16 * 16;
 }
 
-template <int D, typename T, int MODE>
+template <int D, typename T, int MODE, int SUB>
 constexpr size_t tile_lds() {
-  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
-  constexpr int UX = TX + 4, UY = TY + 4, UZ = D == 3 ? TZ + 4 : 1;
-  constexpr int FX = TX + 2, FY = TY + 2, FZ = D == 3 ? TZ + 2 : 1;
-  constexpr int NCN = CPatch<D>::X * CPatch<D>::Y * CPatch<D>::Z;
-  return (size_t)(UZ * UY * UX + FZ * FY * FX) * sizeof(T) + tile_aux_bytes<D, T, MODE>() +
+  using B = RTile<D, SUB>;
+  constexpr int UX = B::X + 4, UY = B::Y + 4, UZ = D == 3 ? B::Z + 4 : 1;
+  constexpr int FX = B::X + 2, FY = B::Y + 2, FZ = D == 3 ? B::Z + 2 : 1;
+  constexpr int NCN = CPatch<D, SUB>::X * CPatch<D, SUB>::Y * CPatch<D, SUB>::Z;
+  return (size_t)(UZ * UY * UX + FZ * FY * FX) * sizeof(T) + tile_aux_bytes<D, T, MODE, SUB>() +
          (size_t)UZ * UY * UX + NCN;
 }
 
@@ -203,16 +216,18 @@ __device__ __forceinline__ void restrict_gather(const T* __restrict__ rf, int64_
 // one are relaxed first (they read only black, ghost or outside values, which this pass
 // leaves unchanged), then the black interior nodes of the tile (which read the fresh red
 // values).  The result is the global red sweep followed by the global black sweep; every
-// workgroup writes its own tile of uout: the interior nodes off the boundary band (the
-// relaxation chunks write the band and the ghosts), or, with write_all, every unknown.
-template <int D, typename T, int MODE>
+// workgroup writes its own block of uout (a tile, or a part of one: RTile): the interior
+// nodes off the boundary band (the relaxation chunks write the band and the ghosts), or,
+// with write_all, every unknown.
+template <int D, typename T, int MODE, int SUB>
 __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   constexpr bool PROLONG = MODE == kRelaxProlong, RESTRICT = MODE == kRelaxRestrict;
   static_assert(!RESTRICT || D == 2, "the restriction is fused in 2D only");
-  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+  using B = RTile<D, SUB>;
+  constexpr int TX = B::X, TY = B::Y, TZ = B::Z;
   constexpr int UX = TX + 4, UY = TY + 4, UZ = D == 3 ? TZ + 4 : 1;
   constexpr int FX = TX + 2, FY = TY + 2, FZ = D == 3 ? TZ + 2 : 1;
-  constexpr int CX = CPatch<D>::X, CY = CPatch<D>::Y, CZ = CPatch<D>::Z;
+  constexpr int CX = CPatch<D, SUB>::X, CY = CPatch<D, SUB>::Y, CZ = CPatch<D, SUB>::Z;
   constexpr int NUN = UZ * UY * UX, NFN = FZ * FY * FX, NCN = CZ * CY * CX;
   T* su = (T*)lds;
   T* sf = su + NUN;
@@ -220,14 +235,17 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   // restriction codes (restriction)
   unsigned char* aux = (unsigned char*)(sf + NFN);
   T* sce = (T*)aux;
-  int8_t* sc = (int8_t*)(aux + tile_aux_bytes<D, T, MODE>());  // codes of the U region
-  int8_t* scc = sc + NUN;                                      // coarse classes of the patch
-  const int tile = xcd_tile(tb, a.nbt);
-  if (tile >= a.ntiles) return;
+  int8_t* sc = (int8_t*)(aux + tile_aux_bytes<D, T, MODE, SUB>());  // codes of the U region
+  int8_t* scc = sc + NUN;  // coarse classes of the patch
+  // the parts of one tile are consecutive block numbers (the same XCD)
+  const int part = xcd_tile(tb, a.nbt);
+  if (part >= a.ntiles * B::N) return;
+  const int tile = part / B::N, q = part % B::N;
   const Geo& g = a.g;
   const int4 t = a.tiles[tile];
   const int64_t base = (int64_t)t.x * g.npp;
-  const int ox = t.y * TX, oy = t.z * TY, oz = t.w * TZ;
+  const int ox = t.y * Tile<D>::X + TX * (q % SUB), oy = t.z * Tile<D>::Y + TY * ((q / SUB) % SUB);
+  const int oz = D == 3 ? t.w * Tile<D>::Z + TZ * (q / (SUB * SUB)) : 0;
   // every global load of the thread is issued before the first is used: positions outside
   // the box read the tile's first node and are replaced by zero afterwards
   constexpr int NU = (NUN + 255) / 256, NF = (NFN + 255) / 256, NC = (NCN + 255) / 256;
@@ -357,61 +375,52 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
     __syncthreads();
     // u + interpolated correction at every unknown of the U region.  Node j takes the coarse
     // nodes floor(j / 2) and, along each odd coordinate, the next one up (weight 2^-(odd
-    // coordinates) each), over those that carry an unknown (Sec. 2.6.1); tile origins are even.
-    // Two nodes per pass; each node reads its 2^D candidate codes and values (the patch
-    // covers every candidate position, absent ones included) before any use.
+    // coordinates) each), over those that carry an unknown (Sec. 2.6.1).  Block origins are
+    // even, so the U region splits into cells of 2^D fine nodes (x, y, z in {2c, 2c + 1}) that
+    // all draw on the same 2^D coarse nodes c .. c + 1: a thread takes a cell, reads those
+    // coarse values and codes once and corrects the cell's nodes.
     constexpr int CS[3] = {1, CX, CX * CY};
     constexpr int NCD = 1 << D;
-    for (int i0 = threadIdx.x; i0 < NUN; i0 += 512) {
-      int ii[2], lb[2], nodd[2];
-      bool odd[2][3], live[2];
-      int8_t cc[2][NCD];
-      T ce[2][NCD], uo[2];
+    constexpr int KX = UX / 2, KY = UY / 2, KZ = D == 3 ? UZ / 2 : 1;
+    constexpr int FS[3] = {1, UX, UX * UY};
+    for (int cell = threadIdx.x; cell < KX * KY * KZ; cell += 256) {
+      const int cx = cell % KX, cy = (cell / KX) % KY, cz = cell / (KX * KY);
+      const int li0 = cx * CS[0] + cy * CS[1] + cz * CS[2];
+      const int ui0 = 2 * cx * FS[0] + 2 * cy * FS[1] + 2 * cz * FS[2];
+      int8_t cc[NCD], ucl[NCD];
+      T ce[NCD], uo[NCD];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i = i0 + 256 * h;
-        ii[h] = i < NUN ? i : i0;
-        const int x = ii[h] % UX, y = (ii[h] / UX) % UY, z = ii[h] / (UX * UY);
-        const int jr[3] = {x, y, z};  // j - o + 2 (o even): the parity of j
-        lb[h] = 0;
-        nodd[h] = 0;
+      for (int m = 0; m < NCD; ++m) {
+        int li = li0, ui = ui0;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) odd[h][q] = q < D && (jr[q] & 1);
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
-          nodd[h] += odd[h][q];
-          lb[h] += (jr[q] >> 1) * CS[q];  // (j >> 1) - (o / 2 - 1)
-        }
-        live[h] = i < NUN && sc[ii[h]] != 0;
-        uo[h] = su[ii[h]];
-#pragma unroll
-        for (int m = 0; m < NCD; ++m) {
-          int li = lb[h];
-#pragma unroll
-          for (int q = 0; q < D; ++q)
-            if ((m >> q) & 1) li += CS[q];
-          cc[h][m] = scc[li];
-          ce[h][m] = sce[li];
-        }
+        for (int q = 0; q < D; ++q)
+          if ((m >> q) & 1) li += CS[q], ui += FS[q];
+        cc[m] = scc[li];
+        ce[m] = sce[li];
+        ucl[m] = sc[ui];
+        uo[m] = su[ui];
       }
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        // 2^-(odd coordinates), exactly
-        const T w1 = nodd[h] == 0 ? (T)1 : nodd[h] == 1 ? (T)0.5 : nodd[h] == 2 ? (T)0.25 : (T)0.125;
+      for (int f = 0; f < NCD; ++f) {
+        // fine node f of the cell: bit q set where its coordinate q is odd
+        const int nodd = __builtin_popcount(f);  // 2^-(odd coordinates), exactly
+        const T w1 = nodd == 0 ? (T)1 : nodd == 1 ? (T)0.5 : nodd == 2 ? (T)0.25 : (T)0.125;
         T num = 0, den = 0;
 #pragma unroll
         for (int m = 0; m < NCD; ++m) {
-          bool ex = cc[h][m] != 0;
-#pragma unroll
-          for (int q = 0; q < D; ++q)
-            if ((m >> q) & 1) ex = ex && odd[h][q];
-          num += ex ? w1 * ce[h][m] : (T)0;
+          if ((m & f) != m) continue;  // candidate m moves along an even coordinate
+          const bool ex = cc[m] != 0;
+          num += ex ? w1 * ce[m] : (T)0;
           den += ex ? w1 : (T)0;
         }
         // den == 1 when every candidate carries an unknown: num / den == num exactly, and the
         // division is left to the nodes next to the boundary
         if (den != (T)1 && den > (T)0) num = num / den;
-        if (live[h] && den > (T)0) su[ii[h]] = uo[h] + num;
+        int ui = ui0;
+#pragma unroll
+        for (int q = 0; q < D; ++q)
+          if ((f >> q) & 1) ui += FS[q];
+        if (ucl[f] != 0 && den > (T)0) su[ui] = uo[f] + num;
       }
     }
   }
@@ -697,13 +706,13 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
 // kRelaxRestrict: it starts from zero with the right-hand side restricted from the finer
 // level's defect (and stores that right-hand side).  Each variant holds only the registers
 // of the paths it runs.
-template <int D, typename T, bool CHUNKS, int MODE>
+template <int D, typename T, bool CHUNKS, int MODE, int SUB>
 __global__ void __launch_bounds__(256) k_relax(RelaxArgs<T> a) {
   extern __shared__ __align__(16) unsigned char relax_smem[];
   if (CHUNKS && (int)blockIdx.x < a.nchunks)
     relax_chunk<D, T, MODE>(a, blockIdx.x, relax_smem);
   else
-    relax_tile<D, T, MODE>(a, (int)blockIdx.x - (CHUNKS ? a.nchunks : 0), relax_smem);
+    relax_tile<D, T, MODE, SUB>(a, (int)blockIdx.x - (CHUNKS ? a.nchunks : 0), relax_smem);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1303,18 +1312,27 @@ static inline int lin_grid(int64_t n) { return (int)((n + 255) / 256); }
 constexpr int kSingleWgBand = 8192;
 constexpr int kSingleWgExt = 24576;
 
-template <int D, typename T>
-size_t relax_lds(const DevLevel& L) {
-  return std::max(tile_lds<D, T, kRelaxProlong>(), (size_t)(L.bc_smax + kChunkThreads) * sizeof(T));
+template <int D, typename T, int MODE, int SUB>
+static void launch_relax_sub(RelaxArgs<T> a, const DevLevel& L, hipStream_t s) {
+  a.nbt = a.ntiles ? tile_grid(a.ntiles * RTile<D, SUB>::N) : 0;
+  const int nb = a.nchunks + a.nbt;
+  if (!nb) return;
+  const size_t lds =
+      std::max(tile_lds<D, T, MODE, SUB>(), (size_t)(L.bc_smax + kChunkThreads) * sizeof(T));
+  if (a.nchunks)
+    hipLaunchKernelGGL((k_relax<D, T, true, MODE, SUB>), dim3(nb), dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_relax<D, T, false, MODE, SUB>), dim3(nb), dim3(256), lds, s, a);
 }
 
+// tiles split in parts on levels with fewer than kSplitTilesBelow tiles (2D)
+constexpr int kSplitTilesBelow = 512;
+
 template <int D, typename T, int MODE>
-static void launch_relax_kernel(const RelaxArgs<T>& a, int nb, const DevLevel& L, hipStream_t s) {
-  const size_t lds = std::max(tile_lds<D, T, MODE>(), (size_t)(L.bc_smax + kChunkThreads) * sizeof(T));
-  if (a.nchunks)
-    hipLaunchKernelGGL((k_relax<D, T, true, MODE>), dim3(nb), dim3(256), lds, s, a);
-  else
-    hipLaunchKernelGGL((k_relax<D, T, false, MODE>), dim3(nb), dim3(256), lds, s, a);
+static void launch_relax_kernel(const RelaxArgs<T>& a, const DevLevel& L, hipStream_t s) {
+  if constexpr (D == 2)
+    if (a.ntiles > 0 && a.ntiles < kSplitTilesBelow) return launch_relax_sub<D, T, MODE, 2>(a, L, s);
+  launch_relax_sub<D, T, MODE, 1>(a, L, s);
 }
 
 size_t defect_lds(const DevLevel& L) { return (size_t)L.ec_smax * sizeof(double); }
@@ -1408,7 +1426,7 @@ void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, co
   }
   a.tiles = L.tiles;
   a.ntiles = L.ntiles;
-  a.nbt = L.ntiles ? tile_grid(L.ntiles) : 0;
+  a.nbt = 0;  // set by the launch (tiles or parts of tiles)
   a.g = L.g;
   a.rcls = L.rcls;
   a.uin = uin;
@@ -1426,7 +1444,6 @@ void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, co
   a.phases = L.bc_phases;
   a.hdr = L.bc_hdr;
   a.data = L.bc_data;
-  const int nb = a.nchunks + a.nbt;
   if ((!L.nchunks || D == 3) && C) {
     // the per-phase boundary path reads u in place, and 3D chunks hold no interpolation
     // data in registers: interpolate first
@@ -1439,14 +1456,12 @@ void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, co
     launch_restrict<D, T>(*F, L, rf, const_cast<T*>(rhs), const_cast<T*>(uin), s);
     restrict_ = false;
   }
-  if (nb) {
-    if (restrict_)
-      launch_relax_kernel<D, T, D == 2 ? kRelaxRestrict : kRelaxPlain>(a, nb, L, s);
-    else if (a.prolong)
-      launch_relax_kernel<D, T, kRelaxProlong>(a, nb, L, s);
-    else
-      launch_relax_kernel<D, T, kRelaxPlain>(a, nb, L, s);
-  }
+  if (restrict_)
+    launch_relax_kernel<D, T, D == 2 ? kRelaxRestrict : kRelaxPlain>(a, L, s);
+  else if (a.prolong)
+    launch_relax_kernel<D, T, kRelaxProlong>(a, L, s);
+  else
+    launch_relax_kernel<D, T, kRelaxPlain>(a, L, s);
   if (!L.nchunks) {
     launch_band<D, T>(L, G, uout, rhs, tmp, batch, s);
     return;
@@ -1466,7 +1481,7 @@ void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, co
     b.uout = k == 0 ? uout : (k & 1) ? z : uout;
     b.nchunks = L.sub[k + 1] - L.sub[k];
     b.hdr = L.bc_hdr + (size_t)L.sub[k] * kBandHdr;
-    if (b.nchunks) launch_relax_kernel<D, T, kRelaxPlain>(b, b.nchunks, L, s);
+    if (b.nchunks) launch_relax_kernel<D, T, kRelaxPlain>(b, L, s);
   }
   if (!(L.nsub & 1)) {
     // an even number of launches leaves the band and ghost values in z
@@ -1623,7 +1638,6 @@ void launch_dc_update(const DevLevel& L, double* u64, const float* u32, float* u
   template void launch_restrict<D, T>(const DevLevel&, const DevLevel&, const T*, T*, T*,     \
                                       hipStream_t);                                           \
   template void launch_prolong<D, T>(const DevLevel&, const DevLevel&, const T*, T*, hipStream_t); \
-  template size_t relax_lds<D, T>(const DevLevel&);
 
 GHOSTMG_INST(2, double)
 GHOSTMG_INST(2, float)
