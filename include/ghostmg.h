@@ -152,7 +152,8 @@ int mg_residual(mg_handle_t h, const double* f, const double* g, const double* u
  * relaxation that first takes the interpolated correction of level + 1 (the cycle's first
  * post-relaxation), 6 = a relaxation from zero with the right-hand side restricted from
  * level - 1 (the cycle's first pre-relaxation on a coarse level; 2D, else a restriction
- * launch followed by a relaxation), 7 = the coarsest solve (inverse times right-hand side).
+ * launch followed by a relaxation), 7 = the coarsest solve (its right-hand side restricted
+ * from level - 1's defect, as in a cycle, then the inverse times it).
  * level runs from 0 to the level above the coarsest (6: from 1; 7: the coarsest level only),
  * else MG_EINVAL.  The level's iterate,
  * defect and coarse arrays are overwritten; a later mg_solve is unaffected.  avg_ms: mean duration; bytes: the

@@ -43,10 +43,10 @@ int max_span(const std::vector<int32_t>& off) {
   return m;
 }
 
-constexpr int kMaxCoarse = 8192;
-// relaxation chunks: owned band and ghost nodes per chunk, and the redundant work (chunk
-// entries per owned node) above which a level relaxes its boundary with one launch per
-// phase instead; owned extension nodes per extension chunk
+// relaxation chunks: owned band and ghost nodes per chunk (2D; twice as many for the wider
+// 3D workgroups), and the redundant work (chunk entries per owned node) above which a level
+// relaxes its boundary with one launch per phase instead; owned extension nodes per
+// extension chunk
 constexpr int kChunkOwn = 320;
 constexpr double kChunkRedundancy2D = 4.0, kChunkRedundancy3D = 8.0;
 constexpr int kExtChunkOwn = 512;
@@ -138,6 +138,27 @@ int upload_level(mg_handle_s* H, int l) {
     if ((rc = upload(&L.umap_off, S.umap_off))) return rc;
     if ((rc = upload(&L.ainv_off, S.ainv_off))) return rc;
     if ((rc = upload(&L.ainv, S.ainv))) return rc;
+    if (dc) {
+      const std::vector<float> a32(S.ainv.begin(), S.ainv.end());
+      if ((rc = upload(&L.ainv32, a32))) return rc;
+    }
+    if (l > 0) {
+      // per unknown: the finer level's node (2x, 2y, 2z) and the restriction code (the solve
+      // restricts its right-hand side itself)
+      const Geo& gc = S.g;
+      const Geo& gf = H->host[l - 1].g;
+      std::vector<int32_t> uf(S.umap.size());
+      std::vector<uint8_t> uc(S.umap.size());
+      for (size_t i = 0; i < S.umap.size(); ++i) {
+        const int64_t X = S.umap[i], p = X / gc.npp, loc = X - p * gc.npp;
+        const int64_t z = H->dim == 3 ? loc / gc.st[2] : 0, rem = loc - z * (H->dim == 3 ? gc.st[2] : 0);
+        const int64_t y = rem / gc.st[1], x = rem - y * gc.st[1];
+        uf[i] = (int32_t)(p * gf.npp + 2 * x + gf.st[1] * 2 * y + gf.st[2] * 2 * z);
+        uc[i] = S.rcode[X];
+      }
+      if ((rc = upload(&L.ufine, uf))) return rc;
+      if ((rc = upload(&L.ucode, uc))) return rc;
+    }
   }
   return MG_OK;
 }
@@ -182,14 +203,17 @@ void relax(mg_handle_s* H, int l, hipStream_t s, bool prolong = false, bool rest
 template <int D, typename T>
 void cycle(mg_handle_s* H, int l, hipStream_t s, bool fresh = false) {
   DevLevel& L = H->dev[l];
-  if (fresh && (l == H->L || H->grid.nu1 == 0)) {
+  if (l == H->L) {
+    // the coarsest solve restricts its right-hand side itself
+    DevLevel* F = fresh ? &H->dev[l - 1] : nullptr;
+    launch_coarse<D, T>(L, F, F ? Arr<T>::r(*F) : nullptr, Arr<T>::rhs(L), Arr<T>::u(L, H->cur[l]),
+                        H->batch, s);
+    return;
+  }
+  if (fresh && H->grid.nu1 == 0) {
     DevLevel& F = H->dev[l - 1];
     launch_restrict<D, T>(F, L, Arr<T>::r(F), Arr<T>::rhs(L), Arr<T>::u(L, H->cur[l]), s);
     fresh = false;
-  }
-  if (l == H->L) {
-    launch_coarse<T>(L, Arr<T>::rhs(L), Arr<T>::u(L, H->cur[l]), H->batch, s);
-    return;
   }
   for (int i = 0; i < H->grid.nu1; ++i) relax<D, T>(H, l, s, false, fresh && i == 0);
   launch_defect<D, T, T>(L, Arr<T>::u(L, H->cur[l]), Arr<T>::rhs(L), Arr<T>::r(L), nullptr, true,
@@ -402,7 +426,7 @@ void free_level(DevLevel& L) {
                   L.cls, L.phi, L.tiles, L.ghosts, L.ghost_off, L.red, L.black, L.red_off, L.black_off,
                   L.ext, L.ext_merged, L.ext_off, L.dag_off, L.dag_start, L.rcode, L.u64[0],
                   L.u64[1], L.rhs64, L.r64, L.gtmp64, L.u32[0], L.u32[1], L.rhs32, L.r32, L.gtmp32,
-                  L.umap, L.umap_off, L.ainv_off, L.ainv};
+                  L.umap, L.umap_off, L.ainv_off, L.ainv, L.ainv32, L.ufine, L.ucode};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   L = DevLevel();
@@ -442,9 +466,12 @@ void time_launch(mg_handle_s* h, int kernel, int level, int i, hipStream_t s) {
                          h->batch, s, nullptr, nullptr, &F, Arr<T>::r(F));
       break;
     }
-    case 7:
-      launch_coarse<T>(L, Arr<T>::rhs(L), Arr<T>::u(L, 0), h->batch, s);
+    case 7: {  // coarsest solve, restricting from level - 1 (if any) as in a cycle
+      DevLevel* F = level > 0 ? &h->dev[level - 1] : nullptr;
+      launch_coarse<D, T>(L, F, F ? Arr<T>::r(*F) : nullptr, Arr<T>::rhs(L), Arr<T>::u(L, 0),
+                          h->batch, s);
       break;
+    }
     default:
       launch_defect<D, T, T>(L, u, Arr<T>::rhs(L), Arr<T>::r(L), h->norms, false, h->batch, s);
   }
@@ -557,7 +584,9 @@ int setup_impl(const double* phi, const mg_bc_rule* bc, mg_bc_fn fn, void* ctx,
       bool built = false;
       const int P = 3 + 3 * H->grid.lambda;
       for (int R = P; R >= 3 && !built; R -= 3)
-        if (P % R == 0 && P / R <= 7) built = build_band_chunks(H, l, kChunkOwn, H->dim == 2 ? kChunkRedundancy2D : kChunkRedundancy3D, R);
+        if (P % R == 0 && P / R <= 7)
+          built = build_band_chunks(H, l, kChunkOwn * (H->dim == 2 ? 1 : 2),
+                                    H->dim == 2 ? kChunkRedundancy2D : kChunkRedundancy3D, R);
       if (!built) {
         S.bc_nchunks = 0;
         S.bc_hdr.clear();
@@ -575,7 +604,7 @@ int setup_impl(const double* phi, const mg_bc_rule* bc, mg_bc_fn fn, void* ctx,
       }
     }
   // the coarsest right-hand side of one problem is staged in 64 KB of LDS
-  if (!rc && max_span(H->host[L].umap_off) > kMaxCoarse) rc = MG_EINVAL;
+  if (!rc && max_span(H->host[L].umap_off) > kMaxCoarseUnknowns) rc = MG_EINVAL;
   if (!rc) {
     H->dev.assign(L + 1, DevLevel());
     for (int l = 0; l <= L && !rc; ++l) rc = upload_level(H, l);
@@ -746,11 +775,17 @@ int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_m
     }
     if (kernel == 1) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0 + (double)S.ext.size() * (sz + 24.0);
     if (kernel == 7) {
-      // the FP64 inverse of every problem, plus its right-hand side gathered and u written
+      // the inverse of every problem (FP64, FP32 in the FP32 cycles), the unknowns' indices
+      // and codes, the right-hand side written and u written, and (below the finest level)
+      // the finer defect read
       b = 0.0;
       for (int p = 0; p < h->batch; ++p) {
         const double m = (double)(S.umap_off[p + 1] - S.umap_off[p]);
-        b += 8.0 * m * m + m * (2.0 * sz + 8.0);
+        b += sz * m * m + m * (2.0 * sz + 5.0);
+      }
+      if (level > 0) {
+        const HostLevel& F = h->host[level - 1];
+        b += ((double)F.nint + (double)F.nghost + (double)F.ext.size()) * sz;
       }
     }
     if (kernel == 4) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0;

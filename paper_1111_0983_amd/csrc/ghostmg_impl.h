@@ -16,21 +16,24 @@ constexpr int kMaxLevels = 16;
 // header words of a relaxation chunk and of an extension chunk
 constexpr int kBandHdr = 8;
 constexpr int kExtHdr = 8;
-constexpr int kChunkThreads = 256;     // workgroup size of every chunk kernel
-constexpr int kChunkPerThread = 4;     // chunk entries owned by one thread
-constexpr int kChunkMaxEntries = kChunkPerThread * kChunkThreads;
-constexpr int kExtMaxTerms = 6 * kChunkThreads;  // composed extension terms per chunk
-constexpr int kExtMaxGhosts = 2 * kChunkThreads;  // ghost sources per extension chunk
-// relaxation chunks: per thread one updated ghost, band_colour_slots(D) red and as many
-// black entries, band_halo_slots(D) entries that are read but never updated (more in 3D,
-// where a band patch's closure has more of them).  In 2D a thread updates one entry per
-// colour phase (short phases, more chunks); in 3D two (the level-0 chunk work is large and
-// more chunks would add redundant entries)
+// extension chunks: workgroup size, extension nodes per thread
+constexpr int kExtThreads = 256;
+constexpr int kExtPerThread = 4;
+constexpr int kExtMaxEntries = kExtPerThread * kExtThreads;
+constexpr int kExtMaxTerms = 6 * kExtThreads;   // composed extension terms per chunk
+constexpr int kExtMaxGhosts = 2 * kExtThreads;  // ghost sources per extension chunk
+// relaxation chunks: workgroup size (larger in 3D, where a band patch must be wide for its
+// closure over several phases to stay a small multiple of it); per thread one updated
+// ghost, band_colour_slots(D) red and as many black entries, band_halo_slots(D) entries
+// that are read but never updated (more in 3D, where a band patch's closure has more of
+// them).  In 2D a thread updates one entry per colour phase (short phases, more chunks); in
+// 3D two (the level-0 chunk work is large and more chunks would add redundant entries)
+constexpr int band_chunk_threads(int D) { return D == 2 ? 256 : 512; }
 constexpr int band_colour_slots(int D) { return D == 2 ? 1 : 2; }
 constexpr int kBandHaloSlots2D = 1, kBandHaloSlots3D = 4;
 constexpr int band_halo_slots(int D) { return D == 2 ? kBandHaloSlots2D : kBandHaloSlots3D; }
 constexpr int band_max_entries(int D) {
-  return (1 + 2 * band_colour_slots(D) + band_halo_slots(D)) * kChunkThreads;
+  return (1 + 2 * band_colour_slots(D) + band_halo_slots(D)) * band_chunk_threads(D);
 }
 
 // Tile shapes of the node-parallel kernels: 64 x 16 nodes in 2D, 16 x 8 x 8 in 3D.
@@ -89,11 +92,11 @@ struct HostLevel {
   // their values after a launch's phases depend on; a relaxation is 3 + 3 lambda phases (red
   // interior, black interior, ghosts; lambda times red band, black band, ghosts), taken
   // bc_range at a time, with a chunk set per launch.
-  // Entries come in four runs: the updated ghosts (at most kChunkThreads), the entries the
-  // red phases update, those the black phases update (at most band_colour_slots(D)
-  // * kChunkThreads each), and the entries only read (at most band_halo_slots(D) * kChunkThreads);
-  // entry i of a run belongs to thread i % kChunkThreads.  Chunk c: header
-  // bc_hdr[c * kBandHdr ..] = {entries, updated ghosts | red << 10 | black << 20, offsets
+  // Entries come in four runs (W = band_chunk_threads(D)): the updated ghosts (at most W),
+  // the entries the red phases update, those the black phases update (at most
+  // band_colour_slots(D) * W each), and the entries only read (at most band_halo_slots(D) *
+  // W); entry i of a run belongs to thread i % W.  Chunk c: header
+  // bc_hdr[c * kBandHdr ..] = {entries, updated ghosts | red << 10 | black << 21, offsets
   // into bc_data of: the per-entry arrays, the ghost stencil ids, the ghost
   // weights, the ghost constants, the interpolation candidates (-1 on the coarsest level)
   // and the restriction data (-1 on the finest level)}: per entry the coarse node index of
@@ -117,7 +120,7 @@ struct HostLevel {
   // Extension chunks.  The steady state of Eq. (exp) on the upwind graph is linear in the
   // ghost defects: every extension value is a fixed combination of the defects of the ghost
   // nodes its upwind paths start from, with weights composed on the host.  Each chunk owns a
-  // run of extension nodes (at most kChunkMaxEntries) and evaluates the defects of the ghost
+  // run of extension nodes (at most kExtMaxEntries) and evaluates the defects of the ghost
   // sources they need (at most kExtMaxGhosts).  Chunk c: header
   // ec_hdr[c * kExtHdr ..] = {extension nodes, ghost sources, offsets into ec_data of: the node
   // indices (ghost sources, then extension nodes), the term offsets (per extension node and
@@ -180,6 +183,10 @@ struct DevLevel {
   int32_t *umap = nullptr, *umap_off = nullptr;
   int64_t* ainv_off = nullptr;
   double* ainv = nullptr;
+  float* ainv32 = nullptr;  // FP32 rounding of ainv (FP32 cycles of the defect correction)
+  // per coarsest unknown: the next finer level's node (2x, 2y, 2z) and the restriction code
+  int32_t* ufine = nullptr;
+  uint8_t* ucode = nullptr;
 };
 
 }  // namespace ghostmg

@@ -5,6 +5,11 @@
 namespace ghostmg {
 
 constexpr int kCoarseRows = 16;  // rows of the coarsest inverse per workgroup (one per wave)
+// unknowns per problem on the coarsest grid (its right-hand side is staged in 64 KB of LDS)
+constexpr int kMaxCoarseUnknowns = 8192;
+// workgroups of a coarsest solve over the whole batch (more where a problem has more than
+// kCoarseRows rows per workgroup)
+constexpr int kCoarseWorkgroups = 256;
 
 // Per-phase boundary relaxation (levels without relaxation chunks), in place on u.
 template <typename T>
@@ -52,6 +57,22 @@ struct RelaxArgs {
   T* rhs_w;
 };
 
+// Coarsest solve: the explicit inverse of every problem (rows of nu doubles at ainv_off[p]),
+// applied to the right-hand side rhs, or to the restriction of rf (geometry gf, the next
+// finer level) when rf is set
+template <typename T>
+struct CoarseArgs {
+  const int32_t *umap, *umap_off;
+  const int64_t* ainv_off;
+  const T* ainv;  // FP64, or its FP32 rounding for the FP32 cycles (summed in FP64)
+  Geo gf;
+  const int32_t* ufine;  // per unknown: finer node (2x, 2y, 2z) and restriction code
+  const uint8_t* ucode;
+  const T* rf;
+  T* rhs;
+  T* u;
+};
+
 // Defect r = rhs - A u: workgroups [0, nechunks) run the extension chunks (Eq. (exp)),
 // then nbt workgroups the interior tiles, then the ghost rows.
 template <typename T, typename TO>
@@ -93,8 +114,11 @@ void launch_restrict(const DevLevel& F, const DevLevel& C, const T* rf, T* rhsc,
                      hipStream_t s);
 template <int D, typename T>
 void launch_prolong(const DevLevel& F, const DevLevel& C, const T* uc, T* uf, hipStream_t s);
-template <typename T>
-void launch_coarse(const DevLevel& C, const T* rhs, T* u, int batch, hipStream_t s);
+// coarsest solve; with F (the next finer level) its right-hand side is first restricted from
+// rf, F's defect, and stored into rhs
+template <int D, typename T>
+void launch_coarse(const DevLevel& C, const DevLevel* F, const T* rf, T* rhs, T* u, int batch,
+                   hipStream_t s);
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t s);
 template <int D>

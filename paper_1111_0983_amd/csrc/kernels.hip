@@ -208,6 +208,42 @@ __device__ __forceinline__ void restrict_gather(const T* __restrict__ rf, int64_
   }
 }
 
+// One colour phase of a tile workgroup: the N nodes of one colour in a region whose rows
+// hold HX nodes of that colour (row (y, z), HY rows per z), at offset O from the U region's
+// origin in every axis; node x of a row has x + y + z + P even... odd per PAR: x = 2 (r mod
+// HX) + ((y + z + PAR) & 1).  Nodes whose code is not an interior one (1, 3) are left alone.
+template <int D, typename T, int N, int HX, int HY, int O, int PAR>
+__device__ __forceinline__ void tile_colour_phase(T* su, const int8_t* sc, const T* sf, int FX,
+                                                  int FY, int SY, int SZ, T h2, T inv2d) {
+  constexpr int K = (N + 255) / 256;
+  int ui[K];
+  int8_t cd[K];
+  T cv[K], fv[K], nb[K][2 * D];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int r0 = (int)threadIdx.x + 256 * k, r = r0 < N ? r0 : 0;
+    const int row = r / HX, y = row % HY, z = row / HY;
+    const int x = 2 * (r % HX) + ((y + z + PAR) & 1);
+    // F index of the node (the F region starts one node inside the U region)
+    const int fi = (x + O - 1) + FX * ((y + O - 1) + (D == 3 ? FY * (z + O - 1) : 0));
+    ui[k] = (x + O) + SY * (y + O) + (D == 3 ? SZ * (z + O) : 0);
+    cd[k] = r0 < N ? sc[ui[k]] : (int8_t)0;
+    cv[k] = su[ui[k]];
+    fv[k] = sf[fi];
+    nb[k][0] = su[ui[k] - 1];
+    nb[k][1] = su[ui[k] + 1];
+    nb[k][2] = su[ui[k] - SY];
+    nb[k][3] = su[ui[k] + SY];
+    if (D == 3) {
+      nb[k][4] = su[ui[k] - SZ];
+      nb[k][5] = su[ui[k] + SZ];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (cd[k] == 1 || cd[k] == 3) su[ui[k]] = interior_update<D, T>(cv[k], nb[k], fv[k], h2, inv2d);
+}
+
 // ---------------------------------------------------------------------------------------
 // relaxation, interior tiles: red-black sweep of Eq. (jac2d), one tile per workgroup
 // ---------------------------------------------------------------------------------------
@@ -427,52 +463,34 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   __syncthreads();
   constexpr int SY = UX, SZ = UX * UY;
   // red nodes of the F region only (tile origins are even: node x of row (y, z) is red when
-  // x + y + z + D is even), FX / 2 per row
-  constexpr int FXH = FX / 2;
-  for (int r = threadIdx.x; r < FXH * FY * FZ; r += 256) {
-    const int row = r / FXH, y = row % FY, z = row / FY;
-    const int x = 2 * (r % FXH) + ((y + z + D) & 1);
-    const int i = x + FX * (y + FY * z);
-    const int ui = (x + 1) + SY * (y + 1) + (D == 3 ? SZ * (z + 1) : 0);
-    if (sc[ui] != 1 && sc[ui] != 3) continue;
-    T nb[2 * D];
-    nb[0] = su[ui - 1];
-    nb[1] = su[ui + 1];
-    nb[2] = su[ui - SY];
-    nb[3] = su[ui + SY];
-    if (D == 3) {
-      nb[4] = su[ui - SZ];
-      nb[5] = su[ui + SZ];
-    }
-    su[ui] = interior_update<D, T>(su[ui], nb, sf[i], a.h2, a.inv2d);
-  }
+  // x + y + z + D is even), FX / 2 per row; then the black nodes of the tile only (x + y + z
+  // odd), TX / 2 per row.  A thread issues the reads of all its nodes of a colour (codes
+  // included) before the first update: a node of one colour reads only values of the other
+  // colour, ghosts or outside nodes, which the phase leaves unchanged.
+  constexpr int FXH = FX / 2, TXH = TX / 2;
+  constexpr int NRED = FXH * FY * FZ, NBLK = TXH * TY * TZ;
+  tile_colour_phase<D, T, NRED, FXH, FY, 1, (D & 1)>(su, sc, sf, FX, FY, SY, SZ, a.h2, a.inv2d);
   __syncthreads();
-  // black nodes of the tile only: x + y + z odd, TX / 2 per row
-  constexpr int TXH = TX / 2;
-  for (int r = threadIdx.x; r < TXH * TY * TZ; r += 256) {
-    const int row = r / TXH, y = row % TY, z = row / TY;
-    const int x = 2 * (r % TXH) + ((y + z + 1) & 1);
-    const int fi = (x + 1) + FX * (y + 1) + (D == 3 ? FX * FY * (z + 1) : 0);
-    const int ui = (x + 2) + SY * (y + 2) + (D == 3 ? SZ * (z + 2) : 0);
-    if (sc[ui] != 1 && sc[ui] != 3) continue;
-    T nb[2 * D];
-    nb[0] = su[ui - 1];
-    nb[1] = su[ui + 1];
-    nb[2] = su[ui - SY];
-    nb[3] = su[ui + SY];
-    if (D == 3) {
-      nb[4] = su[ui - SZ];
-      nb[5] = su[ui + SZ];
-    }
-    su[ui] = interior_update<D, T>(su[ui], nb, sf[fi], a.h2, a.inv2d);
-  }
+  tile_colour_phase<D, T, NBLK, TXH, TY, 2, 1>(su, sc, sf, FX, FY, SY, SZ, a.h2, a.inv2d);
   __syncthreads();
-  for (int i = threadIdx.x; i < TZ * TY * TX; i += 256) {
+  // the block's nodes to uout: every code and value read before the first store
+  constexpr int NST = TZ * TY * TX, KS = (NST + 255) / 256;
+  int8_t cst[KS];
+  T vst[KS];
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const int i0 = threadIdx.x + 256 * k, i = i0 < NST ? i0 : 0;
     const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
     const int ui = (x + 2) + SY * (y + 2) + (D == 3 ? SZ * (z + 2) : 0);
-    const int8_t c = sc[ui];
-    if (c == 0 || (c != 1 && !a.write_all)) continue;
-    a.uout[base + (ox + x) + g.st[1] * (oy + y) + g.st[2] * (D == 3 ? oz + z : 0)] = su[ui];
+    cst[k] = i0 < NST ? sc[ui] : (int8_t)0;
+    vst[k] = su[ui];
+  }
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
+    if (cst[k] == 0 || (cst[k] != 1 && !a.write_all)) continue;
+    a.uout[base + (ox + x) + g.st[1] * (oy + y) + g.st[2] * (D == 3 ? oz + z : 0)] = vst[k];
   }
 }
 
@@ -485,7 +503,7 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
 // lambda times red band, black band, ghosts, Sec. 3.2).  Its entries come in runs: updated
 // ghosts, red-updated, black-updated, read-only; a thread holds one ghost, band_colour_slots(D)
 // red and black entries and band_halo_slots(D) read-only entries (slot s of a run: entry
-// tid + s * kChunkThreads of the run), with their node index, phase mask, neighbour ids,
+// tid + s * band_chunk_threads(D) of the run), with their node index, phase mask, neighbour ids,
 // right-hand side and current value in registers (the ghost also its stencil ids, weights
 // and constant); only the values are shared, in LDS.  A phase updates at most
 // band_colour_slots(D) entries per thread (one ghost in a ghost phase) and issues all its LDS
@@ -529,7 +547,8 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
   int32_t hd[kBandHdr];
 #pragma unroll
   for (int q = 0; q < kBandHdr; ++q) hd[q] = a.hdr[(int64_t)cu * kBandHdr + q];
-  const int ns = hd[0], ng = hd[1] & 1023, nr = (hd[1] >> 10) & 1023, nb = (hd[1] >> 20) & 1023;
+  const uint32_t cnt = (uint32_t)hd[1];
+  const int ns = hd[0], ng = cnt & 1023u, nr = (cnt >> 10) & 2047u, nb = cnt >> 21;
   const int32_t* E = a.data + hd[2];
   const int tid = threadIdx.x;
   // slot s: its run start and length
@@ -547,7 +566,7 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
     } else {
       start = ng + nr + nb, len = ns - ng - nr - nb, j = s - 1 - 2 * NC;
     }
-    const int i = tid + j * kChunkThreads;
+    const int i = tid + j * band_chunk_threads(D);
     ok_of[s] = i < len;
     e_of[s] = ok_of[s] ? start + i : 0;
   }
@@ -701,18 +720,29 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
     if (mask[s] >> 31) a.uout[node[s]] = uv[s];
 }
 
-// CHUNKS: the level has relaxation chunks (workgroups [0, nchunks)).  MODE kRelaxProlong:
-// the relaxation starts from the iterate plus the interpolated coarse correction;
-// kRelaxRestrict: it starts from zero with the right-hand side restricted from the finer
-// level's defect (and stores that right-hand side).  Each variant holds only the registers
-// of the paths it runs.
+// CHUNKS (2D): the launch also runs the level's relaxation chunks (workgroups
+// [0, nchunks)).  MODE kRelaxProlong: the relaxation starts from the iterate plus the
+// interpolated coarse correction; kRelaxRestrict: it starts from zero with the right-hand
+// side restricted from the finer level's defect (and stores that right-hand side).  Each
+// variant holds only the registers of the paths it runs.
 template <int D, typename T, bool CHUNKS, int MODE, int SUB>
 __global__ void __launch_bounds__(256) k_relax(RelaxArgs<T> a) {
   extern __shared__ __align__(16) unsigned char relax_smem[];
-  if (CHUNKS && (int)blockIdx.x < a.nchunks)
-    relax_chunk<D, T, MODE>(a, blockIdx.x, relax_smem);
-  else
-    relax_tile<D, T, MODE, SUB>(a, (int)blockIdx.x - (CHUNKS ? a.nchunks : 0), relax_smem);
+  static_assert(!CHUNKS || band_chunk_threads(D) == 256, "chunks sharing a launch with tiles");
+  if constexpr (CHUNKS) {
+    if ((int)blockIdx.x < a.nchunks) {
+      relax_chunk<D, T, MODE>(a, blockIdx.x, relax_smem);
+      return;
+    }
+  }
+  relax_tile<D, T, MODE, SUB>(a, (int)blockIdx.x - (CHUNKS ? a.nchunks : 0), relax_smem);
+}
+
+// relaxation chunks in a launch of their own (3D: wider workgroups than the tiles')
+template <int D, typename T>
+__global__ void __launch_bounds__(band_chunk_threads(D)) k_relax_chunks(RelaxArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char relax_smem[];
+  relax_chunk<D, T, kRelaxPlain>(a, blockIdx.x, relax_smem);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -816,8 +846,8 @@ __device__ __forceinline__ void extend_one(const ExtRec& e, T* __restrict__ r) {
 template <int D, typename T, typename TO>
 __device__ void extend_chunk(const DefectArgs<T, TO>& a, int c, unsigned char* lds) {
   constexpr int K = Pow3<D>::value;
-  constexpr int NK = kChunkPerThread;
-  constexpr int NT = kExtMaxTerms / kChunkThreads;
+  constexpr int NK = kExtPerThread;
+  constexpr int NT = kExtMaxTerms / kExtThreads;
   const int cu = __builtin_amdgcn_readfirstlane(c);
   int32_t hd[kExtHdr];
 #pragma unroll
@@ -836,7 +866,7 @@ __device__ void extend_chunk(const DefectArgs<T, TO>& a, int c, unsigned char* l
   int32_t node[NK], t0[NK], t1[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    const int e = tid + k * kChunkThreads;
+    const int e = tid + k * kExtThreads;
     const int ec = e < ne ? e : 0;
     node[k] = N[ngs + ec];
     t0[k] = TOF[ec];
@@ -846,14 +876,14 @@ __device__ void extend_chunk(const DefectArgs<T, TO>& a, int c, unsigned char* l
   int32_t ts[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
-    const int i = tid + j * kChunkThreads;
+    const int i = tid + j * kExtThreads;
     const int ic = i < nterms ? i : 0;
     tw[j] = TW[ic];
     ts[j] = TS[ic];
   }
-  // ghost sources tid, tid + kChunkThreads, ... (a second pass only where a chunk has more
+  // ghost sources tid, tid + kExtThreads, ... (a second pass only where a chunk has more
   // sources than threads)
-  for (int g0 = 0; g0 < ngs; g0 += kChunkThreads) {
+  for (int g0 = 0; g0 < ngs; g0 += kExtThreads) {
     const bool gsrc = g0 + tid < ngs;
     const int tg = gsrc ? g0 + tid : 0;
     const int32_t* gn = a.data + hd[6];
@@ -878,7 +908,7 @@ __device__ void extend_chunk(const DefectArgs<T, TO>& a, int c, unsigned char* l
   }
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
-    const int i = tid + j * kChunkThreads;
+    const int i = tid + j * kExtThreads;
     if (i < nterms) {
       lw[i] = tw[j];
       ls[i] = ts[j];
@@ -887,7 +917,7 @@ __device__ void extend_chunk(const DefectArgs<T, TO>& a, int c, unsigned char* l
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    if (tid + k * kChunkThreads >= ne) continue;
+    if (tid + k * kExtThreads >= ne) continue;
     double v = 0.0;
     for (int t = t0[k]; t < t1[k]; ++t) v += lw[t] * sv[ls[t]];
     a.r[node[k]] = (TO)v;
@@ -1141,59 +1171,96 @@ __global__ void __launch_bounds__(256) k_prolong(const int4* __restrict__ tiles,
 }
 
 // ---------------------------------------------------------------------------------------
-// exact solve on the coarsest grid: e = A_c^{-1} r (FP64), several row blocks per problem
+// exact solve on the coarsest grid: e = A_c^{-1} b, summed in FP64 (the FP32 cycles of the
+// defect correction read the inverse rounded to FP32).  b is the level's right-hand
+// side or, when the level has just been entered (rf set), the restriction (Sec. 2.5) of the
+// finer level's defect, which every workgroup forms in LDS itself (workgroup 0 of each
+// problem also stores it as the level's right-hand side).  Rows are dealt round robin over
+// the problem's workgroups (row r: workgroup r mod gridDim.x, wave r / gridDim.x), one
+// wave per row; a wave requests the first block of its row before b is formed and the next
+// block before it sums the current one.
 // ---------------------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kCoarseRows * 64) k_coarse(const int32_t* __restrict__ umap,
-                                                             const int32_t* __restrict__ umap_off,
-                                                             const int64_t* __restrict__ ainv_off,
-                                                             const double* __restrict__ ainv,
-                                                             const T* __restrict__ rhs,
-                                                             T* __restrict__ u) {
-  constexpr int NT = kCoarseRows * 64;  // one row per wave
-  constexpr int NQ = 16;                // loads of the row in flight per lane
+template <int D, typename T>
+__global__ void __launch_bounds__(kCoarseRows * 64) k_coarse(CoarseArgs<T> a) {
+  constexpr int NT = kCoarseRows * 64;
+  constexpr int NQ = 16;  // loads of the row in flight per lane
+  constexpr int KT = Pow3<D>::value;
   extern __shared__ double bsh[];
   const int p = blockIdx.y;
-  const int a = umap_off[p], nu = umap_off[p + 1] - a;
-  const int row0 = blockIdx.x * kCoarseRows;
-  if (row0 >= nu) return;
-  // right-hand side in LDS, 4 gathers in flight per thread
-  for (int i0 = 0; i0 < nu; i0 += 4 * NT) {
-    int32_t idx[4];
+  const int a0 = a.umap_off[p], nu = a.umap_off[p + 1] - a0;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = (int)blockIdx.x + (int)gridDim.x * w;
+  const bool live = r < nu;
+  const T* Ar = a.ainv + a.ainv_off[p] + (int64_t)(live ? r : 0) * nu;
+  T av[NQ];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = i0 + threadIdx.x + NT * q;
-      idx[q] = i < nu ? umap[a + i] : umap[a];
+  for (int q = 0; q < NQ; ++q) {
+    const int j = lane + 64 * q;
+    av[q] = live && j < nu ? Ar[j] : (T)0;
+  }
+  if (a.rf) {
+    // the fine neighbourhoods of NR unknowns per thread in flight together (in 2D, one round
+    // for up to 4 NT unknowns)
+    constexpr int NR = D == 2 ? 3 : 1;
+    for (int i0 = 0; i0 < nu; i0 += NR * NT) {
+      int32_t F0[NR];
+      uint8_t c[NR];
+#pragma unroll
+      for (int h = 0; h < NR; ++h) {
+        const int i = i0 + (int)threadIdx.x + NT * h;
+        F0[h] = a.ufine[a0 + (i < nu ? i : 0)];
+        c[h] = a.ucode[a0 + (i < nu ? i : 0)];
+      }
+      T rr[NR][KT];
+#pragma unroll
+      for (int h = 0; h < NR; ++h) restrict_gather<D, T>(a.rf, F0[h], a.gf, c[h], rr[h]);
+#pragma unroll
+      for (int h = 0; h < NR; ++h) {
+        const int i = i0 + (int)threadIdx.x + NT * h;
+        if (i >= nu) continue;
+        const T v = restrict_box<D, T>(c[h], rr[h]);
+        bsh[i] = (double)v;
+        if (blockIdx.x == 0) a.rhs[a.umap[a0 + i]] = v;
+      }
     }
-    T v[4];
+  } else {
+    // right-hand side in LDS, 4 gathers in flight per thread
+    for (int i0 = 0; i0 < nu; i0 += 4 * NT) {
+      int32_t idx[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = rhs[idx[q]];
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + (int)threadIdx.x + NT * q;
+        idx[q] = i < nu ? a.umap[a0 + i] : a.umap[a0];
+      }
+      T v[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = i0 + threadIdx.x + NT * q;
-      if (i < nu) bsh[i] = (double)v[q];
+      for (int q = 0; q < 4; ++q) v[q] = a.rhs[idx[q]];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + (int)threadIdx.x + NT * q;
+        if (i < nu) bsh[i] = (double)v[q];
+      }
     }
   }
   __syncthreads();
-  const double* A = ainv + ainv_off[p];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r = row0 + w;
-  if (r >= nu) return;
-  const double* Ar = A + (int64_t)r * nu;
+  if (!live) return;
   double acc = 0.0;
   for (int j0 = 0; j0 < nu; j0 += NQ * 64) {
-    double av[NQ], bv[NQ];
+    double bv[NQ];
+    T an[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int j = j0 + lane + 64 * q;
-      av[q] = j < nu ? Ar[j] : 0.0;
+      const int j = j0 + lane + 64 * q, jn = j + NQ * 64;
       bv[q] = j < nu ? bsh[j] : 0.0;
+      an[q] = jn < nu ? Ar[jn] : (T)0;
     }
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc += av[q] * bv[q];
+    for (int q = 0; q < NQ; ++q) acc += (double)av[q] * bv[q];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) av[q] = an[q];
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  if (lane == 0) u[umap[a + r]] = (T)acc;
+  if (lane == 0) a.u[a.umap[a0 + r]] = (T)acc;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1315,14 +1382,29 @@ constexpr int kSingleWgExt = 24576;
 template <int D, typename T, int MODE, int SUB>
 static void launch_relax_sub(RelaxArgs<T> a, const DevLevel& L, hipStream_t s) {
   a.nbt = a.ntiles ? tile_grid(a.ntiles * RTile<D, SUB>::N) : 0;
-  const int nb = a.nchunks + a.nbt;
-  if (!nb) return;
-  const size_t lds =
-      std::max(tile_lds<D, T, MODE, SUB>(), (size_t)(L.bc_smax + kChunkThreads) * sizeof(T));
-  if (a.nchunks)
-    hipLaunchKernelGGL((k_relax<D, T, true, MODE, SUB>), dim3(nb), dim3(256), lds, s, a);
-  else
-    hipLaunchKernelGGL((k_relax<D, T, false, MODE, SUB>), dim3(nb), dim3(256), lds, s, a);
+  const size_t chunk_lds = (size_t)(L.bc_smax + band_chunk_threads(D)) * sizeof(T);
+  if constexpr (D == 3) {
+    // tiles and chunks in launches of their own
+    if (a.nbt) {
+      RelaxArgs<T> t = a;
+      t.nchunks = 0;
+      const size_t tlds = tile_lds<D, T, MODE, SUB>();
+      hipLaunchKernelGGL((k_relax<D, T, false, MODE, SUB>), dim3(a.nbt), dim3(256), tlds, s, t);
+    }
+    if (a.nchunks) {
+      // (3D interpolation and restriction are launches of their own: chunks relax plainly)
+      hipLaunchKernelGGL((k_relax_chunks<D, T>), dim3(a.nchunks), dim3(band_chunk_threads(D)),
+                         chunk_lds, s, a);
+    }
+  } else {
+    const int nb = a.nchunks + a.nbt;
+    if (!nb) return;
+    const size_t lds = std::max(tile_lds<D, T, MODE, SUB>(), chunk_lds);
+    if (a.nchunks)
+      hipLaunchKernelGGL((k_relax<D, T, true, MODE, SUB>), dim3(nb), dim3(256), lds, s, a);
+    else
+      hipLaunchKernelGGL((k_relax<D, T, false, MODE, SUB>), dim3(nb), dim3(256), lds, s, a);
+  }
 }
 
 // tiles split in parts on levels with fewer than kSplitTilesBelow tiles (2D)
@@ -1594,10 +1676,36 @@ void launch_prolong(const DevLevel& F, const DevLevel& C, const T* uc, T* uf, hi
 }
 
 template <typename T>
-void launch_coarse(const DevLevel& C, const T* rhs, T* u, int batch, hipStream_t s) {
-  const int blocks = (C.nu_max + kCoarseRows - 1) / kCoarseRows;
-  hipLaunchKernelGGL((k_coarse<T>), dim3(blocks, batch), dim3(kCoarseRows * 64), C.nu_max * sizeof(double), s,
-                     C.umap, C.umap_off, C.ainv_off, C.ainv, rhs, u);
+struct CoarseInv;
+template <>
+struct CoarseInv<double> {
+  static const double* get(const DevLevel& C) { return C.ainv; }
+};
+template <>
+struct CoarseInv<float> {
+  static const float* get(const DevLevel& C) { return C.ainv32; }
+};
+
+template <int D, typename T>
+void launch_coarse(const DevLevel& C, const DevLevel* F, const T* rf, T* rhs, T* u, int batch,
+                   hipStream_t s) {
+  if (C.nu_max <= 0) return;
+  CoarseArgs<T> a;
+  a.umap = C.umap;
+  a.umap_off = C.umap_off;
+  a.ainv_off = C.ainv_off;
+  a.ainv = CoarseInv<T>::get(C);
+  a.gf = F ? F->g : C.g;
+  a.ufine = C.ufine;
+  a.ucode = C.ucode;
+  a.rf = F ? rf : nullptr;
+  a.rhs = rhs;
+  a.u = u;
+  // about kCoarseWorkgroups workgroups over the batch, at most kCoarseRows rows each
+  const int lo = (C.nu_max + kCoarseRows - 1) / kCoarseRows;
+  const int nwg = std::max(lo, std::min(C.nu_max, std::max(1, kCoarseWorkgroups / batch)));
+  hipLaunchKernelGGL((k_coarse<D, T>), dim3(nwg, batch), dim3(kCoarseRows * 64),
+                     C.nu_max * sizeof(double), s, a);
 }
 
 template <typename T>
@@ -1638,6 +1746,8 @@ void launch_dc_update(const DevLevel& L, double* u64, const float* u32, float* u
   template void launch_restrict<D, T>(const DevLevel&, const DevLevel&, const T*, T*, T*,     \
                                       hipStream_t);                                           \
   template void launch_prolong<D, T>(const DevLevel&, const DevLevel&, const T*, T*, hipStream_t); \
+  template void launch_coarse<D, T>(const DevLevel&, const DevLevel*, const T*, T*, T*, int,        \
+                                    hipStream_t);                                                  \
 
 GHOSTMG_INST(2, double)
 GHOSTMG_INST(2, float)
@@ -1647,8 +1757,6 @@ template void launch_defect<2, double, float>(const DevLevel&, const double*, co
                                               uint64_t*, bool, int, hipStream_t);
 template void launch_defect<3, double, float>(const DevLevel&, const double*, const double*, float*,
                                               uint64_t*, bool, int, hipStream_t);
-template void launch_coarse<double>(const DevLevel&, const double*, double*, int, hipStream_t);
-template void launch_coarse<float>(const DevLevel&, const float*, float*, int, hipStream_t);
 template void launch_fill<double>(double*, int64_t, double, hipStream_t);
 template void launch_fill<float>(float*, int64_t, float, hipStream_t);
 template void launch_fill<uint64_t>(uint64_t*, int64_t, uint64_t, hipStream_t);

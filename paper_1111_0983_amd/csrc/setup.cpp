@@ -934,8 +934,9 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     int cnt[4] = {0, 0, 0, 0};
     for (int32_t v : touched) ++cnt[run_of(v)];
     const int ng = cnt[0], nr = cnt[1], nbk = cnt[2];
-    bool ok = ng <= kChunkThreads && nr <= band_colour_slots(D) * kChunkThreads &&
-              nbk <= band_colour_slots(D) * kChunkThreads && cnt[3] <= band_halo_slots(D) * kChunkThreads;
+    const int W = band_chunk_threads(D);
+    bool ok = ng <= W && nr <= band_colour_slots(D) * W && nbk <= band_colour_slots(D) * W &&
+              cnt[3] <= band_halo_slots(D) * W;
     for (int32_t v : touched)
       if (owned[v] && run_of(v) == 3) ok = false;  // an owned node is always updated
     if (ok) {
@@ -1044,7 +1045,7 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
         Dv.push_back((int32_t)HL.rcode[touched[i]]);
       }
     }
-    const int32_t hdr[kBandHdr] = {ns, ng | (nr << 10) | (nbk << 20), off, gid_off, gw_off, gc_off,
+    const int32_t hdr[kBandHdr] = {ns, (int32_t)((uint32_t)ng | ((uint32_t)nr << 10) | ((uint32_t)nbk << 21)), off, gid_off, gw_off, gc_off,
                                    l < H->L ? pc_off : -1, l > 0 ? rs_off : -1};
     HL.bc_hdr.insert(HL.bc_hdr.end(), hdr, hdr + kBandHdr);
     ++HL.bc_nchunks;
@@ -1134,7 +1135,7 @@ bool build_ext_terms(mg_handle_s* H, int l) {
 }
 
 // Extension chunks of level l: each chunk owns a Morton-ordered run of extension nodes and
-// the ghost nodes their composed weights name.  A chunk with more than kChunkMaxEntries
+// the ghost nodes their composed weights name.  A chunk with more than kExtMaxEntries
 // extension nodes, kExtMaxGhosts ghost sources or kExtMaxTerms terms is split in two;
 // returns false when a single node is still too large, or a source is neither extension
 // node nor ghost.
@@ -1179,7 +1180,7 @@ bool build_ext_chunks(mg_handle_s* H, int l, int own_target) {
     const int ne = (int)(b - a), ngs = (int)ghosts_e.size();
     int64_t nt = 0;
     for (size_t i = a; i < b; ++i) nt += toff[U[i].second + 1] - toff[U[i].second];
-    if (ne > kChunkMaxEntries || ngs > kExtMaxGhosts || nt > kExtMaxTerms) {
+    if (ne > kExtMaxEntries || ngs > kExtMaxGhosts || nt > kExtMaxTerms) {
       for (int32_t q : ghosts_e) lid[q] = -1;
       if (b - a <= 1) return false;
       const size_t m = a + (b - a) / 2;
