@@ -74,6 +74,17 @@ def bench_torus(args, gm, pr, geo, np, torch, dev, step):
         out[f"torus_{name}_setup_s"] = setup
         log(f"[bench] torus {n}^3 {name}: {1e3 * dt:.1f} ms, {info['cycles']} cycles, "
             f"rel {info['rel']:.2e}, setup {setup:.1f}s")
+        if name == "fp64":
+            # every launch sequence of one FP64 cycle, per level (microseconds; a relaxation
+            # is a tile launch plus one chunk launch per phase range)
+            per_level = {}
+            for lev in range(s.nlev - 1):
+                names = ["relax_restrict" if lev > 0 else "relax", "relax", "defect", "relax_prolong"]
+                per_level[str(lev)] = {k: round(s.time_kernel(k, lev, 5)[0] * 1e3, 1)
+                                       for k in dict.fromkeys(names)}
+            per_level[str(s.nlev - 1)] = {
+                "coarse_with_restriction": round(s.time_kernel("coarse", s.nlev - 1, 5)[0] * 1e3, 1)}
+            out["torus_fp64_launch_us_by_level"] = per_level
         s.close()
     out["torus_unknowns"] = unknowns
     out["torus_workload"] = f"torus-{n}^3 3D V(2,1) lambda=5 Nc=16 tol=1e-10"

@@ -893,6 +893,7 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
   std::vector<int32_t> lid(nn, -1);
   std::vector<char> owned(nn, 0);
   std::vector<int32_t> touched, rd;
+  std::vector<int64_t> keyed;
   const double cNh = H->grid.cN * g.h;
   for (int p0 = 0; p0 < P; p0 += R) {
   const int p1 = p0 + R;
@@ -925,25 +926,27 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
         if (updates(role[v], p) && need[v] >= p) return p % 3 == 2 ? 0 : (p % 3 == 0 ? 1 : 2);
       return 3;
     };
-    std::sort(touched.begin(), touched.end(), [&](int32_t x, int32_t y) {
-      const int rx = run_of(x), ry = run_of(y);
-      if (rx != ry) return rx < ry;
-      return x < y;
-    });
+    // (run, node) keys, each run computed once
+    keyed.clear();
+    for (int32_t v : touched) keyed.push_back(((int64_t)run_of(v) << 32) | (uint32_t)v);
+    std::sort(keyed.begin(), keyed.end());
     const int ns = (int)touched.size();
     int cnt[4] = {0, 0, 0, 0};
-    for (int32_t v : touched) ++cnt[run_of(v)];
+    for (int i = 0; i < ns; ++i) {
+      touched[i] = (int32_t)(keyed[i] & 0xffffffff);
+      ++cnt[keyed[i] >> 32];
+    }
     const int ng = cnt[0], nr = cnt[1], nbk = cnt[2];
     const int W = band_chunk_threads(D);
     bool ok = ng <= W && nr <= band_colour_slots(D) * W && nbk <= band_colour_slots(D) * W &&
               cnt[3] <= band_halo_slots(D) * W;
-    for (int32_t v : touched)
-      if (owned[v] && run_of(v) == 3) ok = false;  // an owned node is always updated
+    for (int i = ns - cnt[3]; i < ns; ++i)
+      if (owned[touched[i]]) ok = false;  // an owned node is always updated
     if (ok) {
       for (int i = 0; i < ns; ++i) lid[touched[i]] = i;
-      for (int i = 0; i < ns && ok; ++i) {
+      for (int i = 0; i < ns - cnt[3] && ok; ++i) {
         const int32_t v = touched[i];
-        if (role[v] == 3 || run_of(v) == 3) continue;
+        if (role[v] == 3) continue;
         for (int a2 = 0; a2 < D; ++a2)
           if (lid[v - g.st[a2]] < 0 || lid[v + g.st[a2]] < 0) ok = false;
       }
@@ -1052,6 +1055,8 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     HL.bc_entries += ns;
     HL.bc_nown += (int)(b - a);
     HL.bc_smax = std::max(HL.bc_smax, ns);
+    // over the redundancy budget already: this phase range fails (early exit)
+    if ((double)HL.bc_entries > max_redundancy * (double)(P / R) * (double)U.size()) return false;
     for (int32_t v : touched) {
       need[v] = -2;
       lid[v] = -1;

@@ -24,7 +24,7 @@ def main(argv=None):
     ap.add_argument("--level", type=int, default=0)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--n", type=int, default=2048)
-    ap.add_argument("--nc", type=int, default=32)
+    ap.add_argument("--nc", type=int, default=128)
     ap.add_argument("--fp32", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=2048)
     args = ap.parse_args(argv)
