@@ -134,6 +134,7 @@ int upload_level(mg_handle_s* H, int l) {
   }
   if (l == H->L) {
     L.nu_max = max_span(S.umap_off);
+    L.nu_total = (int)S.umap.size();
     if ((rc = upload(&L.umap, S.umap))) return rc;
     if ((rc = upload(&L.umap_off, S.umap_off))) return rc;
     if ((rc = upload(&L.ainv_off, S.ainv_off))) return rc;
@@ -204,7 +205,7 @@ template <int D, typename T>
 void cycle(mg_handle_s* H, int l, hipStream_t s, bool fresh = false) {
   DevLevel& L = H->dev[l];
   if (l == H->L) {
-    // the coarsest solve restricts its right-hand side itself
+    // the coarsest solve, after the restriction into its right-hand side
     DevLevel* F = fresh ? &H->dev[l - 1] : nullptr;
     launch_coarse<D, T>(L, F, F ? Arr<T>::r(*F) : nullptr, Arr<T>::rhs(L), Arr<T>::u(L, H->cur[l]),
                         H->batch, s);

@@ -179,7 +179,7 @@ struct DevLevel {
   double *u64[2] = {nullptr, nullptr}, *rhs64 = nullptr, *r64 = nullptr, *gtmp64 = nullptr;
   float *u32[2] = {nullptr, nullptr}, *rhs32 = nullptr, *r32 = nullptr, *gtmp32 = nullptr;
   // coarsest level
-  int nu_max = 0;
+  int nu_max = 0, nu_total = 0;  // largest per-problem and total unknown counts
   int32_t *umap = nullptr, *umap_off = nullptr;
   int64_t* ainv_off = nullptr;
   double* ainv = nullptr;

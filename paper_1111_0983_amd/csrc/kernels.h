@@ -7,9 +7,6 @@ namespace ghostmg {
 constexpr int kCoarseRows = 16;  // rows of the coarsest inverse per workgroup (one per wave)
 // unknowns per problem on the coarsest grid (its right-hand side is staged in 64 KB of LDS)
 constexpr int kMaxCoarseUnknowns = 8192;
-// workgroups of a coarsest solve over the whole batch (more where a problem has more than
-// kCoarseRows rows per workgroup)
-constexpr int kCoarseWorkgroups = 256;
 
 // Per-phase boundary relaxation (levels without relaxation chunks), in place on u.
 template <typename T>
@@ -115,7 +112,7 @@ void launch_restrict(const DevLevel& F, const DevLevel& C, const T* rf, T* rhsc,
 template <int D, typename T>
 void launch_prolong(const DevLevel& F, const DevLevel& C, const T* uc, T* uf, hipStream_t s);
 // coarsest solve; with F (the next finer level) its right-hand side is first restricted from
-// rf, F's defect, and stored into rhs
+// rf, F's defect, into rhs (a launch of its own)
 template <int D, typename T>
 void launch_coarse(const DevLevel& C, const DevLevel* F, const T* rf, T* rhs, T* u, int batch,
                    hipStream_t s);

@@ -1172,92 +1172,65 @@ __global__ void __launch_bounds__(256) k_prolong(const int4* __restrict__ tiles,
 
 // ---------------------------------------------------------------------------------------
 // exact solve on the coarsest grid: e = A_c^{-1} b, summed in FP64 (the FP32 cycles of the
-// defect correction read the inverse rounded to FP32).  b is the level's right-hand
-// side or, when the level has just been entered (rf set), the restriction (Sec. 2.5) of the
-// finer level's defect, which every workgroup forms in LDS itself (workgroup 0 of each
-// problem also stores it as the level's right-hand side).  Rows are dealt round robin over
-// the problem's workgroups (row r: workgroup r mod gridDim.x, wave r / gridDim.x), one
-// wave per row; a wave requests the first block of its row before b is formed and the next
-// block before it sums the current one.
+// defect correction read the inverse rounded to FP32), one row per wave, kCoarseRows rows
+// per workgroup, b gathered into LDS.  When the level has just been entered, b is first
+// restricted (Sec. 2.5) from the finer level's defect by k_coarse_restrict, one thread per
+// coarse unknown (its finer node (2x, 2y, 2z) and restriction code precomputed).
 // ---------------------------------------------------------------------------------------
 template <int D, typename T>
+__global__ void __launch_bounds__(256) k_coarse_restrict(CoarseArgs<T> a, int ntot) {
+  constexpr int KT = Pow3<D>::value;
+  const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (i >= ntot) return;
+  const uint8_t c = a.ucode[i];
+  T rr[KT];
+  restrict_gather<D, T>(a.rf, a.ufine[i], a.gf, c, rr);
+  a.rhs[a.umap[i]] = restrict_box<D, T>(c, rr);
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kCoarseRows * 64) k_coarse(CoarseArgs<T> a) {
   constexpr int NT = kCoarseRows * 64;
   constexpr int NQ = 16;  // loads of the row in flight per lane
-  constexpr int KT = Pow3<D>::value;
   extern __shared__ double bsh[];
   const int p = blockIdx.y;
   const int a0 = a.umap_off[p], nu = a.umap_off[p + 1] - a0;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r = (int)blockIdx.x + (int)gridDim.x * w;
-  const bool live = r < nu;
-  const T* Ar = a.ainv + a.ainv_off[p] + (int64_t)(live ? r : 0) * nu;
-  T av[NQ];
+  const int row0 = (int)blockIdx.x * kCoarseRows;
+  if (row0 >= nu) return;
+  // right-hand side in LDS, 4 gathers in flight per thread
+  for (int i0 = 0; i0 < nu; i0 += 4 * NT) {
+    int32_t idx[4];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int j = lane + 64 * q;
-    av[q] = live && j < nu ? Ar[j] : (T)0;
-  }
-  if (a.rf) {
-    // the fine neighbourhoods of NR unknowns per thread in flight together (in 2D, one round
-    // for up to 4 NT unknowns)
-    constexpr int NR = D == 2 ? 3 : 1;
-    for (int i0 = 0; i0 < nu; i0 += NR * NT) {
-      int32_t F0[NR];
-      uint8_t c[NR];
-#pragma unroll
-      for (int h = 0; h < NR; ++h) {
-        const int i = i0 + (int)threadIdx.x + NT * h;
-        F0[h] = a.ufine[a0 + (i < nu ? i : 0)];
-        c[h] = a.ucode[a0 + (i < nu ? i : 0)];
-      }
-      T rr[NR][KT];
-#pragma unroll
-      for (int h = 0; h < NR; ++h) restrict_gather<D, T>(a.rf, F0[h], a.gf, c[h], rr[h]);
-#pragma unroll
-      for (int h = 0; h < NR; ++h) {
-        const int i = i0 + (int)threadIdx.x + NT * h;
-        if (i >= nu) continue;
-        const T v = restrict_box<D, T>(c[h], rr[h]);
-        bsh[i] = (double)v;
-        if (blockIdx.x == 0) a.rhs[a.umap[a0 + i]] = v;
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + (int)threadIdx.x + NT * q;
+      idx[q] = i < nu ? a.umap[a0 + i] : a.umap[a0];
     }
-  } else {
-    // right-hand side in LDS, 4 gathers in flight per thread
-    for (int i0 = 0; i0 < nu; i0 += 4 * NT) {
-      int32_t idx[4];
+    T v[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = i0 + (int)threadIdx.x + NT * q;
-        idx[q] = i < nu ? a.umap[a0 + i] : a.umap[a0];
-      }
-      T v[4];
+    for (int q = 0; q < 4; ++q) v[q] = a.rhs[idx[q]];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = a.rhs[idx[q]];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = i0 + (int)threadIdx.x + NT * q;
-        if (i < nu) bsh[i] = (double)v[q];
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + (int)threadIdx.x + NT * q;
+      if (i < nu) bsh[i] = (double)v[q];
     }
   }
   __syncthreads();
-  if (!live) return;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = row0 + w;
+  if (r >= nu) return;
+  const T* Ar = a.ainv + a.ainv_off[p] + (int64_t)r * nu;
   double acc = 0.0;
   for (int j0 = 0; j0 < nu; j0 += NQ * 64) {
+    T av[NQ];
     double bv[NQ];
-    T an[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int j = j0 + lane + 64 * q, jn = j + NQ * 64;
+      const int j = j0 + lane + 64 * q;
+      av[q] = j < nu ? Ar[j] : (T)0;
       bv[q] = j < nu ? bsh[j] : 0.0;
-      an[q] = jn < nu ? Ar[jn] : (T)0;
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc += (double)av[q] * bv[q];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) av[q] = an[q];
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if (lane == 0) a.u[a.umap[a0 + r]] = (T)acc;
@@ -1698,13 +1671,14 @@ void launch_coarse(const DevLevel& C, const DevLevel* F, const T* rf, T* rhs, T*
   a.gf = F ? F->g : C.g;
   a.ufine = C.ufine;
   a.ucode = C.ucode;
-  a.rf = F ? rf : nullptr;
+  a.rf = rf;
   a.rhs = rhs;
   a.u = u;
-  // about kCoarseWorkgroups workgroups over the batch, at most kCoarseRows rows each
-  const int lo = (C.nu_max + kCoarseRows - 1) / kCoarseRows;
-  const int nwg = std::max(lo, std::min(C.nu_max, std::max(1, kCoarseWorkgroups / batch)));
-  hipLaunchKernelGGL((k_coarse<D, T>), dim3(nwg, batch), dim3(kCoarseRows * 64),
+  if (F && C.nu_total > 0)
+    hipLaunchKernelGGL((k_coarse_restrict<D, T>), dim3(lin_grid(C.nu_total)), dim3(256), 0, s, a,
+                       C.nu_total);
+  const int blocks = (C.nu_max + kCoarseRows - 1) / kCoarseRows;
+  hipLaunchKernelGGL((k_coarse<T>), dim3(blocks, batch), dim3(kCoarseRows * 64),
                      C.nu_max * sizeof(double), s, a);
 }
 
