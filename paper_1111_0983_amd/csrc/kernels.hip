@@ -105,6 +105,18 @@ __device__ __forceinline__ T prolong_candidate(const int j[3], int m, int jc[3])
 }
 
 // u + sum_m w_m e_m / sum_m w_m over the candidates with an unknown (u unchanged if none)
+// num / den for the renormalised interpolation weights: den is 2^-k times the number of
+// candidates that carry an unknown, so when it is a power of two the quotient is exactly a
+// multiplication (the same bits as the division); only the other counts divide
+template <typename T>
+__device__ __forceinline__ T renorm_quotient(T num, T den) {
+  if (den == (T)1) return num;
+  if (den == (T)0.5) return num * (T)2;
+  if (den == (T)0.25) return num * (T)4;
+  if (den == (T)0.125) return num * (T)8;
+  return num / den;
+}
+
 template <int D, typename T>
 __device__ __forceinline__ T prolong_correct(T u, const T* w, const int8_t* cc, const T* ec) {
   T num = 0, den = 0;
@@ -114,7 +126,7 @@ __device__ __forceinline__ T prolong_correct(T u, const T* w, const int8_t* cc, 
     num += w[m] * ec[m];
     den += w[m];
   }
-  return den > (T)0 ? u + num / den : u;
+  return den > (T)0 ? u + renorm_quotient<T>(num, den) : u;
 }
 
 // coarse patch under a tile and its 2-node ring (fused interpolation)
@@ -449,9 +461,7 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
           num += ex ? w1 * ce[m] : (T)0;
           den += ex ? w1 : (T)0;
         }
-        // den == 1 when every candidate carries an unknown: num / den == num exactly, and the
-        // division is left to the nodes next to the boundary
-        if (den != (T)1 && den > (T)0) num = num / den;
+        if (den > (T)0) num = renorm_quotient<T>(num, den);
         int ui = ui0;
 #pragma unroll
         for (int q = 0; q < D; ++q)
@@ -1191,8 +1201,11 @@ __global__ void __launch_bounds__(256) k_coarse_restrict(CoarseArgs<T> a, int nt
 template <typename T>
 __global__ void __launch_bounds__(kCoarseRows * 64) k_coarse(CoarseArgs<T> a) {
   constexpr int NT = kCoarseRows * 64;
-  constexpr int NQ = 16;  // loads of the row in flight per lane
-  extern __shared__ double bsh[];
+  // loads of the row in flight per lane (the stream is latency-bound: the FP32 inverse takes
+  // more loads per lane to keep about as many bytes in flight as the FP64 one)
+  constexpr int NQ = sizeof(T) == 8 ? 16 : 24;
+  extern __shared__ double bsh_d[];
+  T* bsh = (T*)bsh_d;  // b in the cycle's precision (the FP32 right-hand side is exact in FP32)
   const int p = blockIdx.y;
   const int a0 = a.umap_off[p], nu = a.umap_off[p + 1] - a0;
   const int row0 = (int)blockIdx.x * kCoarseRows;
@@ -1211,7 +1224,7 @@ __global__ void __launch_bounds__(kCoarseRows * 64) k_coarse(CoarseArgs<T> a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = i0 + (int)threadIdx.x + NT * q;
-      if (i < nu) bsh[i] = (double)v[q];
+      if (i < nu) bsh[i] = v[q];
     }
   }
   __syncthreads();
@@ -1221,16 +1234,15 @@ __global__ void __launch_bounds__(kCoarseRows * 64) k_coarse(CoarseArgs<T> a) {
   const T* Ar = a.ainv + a.ainv_off[p] + (int64_t)r * nu;
   double acc = 0.0;
   for (int j0 = 0; j0 < nu; j0 += NQ * 64) {
-    T av[NQ];
-    double bv[NQ];
+    T av[NQ], bv[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int j = j0 + lane + 64 * q;
       av[q] = j < nu ? Ar[j] : (T)0;
-      bv[q] = j < nu ? bsh[j] : 0.0;
+      bv[q] = j < nu ? bsh[j] : (T)0;
     }
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc += (double)av[q] * bv[q];
+    for (int q = 0; q < NQ; ++q) acc += (double)av[q] * (double)bv[q];
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if (lane == 0) a.u[a.umap[a0 + r]] = (T)acc;
