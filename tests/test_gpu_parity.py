@@ -127,9 +127,9 @@ def test_defect_matches_oracle(name):
                                      ("flower256", dict(split=0))])
 def test_cycle_iterates_match_oracle(name, kw):
     """Red-black V(2,1) (or W) iterates after each of the first five cycles.  The 3D cases
-    relax their band in launches of 6 or 3 phases (torus48: 6 launches per relaxation at the
-    finest level, an even count that ends with a copy back; with lambda = 3, 4 and 2
-    launches)."""
+    relax their band in launches of 6 phases (torus48: 3 launches per relaxation on both
+    levels; with lambda = 3, 2 launches, an even count that ends with a copy back; torus32:
+    3, then all 18 phases in one launch on its coarser level)."""
     s, o, dom, dim, n, rule, sol = _build(name, **kw)
     rhs = _rhs_oracle(o, dom, dim, n, sol)
     c, _ = o.cls(0)
