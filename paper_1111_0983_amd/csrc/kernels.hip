@@ -83,28 +83,6 @@ __device__ __forceinline__ double ghost_apply(const GhostRec& r, const double* _
 // coarse nodes that carry an unknown; shared by the interpolation kernel and the relaxation
 // that takes the correction while it stages its values
 // ---------------------------------------------------------------------------------------
-// Candidate m (bit q: upper neighbour along axis q) of fine node j: its coarse coordinates
-// and weight (0 when the candidate does not exist: an even coordinate has one neighbour).
-template <int D, typename T>
-__device__ __forceinline__ T prolong_candidate(const int j[3], int m, int jc[3]) {
-  T w = 1;
-  bool skip = false;
-#pragma unroll
-  for (int q = 0; q < D; ++q) {
-    const int bit = (m >> q) & 1;
-    if ((j[q] & 1) == 0) {
-      if (bit) skip = true;
-      jc[q] = j[q] >> 1;
-    } else {
-      jc[q] = bit ? (j[q] + 1) >> 1 : (j[q] - 1) >> 1;
-      w *= (T)0.5;
-    }
-  }
-  if (D == 2) jc[2] = 0;
-  return skip ? (T)0 : w;
-}
-
-// u + sum_m w_m e_m / sum_m w_m over the candidates with an unknown (u unchanged if none)
 // num / den for the renormalised interpolation weights: den is 2^-k times the number of
 // candidates that carry an unknown, so when it is a power of two the quotient is exactly a
 // multiplication (the same bits as the division); only the other counts divide
@@ -117,6 +95,7 @@ __device__ __forceinline__ T renorm_quotient(T num, T den) {
   return num / den;
 }
 
+// u + sum_m w_m e_m / sum_m w_m over the candidates with an unknown (u unchanged if none)
 template <int D, typename T>
 __device__ __forceinline__ T prolong_correct(T u, const T* w, const int8_t* cc, const T* ec) {
   T num = 0, den = 0;
@@ -1135,48 +1114,177 @@ __global__ void __launch_bounds__(256) k_restrict(const int4* __restrict__ tiles
   }
 }
 
+// 3D: one workgroup per part of a coarse tile (RTile<D, 2>: 8 x 4 x 4 coarse nodes): the
+// fine defect patch under the part (fine nodes 2o - 1 .. 2(o + B) - 1 per axis) is staged in
+// LDS in one round of loads, then a thread restricts one coarse node from it (values outside
+// the fine grid are staged as 0; they, like every tap outside a node's box, get weight 0).
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_restrict_parts(const int4* __restrict__ tiles, int ntiles,
+                                                        Geo gc, Geo gf,
+                                                        const uint8_t* __restrict__ code,
+                                                        const T* __restrict__ rf,
+                                                        T* __restrict__ rhsc, T* __restrict__ uc) {
+  using B = RTile<D, 2>;
+  constexpr int BX = B::X, BY = B::Y, BZ = B::Z;
+  static_assert(BX * BY * BZ <= 256, "one coarse node per thread");
+  constexpr int PX = 2 * BX + 1, PY = 2 * BY + 1, PZ = D == 3 ? 2 * BZ + 1 : 1;
+  constexpr int NP = PX * PY * PZ, NL = (NP + 255) / 256;
+  constexpr int KT = Pow3<D>::value;
+  __shared__ T sp[NP];
+  const int part = xcd_tile(blockIdx.x, gridDim.x);
+  if (part >= ntiles * B::N) return;
+  const int tile = part / B::N, q = part % B::N;
+  const int4 t = tiles[tile];
+  const int64_t basec = (int64_t)t.x * gc.npp, basef = (int64_t)t.x * gf.npp;
+  const int ox = t.y * Tile<D>::X + BX * (q % 2), oy = t.z * Tile<D>::Y + BY * ((q / 2) % 2);
+  const int oz = D == 3 ? t.w * Tile<D>::Z + BZ * (q / 4) : 0;
+  T pv[NL];
+  bool pok[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    const int fx = 2 * ox - 1 + i % PX, fy = 2 * oy - 1 + (i / PX) % PY;
+    const int fz = D == 3 ? 2 * oz - 1 + i / (PX * PY) : 0;
+    pok[k] = i < NP && in_box(fx, fy, fz, gf.np, D);
+    pv[k] = rf[pok[k] ? basef + fx + gf.st[1] * fy + gf.st[2] * fz : basef];
+  }
+  const int lx = threadIdx.x % BX, ly = (threadIdx.x / BX) % BY, lz = threadIdx.x / (BX * BY);
+  const int cx = ox + lx, cy = oy + ly, cz = D == 3 ? oz + lz : 0;
+  const bool cok = (int)threadIdx.x < BX * BY * BZ && in_box(cx, cy, cz, gc.np, D);
+  const int64_t X = cok ? basec + cx + gc.st[1] * cy + gc.st[2] * cz : basec;
+  const uint8_t cd = code[X];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < NP) sp[i] = pok[k] ? pv[k] : (T)0;
+  }
+  __syncthreads();
+  if (!cok) return;
+  uc[X] = (T)0;
+  if (cd == kNoUnknown) return;
+  // the 3^D fine values around (2x, 2y, 2z), x slowest (the order restrict_box takes)
+  T rr[KT];
+#pragma unroll
+  for (int qq = 0; qq < KT; ++qq) {
+    const int kx = qq / (D == 3 ? 9 : 3), ky = (qq / (D == 3 ? 3 : 1)) % 3;
+    const int kz = D == 3 ? qq % 3 : 0;
+    rr[qq] = sp[(2 * lx + kx) + PX * ((2 * ly + ky) + PY * (D == 3 ? 2 * lz + kz : 0))];
+  }
+  rhsc[X] = restrict_box<D, T>(cd, rr);
+}
+
 // ---------------------------------------------------------------------------------------
 // interpolation of the coarse error and correction of the fine unknowns (Sec. 2.6.1):
 // multilinear weights renormalised over the coarse nodes that carry an unknown
 // ---------------------------------------------------------------------------------------
+// One workgroup per fine tile: the tile's values and codes and the coarse patch under it
+// (coarse nodes o/2 .. o/2 + T/2 per axis, tile origins o even) are staged in LDS; a thread
+// takes a coarse cell, whose 2^D fine nodes (coordinates 2c, 2c + 1) all draw on the same 2^D
+// coarse nodes, and corrects them; the tile is then stored back.
 template <int D, typename T>
 __global__ void __launch_bounds__(256) k_prolong(const int4* __restrict__ tiles, int ntiles, Geo gf,
                                                  Geo gc, const int8_t* __restrict__ clsf,
                                                  const int8_t* __restrict__ clsc,
                                                  const T* __restrict__ uc, T* __restrict__ uf) {
   constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
-  constexpr int NK = TZ * TY * TX / 256;
-  constexpr int NCAND = 1 << D;
+  constexpr int NF = TZ * TY * TX, NK = NF / 256;
+  constexpr int CX = TX / 2 + 1, CY = TY / 2 + 1, CZ = D == 3 ? TZ / 2 + 1 : 1;
+  constexpr int NC = CX * CY * CZ, KC = (NC + 255) / 256;
+  constexpr int NCD = 1 << D;
+  __shared__ T sfu[NF];
+  __shared__ int8_t sfc[NF];
+  __shared__ T scu[NC];
+  __shared__ int8_t scc[NC];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntiles) return;
   const int4 t = tiles[tile];
   const int64_t basef = (int64_t)t.x * gf.npp, basec = (int64_t)t.x * gc.npp;
+  const int ox = t.y * TX, oy = t.z * TY, oz = D == 3 ? t.w * TZ : 0;
+  // every global load first (positions outside the box read the first node, code 0)
   int64_t P[NK];
   bool ok[NK];
-  int8_t cf[NK], cc[NK][NCAND];
-  T ufv[NK], ec[NK][NCAND], w[NK][NCAND];
-  // all loads first; candidates that do not exist read the first coarse node with weight 0
+  T fv[NK];
+  int8_t fc[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     const int i = threadIdx.x + 256 * k;
-    const int j[3] = {t.y * TX + i % TX, t.z * TY + (i / TX) % TY, D == 3 ? t.w * TZ + i / (TX * TY) : 0};
-    ok[k] = in_box(j[0], j[1], j[2], gf.np, D);
-    P[k] = ok[k] ? basef + j[0] + gf.st[1] * j[1] + gf.st[2] * j[2] : basef;
-    cf[k] = clsf[P[k]];
-    ufv[k] = uf[P[k]];
+    const int x = ox + i % TX, y = oy + (i / TX) % TY, z = D == 3 ? oz + i / (TX * TY) : 0;
+    ok[k] = in_box(x, y, z, gf.np, D);
+    P[k] = ok[k] ? basef + x + gf.st[1] * y + gf.st[2] * z : basef;
+    fv[k] = uf[P[k]];
+    fc[k] = clsf[P[k]];
+  }
+  T cv[KC];
+  int8_t ccv[KC];
+  bool cok[KC];
 #pragma unroll
-    for (int m = 0; m < NCAND; ++m) {
-      int jc[3];
-      w[k][m] = ok[k] ? prolong_candidate<D, T>(j, m, jc) : (T)0;
-      const int64_t X = w[k][m] != (T)0 ? basec + jc[0] + gc.st[1] * jc[1] + gc.st[2] * jc[2] : basec;
-      cc[k][m] = clsc[X];
-      ec[k][m] = uc[X];
-    }
+  for (int k = 0; k < KC; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    const int x = ox / 2 + i % CX, y = oy / 2 + (i / CX) % CY, z = D == 3 ? oz / 2 + i / (CX * CY) : 0;
+    cok[k] = i < NC && in_box(x, y, z, gc.np, D);
+    const int64_t X = cok[k] ? basec + x + gc.st[1] * y + gc.st[2] * z : basec;
+    cv[k] = uc[X];
+    ccv[k] = clsc[X];
   }
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    if (!ok[k] || cf[k] == 0) continue;
-    uf[P[k]] = prolong_correct<D, T>(ufv[k], w[k], cc[k], ec[k]);
+    const int i = threadIdx.x + 256 * k;
+    sfu[i] = fv[k];
+    sfc[i] = ok[k] ? fc[k] : (int8_t)0;
+  }
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < NC) {
+      scu[i] = cok[k] ? cv[k] : (T)0;
+      scc[i] = cok[k] ? ccv[k] : (int8_t)0;
+    }
+  }
+  __syncthreads();
+  constexpr int KX = TX / 2, KY = TY / 2, KZ = D == 3 ? TZ / 2 : 1;
+  constexpr int CS[3] = {1, CX, CX * CY}, FS[3] = {1, TX, TX * TY};
+  for (int cell = threadIdx.x; cell < KX * KY * KZ; cell += 256) {
+    const int cx = cell % KX, cy = (cell / KX) % KY, cz = cell / (KX * KY);
+    const int li0 = cx * CS[0] + cy * CS[1] + cz * CS[2];
+    const int fi0 = 2 * cx * FS[0] + 2 * cy * FS[1] + 2 * cz * FS[2];
+    int8_t cc[NCD], ucl[NCD];
+    T ce[NCD], uo[NCD];
+#pragma unroll
+    for (int m = 0; m < NCD; ++m) {
+      int li = li0, fi = fi0;
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+        if ((m >> q) & 1) li += CS[q], fi += FS[q];
+      cc[m] = scc[li];
+      ce[m] = scu[li];
+      ucl[m] = sfc[fi];
+      uo[m] = sfu[fi];
+    }
+#pragma unroll
+    for (int f = 0; f < NCD; ++f) {
+      // fine node f of the cell (bit q: odd coordinate q), weight 2^-(odd coordinates) on
+      // each candidate that carries an unknown, renormalised (the order of prolong_correct)
+      const int nodd = __builtin_popcount(f);
+      const T w1 = nodd == 0 ? (T)1 : nodd == 1 ? (T)0.5 : nodd == 2 ? (T)0.25 : (T)0.125;
+      T num = 0, den = 0;
+#pragma unroll
+      for (int m = 0; m < NCD; ++m) {
+        if ((m & f) != m || cc[m] == 0) continue;
+        num += w1 * ce[m];
+        den += w1;
+      }
+      int fi = fi0;
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+        if ((f >> q) & 1) fi += FS[q];
+      if (ucl[f] != 0 && den > (T)0) sfu[fi] = uo[f] + renorm_quotient<T>(num, den);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (ok[k] && fc[k] != 0) uf[P[k]] = sfu[i];
   }
 }
 
@@ -1648,7 +1756,11 @@ void launch_rhs_norm(const DevLevel& L, const double* rhs, uint64_t* norms, hipS
 template <int D, typename T>
 void launch_restrict(const DevLevel& F, const DevLevel& C, const T* rf, T* rhsc, T* uc,
                      hipStream_t s) {
-  if (C.ntiles)
+  if (!C.ntiles) return;
+  if constexpr (D == 3)
+    hipLaunchKernelGGL((k_restrict_parts<D, T>), dim3(tile_grid(C.ntiles * RTile<D, 2>::N)),
+                       dim3(256), 0, s, C.tiles, C.ntiles, C.g, F.g, C.rcode, rf, rhsc, uc);
+  else
     hipLaunchKernelGGL((k_restrict<D, T>), dim3(tile_grid(C.ntiles)), dim3(256), 0, s, C.tiles,
                        C.ntiles, C.g, F.g, C.rcode, rf, rhsc, uc);
 }

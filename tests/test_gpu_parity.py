@@ -124,12 +124,13 @@ def test_defect_matches_oracle(name):
 @pytest.mark.parametrize("name,kw", [("disk64", {}), ("flower256", {}), ("flower200ish", {}),
                                      ("circle_paper", dict(gamma=2)), ("torus32", {}),
                                      ("torus48", {}), ("torus48", dict(lam=3)),
-                                     ("flower256", dict(split=0))])
+                                     ("flower256", dict(split=0)), ("flower256", dict(nu2=0))])
 def test_cycle_iterates_match_oracle(name, kw):
     """Red-black V(2,1) (or W) iterates after each of the first five cycles.  The 3D cases
     relax their band in launches of 6 phases (torus48: 3 launches per relaxation on both
     levels; with lambda = 3, 2 launches, an even count that ends with a copy back; torus32:
-    3, then all 18 phases in one launch on its coarser level)."""
+    3, then all 18 phases in one launch on its coarser level).  V(2,0) takes the interpolation
+    as a launch of its own (no post-relaxation to fuse it into)."""
     s, o, dom, dim, n, rule, sol = _build(name, **kw)
     rhs = _rhs_oracle(o, dom, dim, n, sol)
     c, _ = o.cls(0)
