@@ -203,6 +203,35 @@ def test_batch_of_problems_matches_single_solves():
         assert np.abs(got[p] - ref).max() <= 1e-10 * np.abs(ref).max(), p
 
 
+def test_batch_of_3d_problems_matches_oracle():
+    """Two tori of different radii in one batch (3D chunks, extension gather and coarsest
+    solve over problem offsets), each against the oracle's direct solve."""
+    gm = _gm()
+    n, nc = 32, 8
+    doms = [geo.Torus(0.5, 0.25), geo.Torus(0.55, 0.3)]
+    rules = [pr.halfspace_rule([0.0, 0.0, 1.0]), pr.halfspace_rule([1.0, 0.0, 0.0], 0.1)]
+    sol = pr.ExpCos3D()
+    phis = np.concatenate([d.nodal_phi(n) for d in doms])
+    grid = gm.mg_grid_default(3, n, nc, batch=len(doms))
+    s = gm.Solver(_t(phis), rules, grid)
+    nn = (n + 1) ** 3
+    P = geo.grid_points(3, n)
+    fs, gs = [], []
+    for p, d in enumerate(doms):
+        c = s.classes(p)
+        G = s.ghosts(p)
+        fs.append(np.where(c == 1, sol.f(P), 0.0))
+        gs.append(pr.rhs_from_ghosts(3, n, c, G["node"], G["B"], G["type"], sol, d))
+    u = torch.zeros(len(doms) * nn, dtype=torch.float64, device=DEV)
+    info = s.solve(_t(np.concatenate(fs)), _t(np.concatenate(gs)), u, tol=1e-12)
+    assert info["status"] == 0
+    got = u.cpu().numpy().reshape(len(doms), nn)
+    for p, d in enumerate(doms):
+        o = Oracle(d.nodal_phi(n), default_grid(3, n, nc), rules[p])
+        ref = o.direct_solve(_rhs_oracle(o, d, 3, n, sol))
+        assert np.abs(got[p] - ref).max() <= 1e-10 * np.abs(ref).max(), p
+
+
 def test_error_paths():
     gm = _gm()
     s, o, dom, dim, n, rule, sol = _build("disk64")
