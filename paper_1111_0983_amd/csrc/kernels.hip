@@ -199,10 +199,10 @@ __device__ __forceinline__ void restrict_gather(const T* __restrict__ rf, int64_
   }
 }
 
-// One colour phase of a tile workgroup: the N nodes of one colour in a region whose rows
-// hold HX nodes of that colour (row (y, z), HY rows per z), at offset O from the U region's
-// origin in every axis; node x of a row has x + y + z + P even... odd per PAR: x = 2 (r mod
-// HX) + ((y + z + PAR) & 1).  Nodes whose code is not an interior one (1, 3) are left alone.
+// One colour phase of a tile workgroup over the N nodes of one colour in a region that starts
+// O nodes inside the U region along every axis and whose rows (y, z) hold HX nodes of that
+// colour, HY rows per z: node r of the phase lies at x = 2 (r mod HX) + ((y + z + PAR) & 1)
+// of its row.  Nodes whose code is not an interior one (1, 3) are left alone.
 template <int D, typename T, int N, int HX, int HY, int O, int PAR>
 __device__ __forceinline__ void tile_colour_phase(T* su, const int8_t* sc, const T* sf, int FX,
                                                   int FY, int SY, int SZ, T h2, T inv2d) {
