@@ -102,6 +102,7 @@ int upload_level(mg_handle_s* H, int l) {
   if (S.bc_nchunks) {
     L.nchunks = S.bc_nchunks;
     L.bc_smax = S.bc_smax;
+    L.bc_stride = S.bc_stride;
     L.bc_phases = S.bc_range;
     L.nsub = (int)S.bc_sub.size() - 1;
     if (L.nsub < 1 || L.nsub > 7) return MG_EINVAL;

@@ -35,6 +35,26 @@ constexpr int band_halo_slots(int D) { return D == 2 ? kBandHaloSlots2D : kBandH
 constexpr int band_max_entries(int D) {
   return (1 + 2 * band_colour_slots(D) + band_halo_slots(D)) * band_chunk_threads(D);
 }
+// 2D chunks use the fixed layout: every chunk's data has the level's size (bc_stride words)
+// and every entry sits at its slot position, so that a workgroup finds its data at
+// chunk * bc_stride without first reading the chunk's header (one dependent load fewer
+// before the first phase).  3D keeps the packed layout (its chunks are half full, and
+// a fixed layout would double the data the launch reads).
+constexpr bool band_fixed_layout(int D) { return D == 2; }
+// Offsets (int32 words) of the fixed layout: slots S = 1 + 2 band_colour_slots(D) +
+// band_halo_slots(D), W = band_chunk_threads(D), NSW = S W entries: node (-1 where empty),
+// mask, D neighbour words per entry, then the ghost rows (ids, FP64 weights, tap-major with
+// stride W), c_G per ghost slot, the interpolation candidates and the restriction pairs (per
+// entry, where the level has them).
+struct BandFixed {
+  int NSW, W, GID, GW, GC, PC, RS, stride;
+};
+constexpr BandFixed band_fixed(int D, bool pc, bool rs) {
+  const int W = band_chunk_threads(D), NSW = band_max_entries(D), K = D == 2 ? 9 : 27;
+  const int GID = (2 + D) * NSW, GW = GID + (K * W + 1) / 2 * 2, GC = GW + 2 * K * W;
+  const int PC = GC + 2 * W, RS = PC + (pc ? NSW : 0);
+  return BandFixed{NSW, W, GID, GW, GC, PC, RS, RS + (rs ? 2 * NSW : 0)};
+}
 
 // Tile shapes of the node-parallel kernels: 64 x 16 nodes in 2D, 16 x 8 x 8 in 3D.
 template <int D>
@@ -116,6 +136,7 @@ struct HostLevel {
   // launch's set (bc_sub[k] .. bc_sub[k + 1])
   int bc_range = 0;
   std::vector<int> bc_sub;
+  int bc_stride = 0;  // band_fixed_layout: words per chunk (chunk c's data at c * bc_stride)
   int64_t bc_entries = 0;               // sum of chunk sizes (redundant work included)
   // Extension chunks.  The steady state of Eq. (exp) on the upwind graph is linear in the
   // ghost defects: every extension value is a fixed combination of the defects of the ghost
@@ -147,7 +168,7 @@ struct DevLevel {
   Geo g;
   int ntiles = 0, nghost = 0, nred = 0, nblack = 0, next = 0, ndag = 0;
   int max_gp = 0, max_bandp = 0, max_extp = 0;   // largest per-problem list sizes
-  int nchunks = 0, bc_phases = 0, bc_smax = 0;
+  int nchunks = 0, bc_phases = 0, bc_smax = 0, bc_stride = 0;
   // launches per relaxation (bc_phases each) and their chunk ranges; z64 / z32: the band
   // values between launches when there is more than one
   int nsub = 0;

@@ -39,7 +39,10 @@ struct RelaxArgs {
   T h2, inv2d;
   int write_all;  // tiles also write band interior and ghost nodes (levels without chunks)
   int nchunks, phases;
+  // packed layout: chunk c's header at hdr[c * kBandHdr], offsets into data; fixed layout
+  // (band_fixed_layout): chunk c's data at data + c * stride, the header is not read
   const int32_t *hdr, *data;
+  int stride;
   // interpolation of the coarse correction uc (level with geometry gc and classes clsc)
   // applied to uin before relaxing (prolong != 0)
   int prolong;

@@ -532,12 +532,31 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
   constexpr int NC = band_colour_slots(D), NH = band_halo_slots(D);
   constexpr int NS = 1 + 2 * NC + NH;  // slots: ghost, red, black, read-only
   constexpr int NCAND = 1 << D;
+  constexpr bool FIXED = band_fixed_layout(D);
+  constexpr int W = band_chunk_threads(D);
   const int cu = __builtin_amdgcn_readfirstlane(c);
+  // packed layout: the header gives the entry count, the run lengths and the offsets; fixed
+  // layout: every offset is a constant of the level and every run has its full slots
   int32_t hd[kBandHdr];
+  if constexpr (FIXED) {
+    const BandFixed F = band_fixed(D, true, true);  // offsets below PC / RS do not depend on them
+    const int32_t base = cu * a.stride;
+    hd[0] = F.NSW;
+    hd[1] = 0;
+    hd[2] = base;
+    hd[3] = base + F.GID;
+    hd[4] = base + F.GW;
+    hd[5] = base + F.GC;
+    hd[6] = base + F.PC;
+    hd[7] = base + F.RS;
+  } else {
 #pragma unroll
-  for (int q = 0; q < kBandHdr; ++q) hd[q] = a.hdr[(int64_t)cu * kBandHdr + q];
+    for (int q = 0; q < kBandHdr; ++q) hd[q] = a.hdr[(int64_t)cu * kBandHdr + q];
+  }
   const uint32_t cnt = (uint32_t)hd[1];
-  const int ns = hd[0], ng = cnt & 1023u, nr = (cnt >> 10) & 2047u, nb = cnt >> 21;
+  const int ns = hd[0];
+  const int ng = FIXED ? W : (int)(cnt & 1023u), nr = FIXED ? NC * W : (int)((cnt >> 10) & 2047u);
+  const int nb = FIXED ? NC * W : (int)(cnt >> 21);
   const int32_t* E = a.data + hd[2];
   const int tid = threadIdx.x;
   // slot s: its run start and length
@@ -555,7 +574,7 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
     } else {
       start = ng + nr + nb, len = ns - ng - nr - nb, j = s - 1 - 2 * NC;
     }
-    const int i = tid + j * band_chunk_threads(D);
+    const int i = tid + j * W;
     ok_of[s] = i < len;
     e_of[s] = ok_of[s] ? start + i : 0;
   }
@@ -566,6 +585,12 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
   for (int s = 0; s < NS; ++s) {
     const int ec = e_of[s];
     node[s] = E[ec];
+    if constexpr (FIXED) {
+      // empty slot positions hold node -1: they read node 0 (a valid index) and are never
+      // stored (mask 0)
+      ok_of[s] = node[s] >= 0;
+      if (!ok_of[s]) node[s] = 0;
+    }
     const uint32_t mk = (uint32_t)E[ns + ec];
     mask[s] = ok_of[s] ? mk : 0u;
     if (s >= 1 && s <= 2 * NC) {
@@ -1619,6 +1644,7 @@ void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, co
   a.phases = L.bc_phases;
   a.hdr = L.bc_hdr;
   a.data = L.bc_data;
+  a.stride = L.bc_stride;
   if ((!L.nchunks || D == 3) && C) {
     // the per-phase boundary path reads u in place, and 3D chunks hold no interpolation
     // data in registers: interpolate first
@@ -1656,6 +1682,7 @@ void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, co
     b.uout = k == 0 ? uout : (k & 1) ? z : uout;
     b.nchunks = L.sub[k + 1] - L.sub[k];
     b.hdr = L.bc_hdr + (size_t)L.sub[k] * kBandHdr;
+    if (band_fixed_layout(D)) b.data = L.bc_data + (size_t)L.sub[k] * L.bc_stride;
     if (b.nchunks) launch_relax_kernel<D, T, kRelaxPlain>(b, L, s);
   }
   if (!(L.nsub & 1)) {

@@ -798,6 +798,54 @@ void put_doubles(std::vector<int32_t>& v, const std::vector<double>& d) {
 
 int32_t pack16(int a, int b) { return (int32_t)(((uint32_t)(uint16_t)a) | ((uint32_t)(uint16_t)b << 16)); }
 
+// The chunk data just written from Dv[off] (packed layout: ns entries in runs of ng ghosts,
+// nr red, nbk black, then read-only ones) rewritten in the fixed layout (band_fixed): entry i of
+// run r moves to local id (first slot of r + i / W) W + i mod W, and every local id it stores
+// (neighbour pairs, ghost stencil ids) is renumbered the same way.
+void to_fixed_layout(std::vector<int32_t>& Dv, int32_t off, int D, int ns, int ng, int nr, int nbk,
+                     int32_t gid_off, int32_t gw_off, int32_t gc_off, int32_t pc_off,
+                     int32_t rs_off, bool pc, bool rs) {
+  const BandFixed F = band_fixed(D, pc, rs);
+  const int W = F.W, NC = band_colour_slots(D), K = D == 2 ? 9 : 27;
+  const int first_slot[4] = {0, 1, 1 + NC, 1 + 2 * NC};
+  const int start[4] = {0, ng, ng + nr, ng + nr + nbk};
+  std::vector<int32_t> map(ns);
+  for (int e = 0; e < ns; ++e) {
+    const int r = e < start[1] ? 0 : e < start[2] ? 1 : e < start[3] ? 2 : 3;
+    const int i = e - start[r];
+    map[e] = (first_slot[r] + i / W) * W + i % W;
+  }
+  std::vector<int32_t> X((size_t)F.stride, 0);
+  for (int i = 0; i < F.NSW; ++i) X[i] = -1;
+  for (int e = 0; e < ns; ++e) {
+    const int id = map[e];
+    X[id] = Dv[off + e];
+    X[F.NSW + id] = Dv[off + ns + e];
+    for (int q = 0; q < D; ++q) {
+      const uint32_t w = (uint32_t)Dv[off + 2 * ns + e * D + q];
+      const int lo = (int16_t)(w & 0xffffu), hi = (int16_t)(w >> 16);
+      X[2 * F.NSW + id * D + q] = pack16(map[lo], map[hi]);
+    }
+    if (pc) X[F.PC + id] = Dv[pc_off + e];
+    if (rs) {
+      X[F.RS + 2 * id] = Dv[rs_off + 2 * e];
+      X[F.RS + 2 * id + 1] = Dv[rs_off + 2 * e + 1];
+    }
+  }
+  for (int q = 0; q < K; ++q)
+    for (int j = 0; j < ng; ++j) {
+      X[F.GID + q * W + j] = map[Dv[gid_off + q * ng + j]];
+      X[F.GW + 2 * (q * W + j)] = Dv[gw_off + 2 * (q * ng + j)];
+      X[F.GW + 2 * (q * W + j) + 1] = Dv[gw_off + 2 * (q * ng + j) + 1];
+    }
+  for (int j = 0; j < ng; ++j) {
+    X[F.GC + 2 * j] = Dv[gc_off + 2 * j];
+    X[F.GC + 2 * j + 1] = Dv[gc_off + 2 * j + 1];
+  }
+  Dv.resize(off);
+  Dv.insert(Dv.end(), X.begin(), X.end());
+}
+
 // initial runs of at most own_target consecutive (Morton-ordered) nodes of one problem
 std::vector<std::pair<size_t, size_t>> initial_runs(const std::vector<std::pair<uint64_t, int32_t>>& U,
                                                     int own_target) {
@@ -839,6 +887,7 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
   HL.bc_data.clear();
   HL.bc_nchunks = 0;
   HL.bc_smax = 0;
+  HL.bc_stride = 0;
   HL.bc_entries = 0;
   HL.bc_nown = 0;
   HL.bc_range = R;
@@ -1048,13 +1097,26 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
         Dv.push_back((int32_t)HL.rcode[touched[i]]);
       }
     }
-    const int32_t hdr[kBandHdr] = {ns, (int32_t)((uint32_t)ng | ((uint32_t)nr << 10) | ((uint32_t)nbk << 21)), off, gid_off, gw_off, gc_off,
-                                   l < H->L ? pc_off : -1, l > 0 ? rs_off : -1};
-    HL.bc_hdr.insert(HL.bc_hdr.end(), hdr, hdr + kBandHdr);
+    const uint32_t counts = (uint32_t)ng | ((uint32_t)nr << 10) | ((uint32_t)nbk << 21);
+    if (band_fixed_layout(D)) {
+      // the header keeps the counts; the data sits at chunk * bc_stride
+      const BandFixed F = band_fixed(D, l < H->L, l > 0);
+      to_fixed_layout(Dv, off, D, ns, ng, nr, nbk, gid_off, gw_off, gc_off, pc_off, rs_off,
+                      l < H->L, l > 0);
+      HL.bc_stride = F.stride;
+      const int32_t hdr[kBandHdr] = {F.NSW, (int32_t)counts, off, off + F.GID, off + F.GW,
+                                     off + F.GC, l < H->L ? off + F.PC : -1, l > 0 ? off + F.RS : -1};
+      HL.bc_hdr.insert(HL.bc_hdr.end(), hdr, hdr + kBandHdr);
+      HL.bc_smax = F.NSW;
+    } else {
+      const int32_t hdr[kBandHdr] = {ns, (int32_t)counts, off, gid_off, gw_off, gc_off,
+                                     l < H->L ? pc_off : -1, l > 0 ? rs_off : -1};
+      HL.bc_hdr.insert(HL.bc_hdr.end(), hdr, hdr + kBandHdr);
+      HL.bc_smax = std::max(HL.bc_smax, ns);
+    }
     ++HL.bc_nchunks;
     HL.bc_entries += ns;
     HL.bc_nown += (int)(b - a);
-    HL.bc_smax = std::max(HL.bc_smax, ns);
     // over the redundancy budget already: this phase range fails (early exit)
     if ((double)HL.bc_entries > max_redundancy * (double)(P / R) * (double)U.size()) return false;
     for (int32_t v : touched) {
