@@ -130,6 +130,7 @@ int upload_level(mg_handle_s* H, int l) {
   if (S.ec_nchunks) {
     L.nechunks = S.ec_nchunks;
     L.ec_smax = S.ec_smax;
+    L.ec_stride = S.ec_stride;
     if ((rc = upload(&L.ec_hdr, S.ec_hdr))) return rc;
     if ((rc = upload(&L.ec_data, S.ec_data))) return rc;
   }

@@ -41,6 +41,21 @@ constexpr int band_max_entries(int D) {
 // before the first phase).  3D keeps the packed layout (its chunks are half full, and
 // a fixed layout would double the data the launch reads).
 constexpr bool band_fixed_layout(int D) { return D == 2; }
+// Extension chunks always use a fixed layout (offsets in int32 words, every chunk
+// ext_fixed(D).stride words at chunk * stride): ghost-source nodes [0, kExtMaxGhosts) and the
+// extension nodes after them, the term offsets (kExtMaxEntries + 1), the term source ids, the
+// term weights (FP64), the ghost stencil nodes and weights (tap-major, stride
+// kExtMaxGhosts); positions beyond a chunk's counts hold node 0, weight 0 and the last term
+// offset, so a workgroup issues its first loads before its header (the counts) arrives.
+struct ExtFixed {
+  int NODES, TO, TS, TW, GN, GW, stride;
+};
+constexpr ExtFixed ext_fixed(int D) {
+  const int K = D == 2 ? 9 : 27, GS = kExtMaxGhosts, NE = kExtMaxEntries, MT = kExtMaxTerms;
+  const int TO = GS + NE, TS = TO + (NE + 1 + 1) / 2 * 2, TW = TS + (MT + 1) / 2 * 2;
+  const int GN = TW + 2 * MT, GW = GN + (K * GS + 1) / 2 * 2;
+  return ExtFixed{0, TO, TS, TW, GN, GW, GW + 2 * K * GS};
+}
 // Offsets (int32 words) of the fixed layout: slots S = 1 + 2 band_colour_slots(D) +
 // band_halo_slots(D), W = band_chunk_threads(D), NSW = S W entries: node (-1 where empty),
 // mask, D neighbour words per entry, then the ghost rows (ids, FP64 weights, tap-major with
@@ -151,7 +166,7 @@ struct HostLevel {
   // in doubles (ghost values, term weights, term ids).
   std::vector<int32_t> ec_hdr;
   std::vector<int32_t> ec_data;
-  int ec_nchunks = 0, ec_smax = 0;
+  int ec_nchunks = 0, ec_smax = 0, ec_stride = 0;
   // the same composed terms as flat arrays (3D: a gather after the defect, which has already
   // written the ghost defects): extension node, term offsets (records + 1), ghost node and
   // weight of every term
@@ -178,7 +193,7 @@ struct DevLevel {
   int32_t* band_list = nullptr;  // band and ghost nodes (copied back after an even count)
   int nband_list = 0;
   int32_t *bc_hdr = nullptr, *bc_data = nullptr;
-  int nechunks = 0, ec_smax = 0;
+  int nechunks = 0, ec_smax = 0, ec_stride = 0;
   int32_t *ec_hdr = nullptr, *ec_data = nullptr;
   int net = 0;
   int32_t *et_node = nullptr, *et_off = nullptr, *et_src = nullptr;

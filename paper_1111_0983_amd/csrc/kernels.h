@@ -90,7 +90,8 @@ struct DefectArgs {
   T inv_h2;
   uint64_t* norms;
   int nechunks;
-  const int32_t *hdr, *data;
+  const int32_t *hdr, *data;  // extension chunk c: counts at hdr[c * kExtHdr], data at c * stride
+  int stride;
 };
 
 // One complete relaxation (Sec. 2.4 step 1 with the boundary sweeps of Sec. 3.2): reads

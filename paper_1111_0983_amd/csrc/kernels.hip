@@ -863,53 +863,62 @@ __device__ void extend_chunk(const DefectArgs<T, TO>& a, int c, unsigned char* l
   constexpr int NK = kExtPerThread;
   constexpr int NT = kExtMaxTerms / kExtThreads;
   const int cu = __builtin_amdgcn_readfirstlane(c);
-  int32_t hd[kExtHdr];
-#pragma unroll
-  for (int q = 0; q < kExtHdr; ++q) hd[q] = a.hdr[(int64_t)cu * kExtHdr + q];
-  const int ne = hd[0], ngs = hd[1];
-  const int32_t* N = a.data + hd[2];
-  const int32_t* TOF = a.data + hd[3];
-  const int32_t* TS = a.data + hd[4];
-  const double* TW = (const double*)(a.data + hd[5]);
-  const int nterms = TOF[ne];
+  // fixed layout: every address below is known before the header (the counts) arrives
+  constexpr ExtFixed F = ext_fixed(D);
+  constexpr int GS = kExtMaxGhosts;
+  const int32_t* E = a.data + (int64_t)cu * a.stride;
+  const int32_t* N = E;
+  const int32_t* TOF = E + F.TO;
+  const int32_t* TS = E + F.TS;
+  const double* TW = (const double*)(E + F.TW);
+  const int32_t* gn = E + F.GN;
+  const double* gw = (const double*)(E + F.GW);
   const int tid = threadIdx.x;
-  double* sv = (double*)lds;
-  double* lw = sv + ngs;
-  int32_t* ls = (int32_t*)(lw + nterms);
-  // every global load of the chunk is issued before the first use
+  // every global load of the chunk is issued before the first use (positions beyond the
+  // counts hold node 0, weight 0 and the last term offset)
   int32_t node[NK], t0[NK], t1[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     const int e = tid + k * kExtThreads;
-    const int ec = e < ne ? e : 0;
-    node[k] = N[ngs + ec];
-    t0[k] = TOF[ec];
-    t1[k] = e < ne ? TOF[ec + 1] : t0[k];
+    node[k] = N[GS + e];
+    t0[k] = TOF[e];
+    t1[k] = TOF[e + 1];
   }
   double tw[NT];
   int32_t ts[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
     const int i = tid + j * kExtThreads;
-    const int ic = i < nterms ? i : 0;
-    tw[j] = TW[ic];
-    ts[j] = TS[ic];
+    tw[j] = TW[i];
+    ts[j] = TS[i];
   }
+  // the first pass of ghost rows (sources tid)
+  int32_t gnode[K];
+  double gwt[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    gnode[q] = gn[q * GS + tid];
+    gwt[q] = gw[q * GS + tid];
+  }
+  const int32_t self0 = N[tid];
+  const int ne = a.hdr[(int64_t)cu * kExtHdr], ngs = a.hdr[(int64_t)cu * kExtHdr + 1];
+  const int nterms = TOF[ne];
+  double* sv = (double*)lds;
+  double* lw = sv + ngs;
+  int32_t* ls = (int32_t*)(lw + nterms);
   // ghost sources tid, tid + kExtThreads, ... (a second pass only where a chunk has more
   // sources than threads)
   for (int g0 = 0; g0 < ngs; g0 += kExtThreads) {
     const bool gsrc = g0 + tid < ngs;
-    const int tg = gsrc ? g0 + tid : 0;
-    const int32_t* gn = a.data + hd[6];
-    const double* gw = (const double*)(a.data + hd[7]);
-    int32_t gnode[K];
-    double gwt[K];
+    const int tg = g0 + tid;  // < kExtMaxGhosts: positions beyond ngs hold zeros
+    if (g0 > 0) {
 #pragma unroll
-    for (int q = 0; q < K; ++q) {
-      gnode[q] = gn[q * ngs + tg];
-      gwt[q] = gw[q * ngs + tg];
+      for (int q = 0; q < K; ++q) {
+        gnode[q] = gn[q * GS + tg];
+        gwt[q] = gw[q * GS + tg];
+      }
     }
-    const int32_t self = N[tg];
+    const int32_t self = g0 > 0 ? N[tg] : self0;
     double uq[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) uq[q] = (double)a.u[gnode[q]];
@@ -1760,6 +1769,7 @@ void launch_defect(const DevLevel& L, const T* u, const T* rhs, TO* r, uint64_t*
   a.nechunks = with_ext ? L.nechunks : 0;
   a.hdr = L.ec_hdr;
   a.data = L.ec_data;
+  a.stride = L.ec_stride;
   const int nb = a.nechunks + a.nbt + (L.nghost ? lin_grid(L.nghost) : 0);
   if (nb)
     hipLaunchKernelGGL((k_defect<D, T, TO>), dim3(nb), dim3(256),

@@ -1215,6 +1215,7 @@ bool build_ext_chunks(mg_handle_s* H, int l, int own_target) {
   HL.ec_data.clear();
   HL.ec_nchunks = 0;
   HL.ec_smax = 0;
+  HL.ec_stride = 0;
   if (HL.ext.empty()) return true;
   const size_t nn = HL.cls.size();
   std::vector<int32_t> eid(nn, -1), gidx(nn, -1);
@@ -1294,7 +1295,31 @@ bool build_ext_chunks(mg_handle_s* H, int l, int own_target) {
     for (int t = 0; t < K; ++t)
       for (int32_t q : ghosts_e) wv.push_back(HL.gw[(size_t)gidx[q] * K + t]);
     put_doubles(Dv, wv);
-    const int32_t hdr[kExtHdr] = {ne, ngs, off, to_off, ts_off, tw_off, gn_off, gw_off};
+    // rewritten in the fixed layout (ext_fixed): the same arrays at fixed offsets, padded
+    {
+      const ExtFixed F = ext_fixed(D);
+      const int GS = kExtMaxGhosts, NE = kExtMaxEntries;
+      std::vector<int32_t> X((size_t)F.stride, 0);
+      for (int j = 0; j < ngs; ++j) X[j] = Dv[off + j];
+      for (int e = 0; e < ne; ++e) X[GS + e] = Dv[off + ngs + e];
+      for (int e = 0; e <= NE; ++e) X[F.TO + e] = Dv[to_off + (e < ne ? e : ne)];
+      for (int t = 0; t < nterms; ++t) {
+        X[F.TS + t] = Dv[ts_off + t];
+        X[F.TW + 2 * t] = Dv[tw_off + 2 * t];
+        X[F.TW + 2 * t + 1] = Dv[tw_off + 2 * t + 1];
+      }
+      for (int t = 0; t < K; ++t)
+        for (int j = 0; j < ngs; ++j) {
+          X[F.GN + t * GS + j] = Dv[gn_off + t * ngs + j];
+          X[F.GW + 2 * (t * GS + j)] = Dv[gw_off + 2 * (t * ngs + j)];
+          X[F.GW + 2 * (t * GS + j) + 1] = Dv[gw_off + 2 * (t * ngs + j) + 1];
+        }
+      Dv.resize(off);
+      Dv.insert(Dv.end(), X.begin(), X.end());
+      HL.ec_stride = F.stride;
+    }
+    const ExtFixed F = ext_fixed(D);
+    const int32_t hdr[kExtHdr] = {ne, ngs, off, off + F.TO, off + F.TS, off + F.TW, off + F.GN, off + F.GW};
     HL.ec_hdr.insert(HL.ec_hdr.end(), hdr, hdr + kExtHdr);
     ++HL.ec_nchunks;
     HL.ec_smax = std::max(HL.ec_smax, ngs + nterms + (nterms + 1) / 2);
