@@ -279,8 +279,8 @@ int capture(mg_handle_s* H, bool dc, int c, bool norm, hipGraphExec_t* out) {
     dc ? record_dc<3>(H, s) : record_cycle<3>(H, c, norm, s);
   if (hipStreamEndCapture(s, &graph) != hipSuccess) return MG_EHIP;
   const hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
-  return e == hipSuccess ? MG_OK : MG_EHIP;
+  const hipError_t d = hipGraphDestroy(graph);  // the executable graph does not need it
+  return e == hipSuccess && d == hipSuccess ? MG_OK : MG_EHIP;
 }
 
 // finest FP64 buffer after one FP64 cycle that starts in buffer c

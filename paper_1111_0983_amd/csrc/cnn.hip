@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(256) k_wgrad(const __bf16* __restrict__ x,
       }
     }
     __syncthreads();
-    if (threadIdx.x < cout_pad)
+    if ((int)threadIdx.x < cout_pad)
       for (int pl = 0; pl < 32; ++pl) dbacc += from_bf16(ds[pl * cout_pad + threadIdx.x]);
     for (int j = 0; j < ntile_w; ++j) {
       const int tile = wave * ntile_w + j;
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(256) k_wgrad(const __bf16* __restrict__ x,
       if (co < cout && n < ncol) out[(int64_t)co * ncol + n] = acc[j][i];
     }
   }
-  if (threadIdx.x < cout) out[(int64_t)cout * ncol + threadIdx.x] = dbacc;
+  if ((int)threadIdx.x < cout) out[(int64_t)cout * ncol + threadIdx.x] = dbacc;
 }
 
 __global__ void __launch_bounds__(256) k_wgrad_reduce(const float* __restrict__ work, int nblk,
@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(256) k_loss_partial(const float* __restrict__ 
   s2[threadIdx.x] = c;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
+    if ((int)threadIdx.x < o) {
       s1[threadIdx.x] += s1[threadIdx.x + o];
       s2[threadIdx.x] += s2[threadIdx.x + o];
     }
@@ -287,6 +287,12 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ w, const float
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ void atomic_max_f(float* dst, float v) {
   atomicMax((unsigned int*)dst, __float_as_uint(v));  // v >= 0
+}
+
+// zeroes n floats (a kernel rather than a memset node, so that the call can be captured)
+__global__ void __launch_bounds__(256) k_zero_f32(float* __restrict__ p, int n) {
+  const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (i < n) p[i] = 0.f;
 }
 
 __global__ void __launch_bounds__(256) k_feat_scale(int64_t total, int np0, Geo g0,
@@ -499,7 +505,7 @@ int mg_cnn_features(mg_handle_t h, int level, const double* f, const double* g, 
   const int np0 = L0.g.np;
   const int64_t tot0 = (int64_t)h->batch * np0 * np0;
   const int64_t totl = (int64_t)h->batch * Ll.g.np * Ll.g.np;
-  hipMemsetAsync(scale, 0, h->batch * sizeof(float), s);
+  hipLaunchKernelGGL(k_zero_f32, dim3(lin(h->batch)), dim3(256), 0, s, scale, h->batch);
   hipLaunchKernelGGL(k_feat_scale, dim3(lin(tot0)), dim3(256), 0, s, tot0, np0, L0.g, L0.cls, f, g,
                      scale);
   hipLaunchKernelGGL(k_feat, dim3(lin(totl)), dim3(256), 0, s, totl, np0, Ll.g, 1 << level, Ll.cls,
