@@ -283,6 +283,21 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   int8_t cv[NU], fc[NF], ccv[NC];
   uint8_t rcv[NF];
   bool uok[NU], fok[NF], cok[NC];
+  // the coarse patch first: it is staged after the U region, so it must not arrive last
+  if constexpr (PROLONG) {
+    const Geo& gc = a.gc;
+    const int64_t cbase = (int64_t)t.x * gc.npp;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      const int x = i % CX, y = (i / CX) % CY, z = i / (CX * CY);
+      const int cx = ox / 2 - 1 + x, cy = oy / 2 - 1 + y, cz = D == 3 ? oz / 2 - 1 + z : 0;
+      cok[k] = i < NCN && in_box(cx, cy, cz, gc.np, D);
+      const int64_t ci = cok[k] ? cbase + cx + gc.st[1] * cy + gc.st[2] * cz : cbase;
+      ev[k] = a.uc[ci];
+      ccv[k] = a.clsc[ci];
+    }
+  }
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
     const int i = threadIdx.x + 256 * k;
@@ -314,20 +329,6 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
       const int fx = 2 * ox - 3 + i % RX, fy = 2 * oy - 3 + i / RX;
       const bool ok = i < NRN && in_box(fx, fy, 0, a.gf.np, 2);
       rpv[k] = a.rf[ok ? fbase + fx + a.gf.st[1] * fy : fbase];
-    }
-  }
-  if constexpr (PROLONG) {
-    const Geo& gc = a.gc;
-    const int64_t cbase = (int64_t)t.x * gc.npp;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const int i = threadIdx.x + 256 * k;
-      const int x = i % CX, y = (i / CX) % CY, z = i / (CX * CY);
-      const int cx = ox / 2 - 1 + x, cy = oy / 2 - 1 + y, cz = D == 3 ? oz / 2 - 1 + z : 0;
-      cok[k] = i < NCN && in_box(cx, cy, cz, gc.np, D);
-      const int64_t ci = cok[k] ? cbase + cx + gc.st[1] * cy + gc.st[2] * cz : cbase;
-      ev[k] = a.uc[ci];
-      ccv[k] = a.clsc[ci];
     }
   }
 #pragma unroll
