@@ -143,7 +143,10 @@ struct HostLevel {
   // bit 31: owned, written to the output); D words of
   // (minus, plus) int16 local neighbour ids per axis.  Per ghost (tap-major, ghost fastest):
   // Pow3<D> local stencil ids (the ghost's own id for taps of zero weight) and FP64 weights
-  // (0 for those taps); one FP64 constant c_G.
+  // (0 for those taps); one FP64 constant c_G.  That is the packed layout (3D); in 2D
+  // (band_fixed_layout) the same arrays sit at the fixed offsets of band_fixed(), entry i of a
+  // run at its slot position, the ghost rows with stride W, and the header's first word is
+  // the slot count.
   std::vector<int32_t> bc_hdr;
   std::vector<int32_t> bc_data;
   int bc_nchunks = 0, bc_smax = 0, bc_nown = 0;
@@ -162,8 +165,9 @@ struct HostLevel {
   // indices (ghost sources, then extension nodes), the term offsets (per extension node and
   // one past the end, relative to the chunk's first term), the term source ids (local ghost
   // ids), the term weights (FP64), the ghost stencil nodes (tap-major), the ghost row
-  // weights (FP64, tap-major)}; at most kExtMaxTerms terms.  ec_smax: the largest chunk's LDS
-  // in doubles (ghost values, term weights, term ids).
+  // weights (FP64, tap-major)}; at most kExtMaxTerms terms, stored at the fixed offsets of
+  // ext_fixed() (chunk c at c * ec_stride).  ec_smax: the largest chunk's LDS in doubles
+  // (ghost values, term weights, term ids).
   std::vector<int32_t> ec_hdr;
   std::vector<int32_t> ec_data;
   int ec_nchunks = 0, ec_smax = 0, ec_stride = 0;
