@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY: the test-suite, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package; the product library never
 does.  It shares no code with the GPU library (``paper_1111_0983_amd``).
 
-The arithmetic lives in ``ghostmg_oracle.c`` (plain C, FP64, one thread); this module is
+The arithmetic lives in ``ghostmg_oracle.c`` (plain C, FP64; its red-black passes may run on
+several threads with results identical to one thread's); this module is
 argument marshalling plus the two "plain definition" solvers of the discrete system
 Eq. (discr): a dense LAPACK solve and a sparse direct solve of the assembled rows.
 """
@@ -28,8 +29,8 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, so its geometry decisions are
     reproducible bit for bit)."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC",
-               "-shared", "-Wall", "-Wno-unused-function", _SRC, "-o", _LIB, "-lm"]
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+               "-fPIC", "-shared", "-Wall", "-Wno-unused-function", _SRC, "-o", _LIB, "-lm"]
         subprocess.run(cmd, check=True)
     return _LIB
 
@@ -67,6 +68,7 @@ def _load():
                                       ctypes.POINTER(ctypes.c_int)]
         _lib.orc_free.argtypes = [vp]
         _lib.orc_free.restype = None
+        _lib.orc_threads.argtypes = [ctypes.c_int]
         for name in ("orc_num_levels",):
             getattr(_lib, name).argtypes = [vp]
         _lib.orc_level_info.argtypes = [vp, ctypes.c_int, i64p]
@@ -89,6 +91,12 @@ def _load():
         _lib.orc_assemble.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_int64), vp, vp, vp, vp]
     return _lib
+
+
+def threads(n: int = 0) -> int:
+    """Threads of the oracle's red-black passes (n <= 0: query).  Results do not depend on
+    it."""
+    return int(_load().orc_threads(int(n)))
 
 
 def _p(a):

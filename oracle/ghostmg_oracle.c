@@ -20,6 +20,9 @@
  *   - TGCS / V / W cycles (Sec. 1.2 remarks, Sec. 2.4), exact coarsest solve by dense
  *     LU with partial pivoting (Sec. 3.3);
  *   - convergence factor rho = ||r^(m)|| / ||r^(m-1)|| (Sec. 3).
+ * Built with OpenMP, the red-black passes, the defect, the restriction and the
+ * interpolation split their per-node loops over threads; every node's arithmetic is the
+ * same, so the results are bit for bit those of one thread.  GS-LEX stays sequential.
  *
  * Readings where the paper is silent or garbled (listed in the design notes):
  *   grid nodes lo + h*j, j in {0..N}^d; interior iff phi < 0; one-sided second-order
@@ -30,6 +33,9 @@
  *   with a fixed tie order; bilinear interpolation renormalised over present coarse nodes.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -901,20 +907,31 @@ static void defect(const ohandle* H, int l, const double* u, const double* rhs, 
   const olev* L = &H->lev[l];
   const int d = H->g.dim;
   double h2 = L->h * L->h, mi = 0.0, mg = 0.0;
-  for (int64_t P = 0; P < L->nn; ++P) {
-    if (L->cls[P] == ORC_IN) {
-      double s = 0.0;
-      for (int a = 0; a < d; ++a) {
-        s += u[P - L->st[a]] - u[P];
-        s += u[P + L->st[a]] - u[P];
+  /* rows are independent; each thread keeps its own maxima (a NaN is kept), combined below */
+#pragma omp parallel
+  {
+    double ti = 0.0, tg = 0.0;
+#pragma omp for schedule(static)
+    for (int64_t P = 0; P < L->nn; ++P) {
+      if (L->cls[P] == ORC_IN) {
+        double s = 0.0;
+        for (int a = 0; a < d; ++a) {
+          s += u[P - L->st[a]] - u[P];
+          s += u[P + L->st[a]] - u[P];
+        }
+        r[P] = rhs[P] + s / h2;
+        if (fabs(r[P]) > ti || r[P] != r[P]) ti = (r[P] != r[P]) ? NAN : fabs(r[P]);
+      } else if (L->cls[P] == ORC_GHOST) {
+        r[P] = rhs[P] - ghost_apply(H, L, L->gid[P], u);
+        if (fabs(r[P]) > tg || r[P] != r[P]) tg = (r[P] != r[P]) ? NAN : fabs(r[P]);
+      } else {
+        r[P] = 0.0;
       }
-      r[P] = rhs[P] + s / h2;
-      if (fabs(r[P]) > mi || r[P] != r[P]) mi = (r[P] != r[P]) ? NAN : fabs(r[P]);
-    } else if (L->cls[P] == ORC_GHOST) {
-      r[P] = rhs[P] - ghost_apply(H, L, L->gid[P], u);
-      if (fabs(r[P]) > mg || r[P] != r[P]) mg = (r[P] != r[P]) ? NAN : fabs(r[P]);
-    } else {
-      r[P] = 0.0;
+    }
+#pragma omp critical
+    {
+      if (ti != ti || mi != mi) mi = NAN; else if (ti > mi) mi = ti;
+      if (tg != tg || mg != mg) mg = NAN; else if (tg > mg) mg = tg;
     }
   }
   if (nin) *nin = mi;
@@ -965,16 +982,22 @@ static void relax_pass(ohandle* H, int l, double* u, const double* rhs, int band
             u[P] = relax_ghost_value(H, L, P, u, rhs);
         }
   } else {
-    /* red interior, black interior, then every ghost from the same state (Jacobi) */
-    for (int colour = 0; colour < 2; ++colour)
+    /* red interior, black interior, then every ghost from the same state (Jacobi); a node
+     * of one colour reads only the other colour, ghosts and outside nodes, so each of the
+     * three passes may run its nodes in any order (here: on several threads) */
+    for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for schedule(static)
       for (int64_t P = 0; P < L->nn; ++P) {
         if (L->cls[P] != ORC_IN) continue;
         if (band_only && !L->band[P]) continue;
         if (parity(L, d, P) != colour) continue;
         relax_interior(H, L, P, u, rhs);
       }
+    }
+#pragma omp parallel for schedule(static)
     for (int64_t g = 0; g < L->ng; ++g)
       L->tmp[g] = relax_ghost_value(H, L, L->gnode[g], u, rhs);
+#pragma omp parallel for schedule(static)
     for (int64_t g = 0; g < L->ng; ++g) u[L->gnode[g]] = L->tmp[g];
   }
 }
@@ -1011,6 +1034,7 @@ static void restrict_defect(const ohandle* H, int l, const double* r, double* rc
   const olev* F = &H->lev[l];
   const olev* C = &H->lev[l + 1];
   const int d = H->g.dim;
+#pragma omp parallel for schedule(static)
   for (int64_t X = 0; X < C->nn; ++X) {
     rc[X] = 0.0;
     if (C->cls[X] == ORC_OUT) continue;
@@ -1049,6 +1073,7 @@ static void prolong_correct(const ohandle* H, int l, const double* ec, double* u
   const olev* F = &H->lev[l];
   const olev* C = &H->lev[l + 1];
   const int d = H->g.dim;
+#pragma omp parallel for schedule(static)
   for (int64_t P = 0; P < F->nn; ++P) {
     if (F->cls[P] == ORC_OUT) continue;
     int j[3];
@@ -1132,6 +1157,18 @@ static void cycle(ohandle* H, int l, double* u, const double* rhs) {
 /* ------------------------------------------------------------------------------------ */
 
 int orc_num_levels(void* h) { return ((ohandle*)h)->L + 1; }
+
+/* Threads of the red-black passes, the defect, the restriction and the interpolation (the
+ * results do not depend on it); returns the number in use.  n <= 0 only queries. */
+int orc_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 /* out: n, nn, nint, ng, nband(interior part), ne, nu(coarsest only) */
 int orc_level_info(void* h, int l, int64_t* out) {

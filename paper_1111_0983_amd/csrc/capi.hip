@@ -141,10 +141,7 @@ int upload_level(mg_handle_s* H, int l) {
     if ((rc = upload(&L.umap_off, S.umap_off))) return rc;
     if ((rc = upload(&L.ainv_off, S.ainv_off))) return rc;
     if ((rc = upload(&L.ainv, S.ainv))) return rc;
-    if (dc) {
-      const std::vector<float> a32(S.ainv.begin(), S.ainv.end());
-      if ((rc = upload(&L.ainv32, a32))) return rc;
-    }
+    if ((rc = alloc_zero(&L.rhsc, (size_t)L.nu_total))) return rc;
     if (l > 0) {
       // per unknown: the finer level's node (2x, 2y, 2z) and the restriction code (the solve
       // restricts its right-hand side itself)
@@ -210,7 +207,7 @@ void cycle(mg_handle_s* H, int l, hipStream_t s, bool fresh = false) {
     // the coarsest solve, after the restriction into its right-hand side
     DevLevel* F = fresh ? &H->dev[l - 1] : nullptr;
     launch_coarse<D, T>(L, F, F ? Arr<T>::r(*F) : nullptr, Arr<T>::rhs(L), Arr<T>::u(L, H->cur[l]),
-                        H->batch, s);
+                        H->batch, l == 0, s);
     return;
   }
   if (fresh && H->grid.nu1 == 0) {
@@ -429,7 +426,7 @@ void free_level(DevLevel& L) {
                   L.cls, L.phi, L.tiles, L.ghosts, L.ghost_off, L.red, L.black, L.red_off, L.black_off,
                   L.ext, L.ext_merged, L.ext_off, L.dag_off, L.dag_start, L.rcode, L.u64[0],
                   L.u64[1], L.rhs64, L.r64, L.gtmp64, L.u32[0], L.u32[1], L.rhs32, L.r32, L.gtmp32,
-                  L.umap, L.umap_off, L.ainv_off, L.ainv, L.ainv32, L.ufine, L.ucode};
+                  L.umap, L.umap_off, L.ainv_off, L.ainv, L.rhsc, L.ufine, L.ucode};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   L = DevLevel();
@@ -472,7 +469,7 @@ void time_launch(mg_handle_s* h, int kernel, int level, int i, hipStream_t s) {
     case 7: {  // coarsest solve, restricting from level - 1 (if any) as in a cycle
       DevLevel* F = level > 0 ? &h->dev[level - 1] : nullptr;
       launch_coarse<D, T>(L, F, F ? Arr<T>::r(*F) : nullptr, Arr<T>::rhs(L), Arr<T>::u(L, 0),
-                          h->batch, s);
+                          h->batch, level == 0, s);
       break;
     }
     default:
@@ -778,13 +775,13 @@ int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_m
     }
     if (kernel == 1) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0 + (double)S.ext.size() * (sz + 24.0);
     if (kernel == 7) {
-      // the inverse of every problem (FP64, FP32 in the FP32 cycles), the unknowns' indices
-      // and codes, the right-hand side written and u written, and (below the finest level)
-      // the finer defect read
+      // the FP64 inverse of every problem, the unknowns' indices and codes, the FP64
+      // right-hand side written and read, u written, and (below the finest level) the finer
+      // defect read
       b = 0.0;
       for (int p = 0; p < h->batch; ++p) {
         const double m = (double)(S.umap_off[p + 1] - S.umap_off[p]);
-        b += sz * m * m + m * (2.0 * sz + 5.0);
+        b += 8.0 * m * m + m * (16.0 + sz + 5.0);
       }
       if (level > 0) {
         const HostLevel& F = h->host[level - 1];

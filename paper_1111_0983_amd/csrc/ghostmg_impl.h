@@ -223,7 +223,7 @@ struct DevLevel {
   int32_t *umap = nullptr, *umap_off = nullptr;
   int64_t* ainv_off = nullptr;
   double* ainv = nullptr;
-  float* ainv32 = nullptr;  // FP32 rounding of ainv (FP32 cycles of the defect correction)
+  double* rhsc = nullptr;   // FP64 right-hand side by unknown (nu_total), either precision
   // per coarsest unknown: the next finer level's node (2x, 2y, 2z) and the restriction code
   int32_t* ufine = nullptr;
   uint8_t* ucode = nullptr;

@@ -57,19 +57,22 @@ struct RelaxArgs {
   T* rhs_w;
 };
 
-// Coarsest solve: the explicit inverse of every problem (rows of nu doubles at ainv_off[p]),
-// applied to the right-hand side rhs, or to the restriction of rf (geometry gf, the next
-// finer level) when rf is set
+// Coarsest solve: the explicit FP64 inverse of every problem (rows of nu doubles at
+// ainv_off[p]) times the FP64 right-hand side rhsc (compact, by unknown), which is first
+// restricted from rf (geometry gf, the next finer level) when rf is set, or gathered from the
+// level's right-hand side rhs; the product is rounded into the iterate u of the cycle's
+// precision
 template <typename T>
 struct CoarseArgs {
   const int32_t *umap, *umap_off;
   const int64_t* ainv_off;
-  const T* ainv;  // FP64, or its FP32 rounding for the FP32 cycles (summed in FP64)
+  const double* ainv;
   Geo gf;
   const int32_t* ufine;  // per unknown: finer node (2x, 2y, 2z) and restriction code
   const uint8_t* ucode;
   const T* rf;
-  T* rhs;
+  const T* rhs;
+  double* rhsc;
   T* u;
 };
 
@@ -115,11 +118,12 @@ void launch_restrict(const DevLevel& F, const DevLevel& C, const T* rf, T* rhsc,
                      hipStream_t s);
 template <int D, typename T>
 void launch_prolong(const DevLevel& F, const DevLevel& C, const T* uc, T* uf, hipStream_t s);
-// coarsest solve; with F (the next finer level) its right-hand side is first restricted from
-// rf, F's defect, into rhs (a launch of its own)
+// coarsest solve; with F (the next finer level) its FP64 right-hand side is first restricted
+// from rf, F's defect (a launch of its own); without F it is the one last restricted, or,
+// with from_rhs (a hierarchy of one level), it is taken from rhs
 template <int D, typename T>
 void launch_coarse(const DevLevel& C, const DevLevel* F, const T* rf, T* rhs, T* u, int batch,
-                   hipStream_t s);
+                   bool from_rhs, hipStream_t s);
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t s);
 template <int D>

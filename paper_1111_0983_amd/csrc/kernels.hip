@@ -1324,11 +1324,13 @@ __global__ void __launch_bounds__(256) k_prolong(const int4* __restrict__ tiles,
 }
 
 // ---------------------------------------------------------------------------------------
-// exact solve on the coarsest grid: e = A_c^{-1} b, summed in FP64 (the FP32 cycles of the
-// defect correction read the inverse rounded to FP32), one row per wave, kCoarseRows rows
-// per workgroup, b gathered into LDS.  When the level has just been entered, b is first
-// restricted (Sec. 2.5) from the finer level's defect by k_coarse_restrict, one thread per
-// coarse unknown (its finer node (2x, 2y, 2z) and restriction code precomputed).
+// exact solve on the coarsest grid: e = A_c^{-1} b in FP64 in either cycle precision (the
+// FP32 cycles of the defect correction round only the result into their iterate), one row
+// per wave, kCoarseRows rows per workgroup, b (FP64, compact by unknown) staged in LDS.
+// When the level has just been entered, b is first restricted (Sec. 2.5) from the finer
+// level's defect by k_coarse_restrict, one thread per coarse unknown (its finer node
+// (2x, 2y, 2z) and restriction code precomputed), the box sum taken in FP64; on a hierarchy
+// of one level, k_coarse_gather takes b from the level's right-hand side.
 // ---------------------------------------------------------------------------------------
 template <int D, typename T>
 __global__ void __launch_bounds__(256) k_coarse_restrict(CoarseArgs<T> a, int ntot) {
@@ -1338,54 +1340,44 @@ __global__ void __launch_bounds__(256) k_coarse_restrict(CoarseArgs<T> a, int nt
   const uint8_t c = a.ucode[i];
   T rr[KT];
   restrict_gather<D, T>(a.rf, a.ufine[i], a.gf, c, rr);
-  a.rhs[a.umap[i]] = restrict_box<D, T>(c, rr);
+  double rd[KT];
+#pragma unroll
+  for (int q = 0; q < KT; ++q) rd[q] = (double)rr[q];
+  a.rhsc[i] = restrict_box<D, double>(c, rd);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse_gather(CoarseArgs<T> a, int ntot) {
+  const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (i < ntot) a.rhsc[i] = (double)a.rhs[a.umap[i]];
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kCoarseRows * 64) k_coarse(CoarseArgs<T> a) {
   constexpr int NT = kCoarseRows * 64;
-  // loads of the row in flight per lane (the stream is latency-bound: the FP32 inverse takes
-  // more loads per lane to keep about as many bytes in flight as the FP64 one)
-  constexpr int NQ = sizeof(T) == 8 ? 16 : 24;
-  extern __shared__ double bsh_d[];
-  T* bsh = (T*)bsh_d;  // b in the cycle's precision (the FP32 right-hand side is exact in FP32)
+  constexpr int NQ = 16;  // loads of the row in flight per lane (the stream is latency-bound)
+  extern __shared__ double bsh[];
   const int p = blockIdx.y;
   const int a0 = a.umap_off[p], nu = a.umap_off[p + 1] - a0;
   const int row0 = (int)blockIdx.x * kCoarseRows;
   if (row0 >= nu) return;
-  // right-hand side in LDS, 4 gathers in flight per thread
-  for (int i0 = 0; i0 < nu; i0 += 4 * NT) {
-    int32_t idx[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = i0 + (int)threadIdx.x + NT * q;
-      idx[q] = i < nu ? a.umap[a0 + i] : a.umap[a0];
-    }
-    T v[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = a.rhs[idx[q]];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = i0 + (int)threadIdx.x + NT * q;
-      if (i < nu) bsh[i] = v[q];
-    }
-  }
+  for (int i = (int)threadIdx.x; i < nu; i += NT) bsh[i] = a.rhsc[a0 + i];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = row0 + w;
   if (r >= nu) return;
-  const T* Ar = a.ainv + a.ainv_off[p] + (int64_t)r * nu;
+  const double* Ar = a.ainv + a.ainv_off[p] + (int64_t)r * nu;
   double acc = 0.0;
   for (int j0 = 0; j0 < nu; j0 += NQ * 64) {
-    T av[NQ], bv[NQ];
+    double av[NQ], bv[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int j = j0 + lane + 64 * q;
-      av[q] = j < nu ? Ar[j] : (T)0;
-      bv[q] = j < nu ? bsh[j] : (T)0;
+      av[q] = j < nu ? Ar[j] : 0.0;
+      bv[q] = j < nu ? bsh[j] : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc += (double)av[q] * (double)bv[q];
+    for (int q = 0; q < NQ; ++q) acc += av[q] * bv[q];
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if (lane == 0) a.u[a.umap[a0 + r]] = (T)acc;
@@ -1810,34 +1802,27 @@ void launch_prolong(const DevLevel& F, const DevLevel& C, const T* uc, T* uf, hi
                        F.ntiles, F.g, C.g, F.cls, C.cls, uc, uf);
 }
 
-template <typename T>
-struct CoarseInv;
-template <>
-struct CoarseInv<double> {
-  static const double* get(const DevLevel& C) { return C.ainv; }
-};
-template <>
-struct CoarseInv<float> {
-  static const float* get(const DevLevel& C) { return C.ainv32; }
-};
-
 template <int D, typename T>
 void launch_coarse(const DevLevel& C, const DevLevel* F, const T* rf, T* rhs, T* u, int batch,
-                   hipStream_t s) {
+                   bool from_rhs, hipStream_t s) {
   if (C.nu_max <= 0) return;
   CoarseArgs<T> a;
   a.umap = C.umap;
   a.umap_off = C.umap_off;
   a.ainv_off = C.ainv_off;
-  a.ainv = CoarseInv<T>::get(C);
+  a.ainv = C.ainv;
   a.gf = F ? F->g : C.g;
   a.ufine = C.ufine;
   a.ucode = C.ucode;
   a.rf = rf;
   a.rhs = rhs;
+  a.rhsc = C.rhsc;
   a.u = u;
   if (F && C.nu_total > 0)
     hipLaunchKernelGGL((k_coarse_restrict<D, T>), dim3(lin_grid(C.nu_total)), dim3(256), 0, s, a,
+                       C.nu_total);
+  else if (from_rhs && C.nu_total > 0)
+    hipLaunchKernelGGL((k_coarse_gather<T>), dim3(lin_grid(C.nu_total)), dim3(256), 0, s, a,
                        C.nu_total);
   const int blocks = (C.nu_max + kCoarseRows - 1) / kCoarseRows;
   hipLaunchKernelGGL((k_coarse<T>), dim3(blocks, batch), dim3(kCoarseRows * 64),
@@ -1883,7 +1868,7 @@ void launch_dc_update(const DevLevel& L, double* u64, const float* u32, float* u
                                       hipStream_t);                                           \
   template void launch_prolong<D, T>(const DevLevel&, const DevLevel&, const T*, T*, hipStream_t); \
   template void launch_coarse<D, T>(const DevLevel&, const DevLevel*, const T*, T*, T*, int,        \
-                                    hipStream_t);                                                  \
+                                    bool, hipStream_t);                                            \
 
 GHOSTMG_INST(2, double)
 GHOSTMG_INST(2, float)

@@ -8,9 +8,9 @@
   the learned guess (FP32 cycles inside FP64 defect correction).
 
 Samples whose domain comes within 3 coarsest mesh widths of the box, which have a connected
-component without a Dirichlet ghost (a singular problem), or whose cycle reduces the defect
-by less than a factor 0.8 per cycle (a boundary the coarsest grid does not resolve) are
-rejected.
+component without a Dirichlet ghost (a singular problem), or whose interior components merge
+on a coarser level of the hierarchy (a topology the coarsest grid does not resolve) are
+rejected; all three are decided from phi and the boundary partition alone.
 """
 from __future__ import annotations
 
@@ -45,20 +45,31 @@ def _components_ok(cls: np.ndarray, ghosts: dict, n: int) -> bool:
     return bool(has[1:].all())
 
 
-def _slow(solver, f, n, B, rho_max: float = 0.8):
-    """Problems whose mean defect reduction per cycle between cycles 5 and 10 from the zero
-    guess is worse than rho_max (including growth): the coarsest grid does not resolve their
-    boundary well enough for the cycle to converge at a useful rate (the paper's caveat on
-    too-coarse grids), so they are rejected like singular ones."""
-    cls = torch.from_numpy(np.concatenate([solver.classes(i) for i in range(B)])).to(f.device)
-    fi = torch.where(cls == 1, f, torch.zeros_like(f)).contiguous()
-    g = torch.zeros_like(fi)
-    u = torch.zeros_like(fi)
-    solver.cycles(fi, g, u, 5)
-    r5 = solver.residual(fi, g, u).max(axis=1)
-    solver.cycles(fi, g, u, 5)
-    r10 = solver.residual(fi, g, u).max(axis=1)
-    return [i for i in range(B) if not (r10[i] < r5[i] * rho_max ** 5)]
+def components_merge(cls_levels) -> bool:
+    """True when interior components of the finest grid merge on a coarser level of the
+    hierarchy: the number of connected components of Omega_h (4-connected interior nodes)
+    drops from one level to the next.  The coarse grid then cannot represent the domain:
+    its correction couples pieces that are separate on the fine grid, and the cycle
+    converges slowly or diverges (as for the paper's flower on too coarse a grid, Table
+    rhoSF3).  cls_levels: the node classes of every level, finest first, as square 2D
+    arrays.  A property of phi alone."""
+    from scipy import ndimage
+
+    prev = None
+    for c in cls_levels:
+        k = ndimage.label(np.asarray(c) == 1)[1]
+        if prev is not None and k < prev:
+            return True
+        prev = k
+    return False
+
+
+def _merges(solver, problem: int) -> bool:
+    levels = []
+    for lev in range(solver.nlev):
+        nl = solver.level(lev)["n"]
+        levels.append(solver.classes(problem, lev).reshape(nl + 1, nl + 1))
+    return components_merge(levels)
 
 
 def build_batch(seeds, n=N_FINE, nc=N_COARSE, device="cuda:0", precision=gm.MG_FP64,
@@ -100,7 +111,7 @@ def build_batch(seeds, n=N_FINE, nc=N_COARSE, device="cuda:0", precision=gm.MG_F
         bad = [i for i in range(len(probs))
                if not _components_ok(solver.classes(i), solver.ghosts(i), n)]
         if not bad and screen:
-            bad = _slow(solver, torch.cat(fs), n, len(probs))
+            bad = [i for i in range(len(probs)) if _merges(solver, i)]
         if bad:
             solver.close()
             probs = [p for i, p in enumerate(probs) if i not in bad]

@@ -522,3 +522,27 @@ def test_two_arc_partition_second_order():
         errs.append(np.abs(u - w.solution.u(geo.grid_points(2, n)))[c == 1].max())
     ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
     assert all(2.5 < r < 6.0 for r in ratios), (errs, ratios)
+
+
+def test_oracle_threads_do_not_change_results():
+    """The red-black passes, defect, restriction and interpolation split their node loops
+    over threads: every node's arithmetic is unchanged, so iterates are bit-identical."""
+    import oracle as orc
+    w = pr.flower(128, 16)
+    phi = w.domain.nodal_phi(128)
+    o = Oracle(phi, default_grid(2, 128, 16), w.rule)
+    c, _ = o.cls(0)
+    G = o.ghosts(0)
+    rhs = pr.rhs_from_ghosts(2, 128, c, G["node"], G["B"], G["type"], w.solution, w.domain)
+    before = orc.threads()
+    try:
+        out = []
+        for t in (1, 4):
+            orc.threads(t)
+            u = np.zeros(rhs.size)
+            for _ in range(3):
+                o.cycle(u, rhs)
+            out.append(u)
+    finally:
+        orc.threads(before)
+    assert np.array_equal(out[0], out[1])
