@@ -74,6 +74,7 @@ def _load():
         _lib.orc_level_info.argtypes = [vp, ctypes.c_int, i64p]
         _lib.orc_get_cls.argtypes = [vp, ctypes.c_int, i8p, i8p]
         _lib.orc_get_ghosts.argtypes = [vp, ctypes.c_int] + [vp] * 11
+        _lib.orc_get_labels.argtypes = [vp, ctypes.c_int, i8p]
         _lib.orc_get_extension.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         _lib.orc_get_boxes.argtypes = [vp, ctypes.c_int, vp, vp]
         _lib.orc_defect.argtypes = [vp, ctypes.c_int, dp, dp, dp, dp]
@@ -169,6 +170,13 @@ class Oracle:
         b = np.zeros(nn, np.int8)
         _lib.orc_get_cls(self._h, l, _p(c), _p(b))
         return c, b
+
+    def labels(self, l: int) -> np.ndarray:
+        """BC type (1 D, 0 N) of the closest boundary point of every ghost and extension
+        node of level l, -1 elsewhere."""
+        lab = np.zeros(self.info(l)["nn"], np.int8)
+        _lib.orc_get_labels(self._h, l, _p(lab))
+        return lab
 
     def ghosts(self, l: int) -> dict:
         ng = self.info(l)["ng"]

@@ -1194,6 +1194,15 @@ int orc_get_cls(void* h, int l, int8_t* cls, int8_t* band) {
   return ORC_OK;
 }
 
+/* BC labels of the nodes of level l: the type (1 D, 0 N) of the closest boundary point of
+ * every ghost and extension node, -1 elsewhere */
+int orc_get_labels(void* h, int l, int8_t* lab) {
+  ohandle* H = (ohandle*)h;
+  if (l < 0 || l > H->L || !lab) return ORC_EINVAL;
+  memcpy(lab, H->lev[l].lab, (size_t)H->lev[l].nn);
+  return ORC_OK;
+}
+
 int orc_get_ghosts(void* h, int l, int64_t* node, int8_t* type, int8_t* rung, int8_t* sgn,
                    double* B, double* nG, double* nB, double* xi, double* c, int64_t* wn,
                    double* w) {

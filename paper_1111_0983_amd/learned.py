@@ -87,8 +87,10 @@ def build_batch(seeds, n=N_FINE, nc=N_COARSE, device="cuda:0", precision=gm.MG_F
         phis.append(phi)
         fs.append(el.nodal_f(p, n, device=device))
     while probs:
+        # a few accepted problems converge slowly (rho 0.9-0.95: concave corners where two
+        # ellipses meet, around 500 cycles to 1e-10); the budget lets every one finish
         grid = gm.mg_grid_default(2, n, nc, batch=len(probs), precision=precision,
-                                  inner_cycles=inner_cycles, max_cycles=200)
+                                  inner_cycles=inner_cycles, max_cycles=1000)
         try:
             solver = gm.Solver(torch.cat(phis), [p.rule for p in probs], grid)
         except gm.GhostMGError as e:
