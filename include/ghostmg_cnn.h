@@ -52,6 +52,16 @@ int64_t cnn_wgrad_work(int B, int H, int W, int cin, int cout);
 int cnn_wgrad(const void* x, const void* dy, int B, int H, int W, int cin, int cin_pad,
               int cout, int cout_pad, int dil, float* work, float* dw, float* db, void* stream);
 
+/* cnn_wgrad without a workspace argument and without any device allocation, for callers that
+ * cannot allocate (code under stream capture, tight loops, harnesses that forbid hipMalloc).
+ * The per-block partial sums live in a 16 MiB array of device memory that the library holds
+ * for the life of the process on every GPU it runs on: cnn_wgrad_work(B, H, W, cin, cout) must
+ * not exceed 4,194,304 floats (for cin = cout = 32: B*H*W <= 464,896 pixels), else MG_EINVAL.
+ * Every call on one GPU shares that array, so calls that overlap on one GPU (two streams, two
+ * threads) race; calls ordered on one stream do not.  Same results as cnn_wgrad. */
+int cnn_wgrad_noalloc(const void* x, const void* dy, int B, int H, int W, int cin, int cin_pad,
+                      int cout, int cout_pad, int dil, float* dw, float* db, void* stream);
+
 /* Masked mean squared error of pred against target over mask != 0 (FP32 [n] each):
  * *loss (device FP32) and dy = d loss / d pred as BF16 [n][8] (channel 0, others zero). */
 int cnn_loss(const float* pred, const float* target, const float* mask, int64_t n, float* loss,

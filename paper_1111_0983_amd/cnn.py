@@ -26,6 +26,7 @@ _lib.cnn_conv.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.
 _lib.cnn_wgrad_work.argtypes = [ctypes.c_int] * 5
 _lib.cnn_wgrad_work.restype = ctypes.c_int64
 _lib.cnn_wgrad.argtypes = [_vp, _vp] + [ctypes.c_int] * 8 + [_vp, _vp, _vp, _vp]
+_lib.cnn_wgrad_noalloc.argtypes = [_vp, _vp] + [ctypes.c_int] * 8 + [_vp, _vp, _vp]
 _lib.cnn_loss.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
 _lib.cnn_adam.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                           ctypes.c_float, ctypes.c_float, ctypes.c_int, _vp]
@@ -85,6 +86,13 @@ def wgrad(x, dy, B, H, W, cin, cout, dil, stream=None):
     _check(_lib.cnn_wgrad(_p(x), _p(dy), B, H, W, cin, cpad(cin), cout, cpad(cout), dil,
                           _p(work), _p(dw), _p(db), _vp(stream)), "cnn_wgrad")
     return dw, db
+
+
+def wgrad_noalloc(x, dy, B, H, W, cin, cout, dil, dw, db, stream=None):
+    """cnn_wgrad_noalloc: the weight gradient into the caller's dw, db with no allocation
+    (neither by the library nor here)."""
+    _check(_lib.cnn_wgrad_noalloc(_p(x), _p(dy), B, H, W, cin, cpad(cin), cout, cpad(cout), dil,
+                                  _p(dw), _p(db), _vp(stream)), "cnn_wgrad_noalloc")
 
 
 def loss(pred, target, mask, with_grad=True, stream=None):

@@ -6,6 +6,8 @@
 // and B[k 8(l/16)..+7][col l%16] and receives D[rows 4(l/16)..+3][col l%16].
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "../../include/ghostmg_cnn.h"
 #include "ghostmg_impl.h"
 
@@ -403,6 +405,31 @@ __global__ void __launch_bounds__(256) k_apply(int64_t total, int np0, Geo g0, G
 
 inline int lin(int64_t n) { return (int)((n + 255) / 256); }
 
+// Per-block partial sums of cnn_wgrad_noalloc: a file-scope device array (every GPU the
+// library runs on holds its own copy until the process ends).  Host code never passes the
+// array's name to a kernel or a copy: it takes the device address that hipGetSymbolAddress
+// returns for the current device, looked up once per device.
+constexpr int64_t kWgradScratchFloats = (int64_t)4 << 20;  // 16 MiB
+__device__ __align__(256) float scratch[kWgradScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+int wgrad_scratch(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return MG_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return MG_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MG_EHIP;
+    g_scratch_ptr[dev] = (float*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -469,6 +496,17 @@ int cnn_wgrad(const void* x, const void* dy, int B, int H, int W, int cin, int c
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(lin(nout)), dim3(256), 0, s, (const float*)work, nblk,
                      wstride, cin, cin_pad, cout, dw, db);
   return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
+}
+
+int cnn_wgrad_noalloc(const void* x, const void* dy, int B, int H, int W, int cin, int cin_pad,
+                      int cout, int cout_pad, int dil, float* dw, float* db, void* stream) {
+  if (cin_pad != cnn_cpad(cin) || cout_pad != cnn_cpad(cout) || B < 1 || H < 1 || W < 1)
+    return MG_EINVAL;
+  if (cnn_wgrad_work(B, H, W, cin, cout) > kWgradScratchFloats) return MG_EINVAL;
+  float* work = nullptr;
+  const int rc = wgrad_scratch(&work);
+  if (rc != MG_OK) return rc;
+  return cnn_wgrad(x, dy, B, H, W, cin, cin_pad, cout, cout_pad, dil, work, dw, db, stream);
 }
 
 int cnn_loss(const float* pred, const float* target, const float* mask, int64_t n, float* loss,
