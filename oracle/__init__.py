@@ -35,6 +35,23 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+_LIB_NATIVE = os.path.join(_HERE, "libghostmg_oracle_native.so")
+
+
+def use_native() -> str:
+    """Compile the oracle for the host it runs on (gcc -O3 -march=native, OpenMP, still no
+    FMA contraction, so results are those of the portable build) and load that library for
+    every later call.  Only the CPU-baseline timing uses it; call before the first Oracle."""
+    global _LIB, _lib
+    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-std=c99", "-fPIC", "-shared", "-Wall", "-Wno-unused-function", _SRC, "-o",
+           _LIB_NATIVE, "-lm"]
+    subprocess.run(cmd, check=True)
+    _LIB, _lib = _LIB_NATIVE, None
+    _load()
+    return _LIB
+
+
 class _Grid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("lo", ctypes.c_double),
                 ("hi", ctypes.c_double), ("n_coarse", ctypes.c_int), ("nu1", ctypes.c_int),

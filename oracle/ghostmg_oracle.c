@@ -622,7 +622,7 @@ static int member(const olev* F, int64_t P, int inside, int lab) {
 /* Maximal full rectangle T in the 3^d neighbourhood whose nodes all lie in I_h (Sec. 2.5). */
 static void choose_box(const olev* F, int d, const int jf[3], int inside, int lab, int8_t lo[3],
                        int8_t hi[3]) {
-  int best_key[7];
+  int best_key[7] = {0, 0, 0, 0, 0, 0, 0};
   int have = 0;
   int ncand = 1;
   for (int a = 0; a < d; ++a) ncand *= 4;

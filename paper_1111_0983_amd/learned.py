@@ -300,8 +300,8 @@ def evaluate_each(net, probs, f, g, tol=1e-10, device="cuda:0", reps=3):
         phi = el.nodal_phi(p, N_FINE, device=device)
         fi = f[i * nn:(i + 1) * nn].contiguous()
         gi = g[i * nn:(i + 1) * nn].contiguous()
-        s64 = gm.Solver(phi, [p.rule], gm.mg_grid_default(2, N_FINE, N_COARSE, max_cycles=400))
-        sdc = gm.Solver(phi, [p.rule], gm.mg_grid_default(2, N_FINE, N_COARSE, max_cycles=400,
+        s64 = gm.Solver(phi, [p.rule], gm.mg_grid_default(2, N_FINE, N_COARSE, max_cycles=1000))
+        sdc = gm.Solver(phi, [p.rule], gm.mg_grid_default(2, N_FINE, N_COARSE, max_cycles=1000,
                                                           precision=gm.MG_FP32_DC))
         u = torch.zeros_like(fi)
 
