@@ -138,6 +138,17 @@ int mg_solve(mg_handle_t h, const double* f, const double* g, double* u, double 
 /* Exactly ncycles cycles from u, no tolerance test (iterate-level checks). */
 int mg_cycles(mg_handle_t h, const double* f, const double* g, double* u, int ncycles);
 
+/* Convergence factor of the cycle (Sec. 3): the homogeneous problem (f = g = 0) iterated
+ * from u0 (device, batch * (n+1)^dim FP64, read only), rho^(m) = ||r^(m)||_inf /
+ * ||r^(m-1)||_inf (max over the batch, interior and ghost parts), the iterate rescaled after
+ * every cycle; stops when |rho^(m) - rho^(m-1)| / rho^(m) < rtol (rtol 0: never), when
+ * rho^(m) > 1e3 or the defect vanishes or is not finite, or after max_cycles.  *rho: the
+ * last factor; hist (host, max_cycles values, may be NULL): rho^(m) for m = 1..*ncycles.
+ * The two-grid cycle of the paper is a hierarchy of two levels (n_coarse = n / 2).
+ * FP64 handles only (MG_EINVAL otherwise); MG_EINVAL also for a zero initial defect. */
+int mg_rho(mg_handle_t h, const double* u0, int max_cycles, double rtol, double* rho,
+           double* hist, int* ncycles);
+
 /* Defect r = (f + Delta_h u on Omega_h, g - L_h u on Gamma_h, 0 elsewhere) of the finest
  * level (Sec. 2.4 step 3); r may be NULL.  norms (host, 2 * batch values): the infinity
  * norms of the interior and ghost parts per problem. */
@@ -162,6 +173,17 @@ int mg_residual(mg_handle_t h, const double* f, const double* g, const double* u
  * its row weights; per extension node its value and weights). */
 int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_ms,
                    double* bytes);
+
+/* Level-set reinitialisation, Eq. (sdf) (Sec. 2.2): `iters` forward-Euler steps (dt = h / 2)
+ * of d phi / d t = sgn(phi0) (1 - |grad phi|) from phi = phi0, which turn a level-set function
+ * into a signed distance function near its zero set, as mg_setup assumes (a few mesh widths
+ * per step pair; the zero set does not move).  Upwind (Godunov) |grad phi| away from the
+ * boundary; nodes next to it (phi0 changes sign or vanishes towards an axis neighbour) relax
+ * towards phi0 / |grad phi0|.  phi0, phi, tmp: device memory, batch * (n+1)^dim FP64 each on
+ * the box [lo, hi]^dim (x fastest), three distinct buffers; phi receives the result, tmp is
+ * scratch.  Work is ordered on `stream` (hipStream_t, NULL = null stream). */
+int mg_reinit(int dim, int n, int batch, double lo, double hi, const double* phi0, int iters,
+              double* phi, double* tmp, void* stream);
 
 void mg_free(mg_handle_t h);
 

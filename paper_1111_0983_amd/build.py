@@ -19,7 +19,8 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",
 SOURCES = [("setup.cpp", ["-ffp-contract=off", "-x", "hip"]),
            ("kernels.hip", []),
            ("capi.hip", []),
-           ("cnn.hip", [])]
+           ("cnn.hip", []),
+           ("reinit.hip", [])]
 
 
 def build(verbose: bool = False) -> str:

@@ -420,6 +420,70 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
   return status;
 }
 
+// The convergence factor of Sec. 3: the homogeneous problem (f = g = 0) from the initial
+// iterate u0, rho^(m) = ||r^(m)||_inf / ||r^(m-1)||_inf (max over the batch and over the
+// interior and ghost parts), the iterate rescaled by 1 / ||r^(m)|| after every cycle (the
+// iteration is linear), stopped when |rho^(m) - rho^(m-1)| / rho^(m) < rtol, when the
+// defect vanishes or stops being finite, when rho^(m) > 1e3, or after max_cycles cycles.
+int rho_impl(mg_handle_s* H, const double* u0, int max_cycles, double rtol, double* rho,
+             double* hist, int* ncycles) {
+  hipStream_t s = stream_of(H);
+  // f, g and u all read from u0 (valid memory); the right-hand side is then cleared
+  int rc = H->dim == 2 ? pack<2>(H, u0, u0, u0) : pack<3>(H, u0, u0, u0);
+  if (rc) return rc;
+  DevLevel& L = H->dev[0];
+  const int64_t nn = (int64_t)H->batch * L.g.npp;
+  launch_fill<double>(L.rhs64, nn, 0.0, s);
+  for (int c = 0; c < (after_cycle(H, 0) == 1 ? 2 : 1); ++c)
+    if ((rc = capture(H, false, c, true, &H->graph_cycle[c][1]))) return rc;
+  auto norm = [&](double* out) -> int {
+    HIP_TRY(hipMemcpyAsync(H->norms_host, H->norms, 2 * H->batch * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double m = 0.0;
+    for (int p = 0; p < 2 * H->batch; ++p) {
+      const double v = H->norms_host[p];
+      if (!(v == v)) {
+        m = NAN;
+        break;
+      }
+      m = std::max(m, v);
+    }
+    *out = m;
+    return MG_OK;
+  };
+  if (H->dim == 2)
+    defect_norm64<2>(H, 0, s);
+  else
+    defect_norm64<3>(H, 0, s);
+  double rprev;
+  if ((rc = norm(&rprev))) return rc;
+  if (!(rprev > 0.0) || !(rprev < INFINITY)) return MG_EINVAL;
+  launch_scale(L.u64[0], nn, 1.0 / rprev, s);
+  H->cur0 = 0;
+  double rr = 0.0, prev_rho = -1.0;
+  int m = 0;
+  while (m < max_cycles) {
+    HIP_TRY(hipGraphLaunch(H->graph_cycle[H->cur0][1], s));
+    H->cur0 = after_cycle(H, H->cur0);
+    ++m;
+    double rn;
+    if ((rc = norm(&rn))) return rc;
+    rr = rn;  // the previous iterate's defect norm is 1 after the rescaling
+    if (hist) hist[m - 1] = rr;
+    if (!(rn > 0.0) || !(rn < INFINITY)) break;
+    launch_scale(L.u64[H->cur0], nn, 1.0 / rn, s);
+    if (prev_rho > 0.0 && std::fabs(rr - prev_rho) / rr < rtol) break;
+    if (rr > 1e3) break;
+    prev_rho = rr;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hipGetLastError() != hipSuccess) return MG_EHIP;
+  *rho = rr;
+  *ncycles = m;
+  return MG_OK;
+}
+
 void free_level(DevLevel& L) {
   void* ptrs[] = {L.bc_hdr, L.bc_data, L.z64, L.z32, L.band_list, L.ec_hdr, L.ec_data,
                   L.et_node, L.et_off, L.et_src, L.et_wt, L.rcls, L.gw,
@@ -703,6 +767,14 @@ int mg_solve(mg_handle_t h, const double* f, const double* g, double* u, double 
 int mg_cycles(mg_handle_t h, const double* f, const double* g, double* u, int ncycles) {
   if (!h || ncycles < 0) return MG_EINVAL;
   return solve_impl(h, f, g, u, 0.0, ncycles, nullptr);
+}
+
+int mg_rho(mg_handle_t h, const double* u0, int max_cycles, double rtol, double* rho,
+           double* hist, int* ncycles) {
+  if (!h || !u0 || !rho || !ncycles || max_cycles < 1 || !(rtol >= 0.0) ||
+      h->grid.precision != MG_FP64)
+    return MG_EINVAL;
+  return rho_impl(h, u0, max_cycles, rtol, rho, hist, ncycles);
 }
 
 int mg_residual(mg_handle_t h, const double* f, const double* g, const double* u, double* r,

@@ -126,6 +126,7 @@ void launch_coarse(const DevLevel& C, const DevLevel* F, const T* rf, T* rhs, T*
                    bool from_rhs, hipStream_t s);
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t s);
+void launch_scale(double* p, int64_t n, double v, hipStream_t s);
 template <int D>
 void launch_pack(const DevLevel& L, const double* f, const double* g, const double* uin,
                  double* rhs, double* u, hipStream_t s);

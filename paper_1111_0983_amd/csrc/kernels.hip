@@ -1387,6 +1387,12 @@ __global__ void __launch_bounds__(kCoarseRows * 64) k_coarse(CoarseArgs<T> a) {
 // plumbing: fills, packing of the caller's arrays, defect-correction updates
 // ---------------------------------------------------------------------------------------
 template <typename T>
+__global__ void __launch_bounds__(256) k_scale(T* __restrict__ p, int64_t n, T v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] *= v;
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256) k_fill(T* __restrict__ p, int64_t n, T v) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1827,6 +1833,10 @@ void launch_coarse(const DevLevel& C, const DevLevel* F, const T* rf, T* rhs, T*
   const int blocks = (C.nu_max + kCoarseRows - 1) / kCoarseRows;
   hipLaunchKernelGGL((k_coarse<T>), dim3(blocks, batch), dim3(kCoarseRows * 64),
                      C.nu_max * sizeof(double), s, a);
+}
+
+void launch_scale(double* p, int64_t n, double v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL((k_scale<double>), dim3(lin_grid(n)), dim3(256), 0, s, p, n, v);
 }
 
 template <typename T>

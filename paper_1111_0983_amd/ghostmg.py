@@ -73,6 +73,9 @@ def _load():
     lib.mg_solve.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(mg_stats)]
     lib.mg_cycles.argtypes = [vp, vp, vp, vp, ctypes.c_int]
     lib.mg_residual.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.mg_rho.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp, vp, vp]
+    lib.mg_reinit.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                              ctypes.c_double, vp, ctypes.c_int, vp, vp, vp]
     lib.mg_time_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.mg_free.argtypes = [vp]
@@ -124,6 +127,20 @@ def _ptr(t):
         return ctypes.c_void_p(t.ctypes.data)
     assert t.dtype.is_floating_point and t.is_contiguous()
     return ctypes.c_void_p(t.data_ptr())
+
+
+def reinit(phi0, dim: int, n: int, iters: int, batch: int = 1, lo: float = -1.0,
+           hi: float = 1.0, stream=None):
+    """Signed distance function from the level-set function phi0 (device tensor of
+    batch * (n+1)^dim FP64 values) by `iters` steps of Eq. (sdf) (mg_reinit)."""
+    import torch
+
+    assert phi0.dtype == torch.float64 and phi0.is_contiguous() and phi0.is_cuda
+    phi = torch.empty_like(phi0)
+    tmp = torch.empty_like(phi0)
+    _check(_lib.mg_reinit(dim, n, batch, lo, hi, _ptr(phi0), int(iters), _ptr(phi), _ptr(tmp),
+                          ctypes.c_void_p(stream)), "mg_reinit")
+    return phi
 
 
 class Solver:
@@ -201,6 +218,16 @@ class Solver:
 
     def cycles(self, f, g, u, ncycles: int):
         _check(_lib.mg_cycles(self._h, _ptr(f), _ptr(g), _ptr(u), int(ncycles)), "mg_cycles")
+
+    def rho(self, u0, max_cycles: int = 100, rtol: float = 1e-3):
+        """Convergence factor of the cycle on the homogeneous problem from u0 (mg_rho):
+        (last factor, the factors of every cycle)."""
+        hist = np.zeros(max_cycles)
+        r = ctypes.c_double(0.0)
+        m = ctypes.c_int(0)
+        _check(_lib.mg_rho(self._h, _ptr(u0), int(max_cycles), float(rtol), ctypes.byref(r),
+                           ctypes.c_void_p(hist.ctypes.data), ctypes.byref(m)), "mg_rho")
+        return r.value, hist[:m.value]
 
     def residual(self, f, g, u, r=None):
         norms = np.zeros(2 * self.batch)
