@@ -372,6 +372,8 @@ def bench_learned(args, torch):
     pp = learned.evaluate_each(net, probs, f, g, reps=2)
     out = {f"learned_{k}": round(v, 3) for k, v in pp.items() if k.endswith(("_mean", "_median"))}
     out["learned_problems"] = len(probs)
+    out["learned_failed"] = pp.get("failed", [])
+    out["learned_zero64_cycles_max"] = max(pp["zero64_cycles"]) if pp.get("zero64_cycles") else None
     out["learned_rejected"] = {"box_margin": drawn - len(seeds),
                                "singular_or_merging": len(seeds) - len(probs)}
     out["learned_workload"] = "ellipse unions 512^2, Nc=32, per-problem solves to 1e-10"
@@ -379,6 +381,77 @@ def bench_learned(args, torch):
         f"{pp['zero64_ms_mean']:.2f} ms, zero FP32-DC {pp['zero_dc_cycles_mean']:.1f} cycles "
         f"{pp['zero_dc_ms_mean']:.2f} ms, learned FP32-DC {pp['learned_dc_cycles_mean']:.1f} "
         f"cycles {pp['learned_dc_ms_mean']:.2f} ms (means over {len(probs)} problems)")
+    return out
+
+
+def bench_paper_rho(gm, torch, dev):
+    """The convergence factors of the paper's tables measured on the GPU cycle (red-black
+    ordering, W-cycle, lambda = 5, delta = 3h, D/N-split transfers, coarsest grid 8 and the
+    diagonal Nc = N/2), beside the printed GS-LEX values (tests/golden/rho_tables.txt)."""
+    import numpy as np
+
+    from workloads import geometry as geo, problems as pr
+
+    printed = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "rho_tables.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        t, dom, a, b, cyc, lam, nc, n, v = line.split()
+        printed[(dom, int(a), int(b), cyc, int(lam), nc, int(n))] = v
+    doms = {"circle": geo.paper_circle(), "ellipse": geo.rotated_ellipse_paper(),
+            "saddle": geo.saddle_domain(), "flower": geo.Flower(0.5, 0.2, 5)}
+    rows = []
+    t0 = time.perf_counter()
+    for key, v in sorted(printed.items()):
+        dom, a, b, cyc, lam, nc, n = key
+        ncv = n // 2 if cyc == "TGCS" else int(nc)
+        grid = gm.mg_grid_default(2, n, ncv, nu1=a, nu2=b, gamma=2 if cyc == "W" else 1, lam=lam)
+        phi = doms[dom].nodal_phi(n)
+        try:
+            s = gm.Solver(torch.from_numpy(phi).to(dev), [pr.paper_rule()], grid)
+        except gm.GhostMGError as e:
+            rows.append([dom, a + b, cyc, lam, ncv, n, v, f"setup {e.code}"])
+            continue
+        c = s.classes()
+        u0 = torch.from_numpy(np.where(c > 0, np.random.default_rng(1).uniform(-1, 1, c.size),
+                                       0.0)).to(dev)
+        r, hist = s.rho(u0, max_cycles=100, rtol=1e-3)
+        s.close()
+        rows.append([dom, a + b, cyc, lam, ncv, n, v, round(r, 3)])
+    log(f"[bench] paper rho tables on the GPU: {len(rows)} entries in "
+        f"{time.perf_counter() - t0:.1f}s")
+    return {"paper_rho_gpu": {"columns": ["domain", "nu", "cycle", "lambda", "Nc", "N",
+                                          "printed (GS-LEX)", "GPU red-black"],
+                              "rows": rows}}
+
+
+def bench_reinit(gm, torch, dev, n=384, iters=100):
+    """Eq. (sdf) on the GPU at the headline size: the tank's quadratic level set
+    (x/a)^2 + (y/b)^2 + (z/c)^2 - 1 reinitialised by `iters` steps."""
+    from workloads import tank
+
+    x = torch.linspace(-1.0, 1.0, n + 1, dtype=torch.float64, device=dev)
+    Z, Y, X = torch.meshgrid(x, x, x, indexing="ij")
+    a, b, c = tank.AXES
+    phi0 = ((X / a) ** 2 + ((Y + 0.2) / b) ** 2 + (Z / c) ** 2 - 1.0).reshape(-1).contiguous()
+    del X, Y, Z
+    gm.reinit(phi0, 3, n, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi = gm.reinit(phi0, 3, n, iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ex = tank.ellipsoid_sdf(n, (0.0, -0.2, 0.0), device=dev)
+    h = 2.0 / n
+    near = ex.abs() < 3 * h
+    err = float((phi - ex).abs()[near].max())
+    nodes = (n + 1) ** 3
+    out = {"reinit_workload": f"ellipsoid level set {n}^3, {iters} steps of Eq. (sdf)",
+           "reinit_ms": 1e3 * dt, "reinit_us_per_step": 1e6 * dt / iters,
+           "reinit_GBs_per_step": 24.0 * nodes / (dt / iters) / 1e9,
+           "reinit_max_err_within_3h_over_h": err / h}
+    log(f"[bench] reinit {n}^3: {1e3 * dt:.1f} ms for {iters} steps "
+        f"({out['reinit_GBs_per_step']:.0f} GB/s), error within 3h = {err / h:.3f} h")
     return out
 
 
@@ -395,7 +468,9 @@ def main():
     ap.add_argument("--no-flower", action="store_true")
     ap.add_argument("--no-torus", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--learned-problems", type=int, default=16)
+    ap.add_argument("--learned-problems", type=int, default=64)
+    ap.add_argument("--no-paper-rho", action="store_true")
+    ap.add_argument("--no-reinit", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -433,6 +508,10 @@ def main():
         extra.update(bench_torus(args, gm, pr, geo, np, torch, dev))
     if not args.no_learned:
         extra.update(bench_learned(args, torch))
+    if not args.no_paper_rho:
+        extra.update(bench_paper_rho(gm, torch, dev))
+    if not args.no_reinit:
+        extra.update(bench_reinit(gm, torch, dev))
     out = {"metric": METRIC, "value": res["value"], "unit": "unknowns/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",

@@ -80,12 +80,14 @@ int mg_cnn_features(mg_handle_t h, int level, const double* f, const double* g, 
                     float* scale);
 
 /* Training target on level `level`: target[b][i] = u_finest(node i) / scale[b] and
- * mask = 1 at the level's unknowns (FP32 [batch][(n_l+1)^2] each). */
+ * mask = 1 at the level's unknowns whose finest node is an unknown too, else 0 (FP32
+ * [batch][(n_l+1)^2] each). */
 int mg_cnn_target(mg_handle_t h, int level, const double* u, const float* scale, float* target,
                   float* mask);
 
 /* Initial guess: u0 on the finest grid = scale * multilinear interpolation of pred (FP32
- * [batch][(n_l+1)^2]) over the level's unknowns, at the finest unknowns; 0 elsewhere. */
+ * [batch][(n_l+1)^2]) over the level's unknowns whose finest node is an unknown (weights
+ * renormalised), at the finest unknowns; 0 elsewhere and where no such node is near. */
 int mg_cnn_apply(mg_handle_t h, int level, const float* pred, const float* scale, double* u0);
 
 #ifdef __cplusplus

@@ -354,8 +354,18 @@ __global__ void __launch_bounds__(256) k_feat_ghost(const GhostRec* __restrict__
   xout[p * 8 + 3] = to_bf16(r.type ? 1.f : -1.f);
 }
 
+// a node of level l carries a prediction the finest grid can use when it is an unknown of
+// level l and the finest node at the same point is an unknown too (a coarse ghost may lie
+// outside the finest ghost layer, where the finest solution is not defined)
+__device__ __forceinline__ bool valid_coarse(const int8_t* clsl, const Geo& gl, const int8_t* cls0,
+                                             const Geo& g0, int ratio, int b, int x, int y) {
+  return clsl[(int64_t)b * gl.npp + x + gl.st[1] * y] != 0 &&
+         cls0[(int64_t)b * g0.npp + ratio * x + g0.st[1] * (ratio * y)] != 0;
+}
+
 __global__ void __launch_bounds__(256) k_target(int64_t total, int np0, Geo gl, int ratio,
                                                 const int8_t* __restrict__ clsl,
+                                                const int8_t* __restrict__ cls0, Geo g0,
                                                 const double* __restrict__ u,
                                                 const float* __restrict__ scale,
                                                 float* __restrict__ tgt, float* __restrict__ mask) {
@@ -365,11 +375,11 @@ __global__ void __launch_bounds__(256) k_target(int64_t total, int np0, Geo gl, 
   const int b = (int)(i / nl);
   const int q = (int)(i - (int64_t)b * nl);
   const int x = q % gl.np, y = q / gl.np;
-  const int8_t c = clsl[(int64_t)b * gl.npp + x + gl.st[1] * y];
+  const bool ok = valid_coarse(clsl, gl, cls0, g0, ratio, b, x, y);
   const float s = scale[b] > 0.f ? scale[b] : 1.f;
   const int64_t F = (int64_t)b * np0 * np0 + (int64_t)(ratio * x) + (int64_t)np0 * (ratio * y);
-  tgt[i] = c ? (float)(u[F] / s) : 0.f;
-  mask[i] = c ? 1.f : 0.f;
+  tgt[i] = ok ? (float)(u[F] / s) : 0.f;
+  mask[i] = ok ? 1.f : 0.f;
 }
 
 __global__ void __launch_bounds__(256) k_apply(int64_t total, int np0, Geo g0, Geo gl, int ratio,
@@ -396,7 +406,7 @@ __global__ void __launch_bounds__(256) k_apply(int64_t total, int np0, Geo g0, G
       const int X = X0 + cx, Y = Y0 + cy;
       const float w = (cx ? fx : 1.f - fx) * (cy ? fy : 1.f - fy);
       if (w == 0.f || X >= gl.np || Y >= gl.np) continue;
-      if (!clsl[(int64_t)b * gl.npp + X + gl.st[1] * Y]) continue;
+      if (!valid_coarse(clsl, gl, cls0, g0, ratio, b, X, Y)) continue;
       num += w * pred[(int64_t)b * gl.np * gl.np + X + (int64_t)gl.np * Y];
       den += w;
     }
@@ -562,7 +572,7 @@ int mg_cnn_target(mg_handle_t h, int level, const double* u, const float* scale,
   const int np0 = h->dev[0].g.np;
   const int64_t totl = (int64_t)h->batch * Ll.g.np * Ll.g.np;
   hipLaunchKernelGGL(k_target, dim3(lin(totl)), dim3(256), 0, h->stream, totl, np0, Ll.g,
-                     1 << level, Ll.cls, u, scale, target, mask);
+                     1 << level, Ll.cls, h->dev[0].cls, h->dev[0].g, u, scale, target, mask);
   return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 

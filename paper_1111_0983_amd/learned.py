@@ -153,8 +153,26 @@ def generate(n_samples: int, seed0: int = 0, batch: int = 64, device="cuda:0", l
             continue
         u = torch.zeros_like(f)
         # training targets: 1e-8 is far below what the network can reproduce; a batch whose
-        # slowest problem misses it within the cycle budget keeps the problems that reached it
+        # slowest problem misses it within the cycle budget keeps the problems that reached it.
+        # Problems on which the cycle diverges (a few percent of the ellipse unions: concave
+        # corners, coarse components without a Dirichlet condition) have no target: the batch
+        # is solved again without them.
         info = solver.solve(f, g, u, tol=1e-8, check=False)
+        while info["status"] == gm.MG_EDIVERGED:
+            B0 = len(probs)
+            fmax = f.reshape(B0, -1).abs().max(dim=1).values.cpu().numpy()
+            rel = solver.residual(f, g, u).max(axis=1) / np.maximum(fmax, 1e-300)
+            keep = [p.seed for p, r in zip(probs, rel) if r < 1.0]
+            solver.close()
+            rejected += B0 - len(keep)
+            if not keep or len(keep) == B0:
+                solver = None
+                break
+            solver, f, g, probs = build_batch(keep, device=device)
+            u = torch.zeros_like(f)
+            info = solver.solve(f, g, u, tol=1e-8, check=False)
+        if solver is None:
+            continue
         if info["status"] not in (gm.MG_OK, gm.MG_ENOCONV):
             raise gm.GhostMGError(info["status"], "mg_solve")
         B0 = len(probs)
@@ -289,21 +307,29 @@ def evaluate_each(net, probs, f, g, tol=1e-10, device="cuda:0", reps=3):
     """Cycles and time to the tolerance of every problem solved on its own (a batch solve
     runs until its slowest problem converges): FP64 and FP32 defect correction from the zero
     guess, FP32 defect correction and FP64 from the learned guess (network inference
-    included in the time).  Returns per-problem lists and their means / medians."""
+    included in the time).  Returns per-problem lists and their means / medians; problems on
+    which the zero-guess FP64 cycle does not reach the tolerance are listed under "failed"
+    (seed, status) and left out of the lists."""
     from workloads import ellipses as el
 
     nn = (N_FINE + 1) ** 2
     rows = {k: [] for k in ("zero64_cycles", "zero64_ms", "zero_dc_cycles", "zero_dc_ms",
                             "learned_dc_cycles", "learned_dc_ms", "learned64_cycles",
                             "learned64_ms", "guess_rel_error")}
+    failed = []
     for i, p in enumerate(probs):
         phi = el.nodal_phi(p, N_FINE, device=device)
         fi = f[i * nn:(i + 1) * nn].contiguous()
         gi = g[i * nn:(i + 1) * nn].contiguous()
         s64 = gm.Solver(phi, [p.rule], gm.mg_grid_default(2, N_FINE, N_COARSE, max_cycles=1000))
+        u = torch.zeros_like(fi)
+        first = s64.solve(fi, gi, u, tol=tol, check=False)
+        if first["status"] != gm.MG_OK:
+            failed.append((p.seed, first["status"]))
+            s64.close()
+            continue
         sdc = gm.Solver(phi, [p.rule], gm.mg_grid_default(2, N_FINE, N_COARSE, max_cycles=1000,
                                                           precision=gm.MG_FP32_DC))
-        u = torch.zeros_like(fi)
 
         def timed(fn):
             best, info = None, None
@@ -357,6 +383,7 @@ def evaluate_each(net, probs, f, g, tol=1e-10, device="cuda:0", reps=3):
     for k, v in list(res.items()):
         res[k + "_mean"] = float(np.mean(v))
         res[k + "_median"] = float(np.median(v))
+    res["failed"] = failed
     return res
 
 

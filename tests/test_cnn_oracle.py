@@ -54,3 +54,27 @@ def test_gradients_match_finite_differences():
         fd = (co.loss_and_grads(pp, x, tgt, mask, dils)[0] -
               co.loss_and_grads(pm, x, tgt, mask, dils)[0]) / (2 * eps)
         assert abs(fd - grads[li][1][0]) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    one = 1.0
+    ulp = 2.0 ** -7  # BF16 has 8 significand bits
+    vals = np.array([one, one + ulp / 4, one + ulp / 2, one + 3 * ulp / 2, one + 0.75 * ulp,
+                     -3.0 - 2 * ulp, 0.0])
+    got = co.bf16(vals)
+    # ties go to the even significand: 1 + ulp/2 -> 1, 1 + 3 ulp / 2 -> 1 + 2 ulp
+    want = np.array([one, one, one, one + 2 * ulp, one + ulp, -3.0 - 2 * ulp, 0.0])
+    assert np.array_equal(got, want), (got, want)
+    assert np.array_equal(co.bf16(got), got)
+
+
+def test_adam_step_closed_form():
+    """First step: m = (1 - b1) g, v = (1 - b2) g^2, so the bias-corrected step is
+    lr g / (|g| + eps): -lr sign(g) up to eps."""
+    g = np.array([0.5, -2.0, 1e-3])
+    w, m, v = co.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01)
+    assert np.allclose(w, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+    w2, m2, v2 = co.adam(w, g, m, v, 2, lr=0.01)
+    mh = (0.9 * m + 0.1 * g) / (1 - 0.81)
+    vh = (0.999 * v + 0.001 * g * g) / (1 - 0.999 ** 2)
+    assert np.allclose(w2, w - 0.01 * mh / (np.sqrt(vh) + 1e-8), rtol=1e-12, atol=0)

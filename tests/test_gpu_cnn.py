@@ -1,5 +1,6 @@
 """GPU parity of the learned-guess kernels (BF16 MFMA, FP32 accumulation) with the FP64
-numpy reference on the same BF16-rounded inputs."""
+numpy reference on the same BF16-rounded inputs: convolutions, the loss, the gradients of
+every layer element by element at the training shape, and Adam."""
 import numpy as np
 import pytest
 
@@ -103,3 +104,78 @@ def test_training_reduces_loss():
         losses.append(out[0].item())
         net.adam(net.backward(dy, B, H, W), lr=3e-3)
     assert losses[-1] < 0.5 * losses[0], losses[::10]
+
+
+def test_gradients_elementwise_at_training_shape():
+    """Weight and bias gradients of every layer, element by element, at the training shape
+    (64 problems of 65 x 65 nodes, the 4 -> 32 -> 32 -> 32 -> 32 -> 1 network) against the
+    FP64 reference with BF16 rounding at the points where the kernels store BF16 (weights,
+    hidden activations, loss gradient, data gradients): the remaining differences are FP32
+    accumulation and the rare BF16 rounding decision it flips."""
+    from paper_1111_0983_amd import cnn
+    rng = np.random.default_rng(11)
+    B, H, W = 64, 65, 65
+    net = cnn.GuessNet(seed=5, device=DEV)
+    cin, cout, _ = net.layers[-1]
+    net.w[-1].copy_(torch.from_numpy(rng.normal(0.0, (2.0 / (9 * cin)) ** 0.5,
+                                                size=cout * 9 * cin).astype(np.float32)))
+    for b in net.b:
+        b.copy_(torch.from_numpy(rng.normal(0.0, 0.05, size=b.numel()).astype(np.float32)))
+    net.repack()
+    x = _rounded(rng.normal(size=(B, H, W, 4)))
+    tgt = rng.normal(size=(B, H, W)).astype(np.float32).astype(np.float64)
+    mask = (rng.uniform(size=(B, H, W)) > 0.3).astype(np.float64)
+    xd = _bf(_to_nhwc_padded(x, 8)).to(DEV).reshape(-1)
+    pred = net.forward(xd, B, H, W)
+    out, dy = cnn.loss(pred, torch.from_numpy(tgt.astype(np.float32)).to(DEV).reshape(-1),
+                       torch.from_numpy(mask.astype(np.float32)).to(DEV).reshape(-1))
+    grads = net.backward(dy, B, H, W)
+    params = []
+    for (ci, co_, _), w, b in zip(net.layers, net.w, net.b):
+        params.append((w.cpu().numpy().astype(np.float64).reshape(co_, 3, 3, ci),
+                       b.cpu().numpy().astype(np.float64)))
+    dils = [d for _, _, d in net.layers]
+    loss, rgrads, rpred = co.loss_and_grads(params, x, tgt, mask, dils, bf16_points=True)
+    assert abs(out[0].item() - loss) <= 1e-4 * loss
+    gp = pred.cpu().numpy().reshape(B, H, W)
+    assert np.abs(gp - rpred).max() <= 2e-3 * np.abs(rpred).max()
+    L = len(net.layers)
+    errs = []
+    for i, ((dw, db), (rdw, rdb)) in enumerate(zip(grads, rgrads)):
+        ci, co_, _ = net.layers[i]
+        gw = dw.cpu().numpy().reshape(co_, 3, 3, ci)
+        gb = db.cpu().numpy()
+        ew = np.abs(gw - rdw) / (np.abs(rdw) + 1e-2 * np.abs(rdw).max())
+        eb = np.abs(gb - rdb) / (np.abs(rdb) + 1e-2 * np.abs(rdb).max())
+        print(f"layer {i}: max per-weight error {ew.max():.2e} (median {np.median(ew):.1e}), "
+              f"bias {eb.max():.2e}")
+        errs.append((i, ew.max(), eb.max()))
+    for i, e_w, e_b in errs:
+        # the gradient of layer i passes through L - i BF16-rounded stages (the loss gradient
+        # and one data gradient per later layer); each can differ by one BF16 rounding step
+        # (2^-7 relative) where FP32 accumulation flips a rounding decision
+        bound = (L - i) * 2.0 ** -7
+        assert e_w <= bound and e_b <= bound, (i, e_w, e_b, bound)
+
+
+def test_adam_matches_reference():
+    from paper_1111_0983_amd import cnn
+    rng = np.random.default_rng(3)
+    n = 10_000
+    w = rng.normal(size=n).astype(np.float32)
+    m = np.zeros(n)
+    v = np.zeros(n)
+    wr = w.astype(np.float64)
+    wd = torch.from_numpy(w).to(DEV)
+    md = torch.zeros(n, dtype=torch.float32, device=DEV)
+    vd = torch.zeros(n, dtype=torch.float32, device=DEV)
+    for t in range(1, 6):
+        g = rng.normal(size=n).astype(np.float32)
+        gd = torch.from_numpy(g).to(DEV)
+        cnn._check(cnn._lib.cnn_adam(cnn._p(wd), cnn._p(gd), cnn._p(md), cnn._p(vd), n, 1e-3,
+                                     0.9, 0.999, 1e-8, t, None), "cnn_adam")
+        wr, m, v = co.adam(wr, g.astype(np.float64), m, v, t, 1e-3)
+    torch.cuda.synchronize()
+    got = wd.cpu().numpy().astype(np.float64)
+    # FP32 state and arithmetic against FP64: the step is O(lr), its rounding O(lr 1e-7)
+    assert np.abs(got - wr).max() <= 1e-6, np.abs(got - wr).max()
