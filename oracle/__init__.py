@@ -57,7 +57,7 @@ class _Grid(ctypes.Structure):
                 ("hi", ctypes.c_double), ("n_coarse", ctypes.c_int), ("nu1", ctypes.c_int),
                 ("nu2", ctypes.c_int), ("gamma", ctypes.c_int), ("lam", ctypes.c_int),
                 ("delta_h", ctypes.c_double), ("cD", ctypes.c_double), ("cN", ctypes.c_double),
-                ("ordering", ctypes.c_int), ("split", ctypes.c_int)]
+                ("ordering", ctypes.c_int), ("split", ctypes.c_int), ("smoother", ctypes.c_int)]
 
 
 class _Rule(ctypes.Structure):
@@ -97,6 +97,8 @@ def _load():
         _lib.orc_defect.argtypes = [vp, ctypes.c_int, dp, dp, dp, dp]
         _lib.orc_relax.argtypes = [vp, ctypes.c_int, dp, dp, ctypes.c_int]
         _lib.orc_extend.argtypes = [vp, ctypes.c_int, dp]
+        _lib.orc_boundary_step.argtypes = [vp, ctypes.c_int, ctypes.c_int64, dp, dp, ctypes.c_int]
+        _lib.orc_smoothing.argtypes = [vp, dp, ctypes.c_int, dp]
         _lib.orc_restrict.argtypes = [vp, ctypes.c_int, dp, dp]
         _lib.orc_prolong.argtypes = [vp, ctypes.c_int, dp, dp]
         _lib.orc_coarse_solve.argtypes = [vp, dp, dp]
@@ -126,7 +128,7 @@ def default_grid(dim: int, n: int, n_coarse: int, **kw) -> dict:
     mu_N dt = 0.9 * 2h / (3 sqrt(d)) (Sec. 2.3, Sec. 1.1 for d = 1)."""
     g = dict(dim=dim, n=n, lo=-1.0, hi=1.0, n_coarse=n_coarse, nu1=2, nu2=1, gamma=1,
              lam=5, delta_h=3.0, cD=0.9, cN=0.9 * 2.0 / (3.0 * np.sqrt(dim)), ordering=1,
-             split=1)
+             split=1, smoother=0)
     g.update(kw)
     return g
 
@@ -242,6 +244,19 @@ class Oracle:
         assert u.dtype == np.float64 and u.flags.c_contiguous
         _lib.orc_relax(self._h, l, _p(u), _p(self._arr(rhs, l)), band_only)
 
+    def boundary_step(self, l, P, u, rhs, kind):
+        """In place: one Kaczmarz step (kind 1) or one block relaxation (kind 2) at node P of
+        level l (Sec. 3.3); returns the oracle status (EGEOM: singular block)."""
+        assert u.dtype == np.float64 and u.flags.c_contiguous
+        return _lib.orc_boundary_step(self._h, l, int(P), _p(u), _p(self._arr(rhs, l)), kind)
+
+    def smoothing(self, u0, iters):
+        """Smoothing factors mu^(m) of the relaxation alone on the homogeneous problem."""
+        u = np.ascontiguousarray(u0, dtype=np.float64).ravel().copy()
+        hist = np.zeros(iters)
+        _lib.orc_smoothing(self._h, _p(u), int(iters), _p(hist))
+        return hist
+
     def extend(self, l, r):
         assert r.dtype == np.float64 and r.flags.c_contiguous
         _lib.orc_extend(self._h, l, _p(r))
@@ -323,4 +338,4 @@ class Oracle:
 
 
 _Grid._fields_names = ["dim", "n", "lo", "hi", "n_coarse", "nu1", "nu2", "gamma", "lam",
-                       "delta_h", "cD", "cN", "ordering", "split"]
+                       "delta_h", "cD", "cN", "ordering", "split", "smoother"]

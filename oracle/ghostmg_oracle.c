@@ -66,6 +66,10 @@ typedef struct {
   int split;        /* 0: outside pass over all of D_h - Omega_h (the paper's composite
                        restriction); 1: Dirichlet- and Neumann-labelled outside nodes are
                        extended and restricted separately */
+  int smoother;     /* boundary relaxation (Sec. 3.3): 0 = the paper's ghost relaxation with
+                       lambda extra sweeps; 1 = lambda Kaczmarz sweeps over the band after an
+                       interior Gauss-Seidel sweep; 2 = block relaxation of the band after a
+                       Gauss-Seidel sweep of the interior off the band (GS-LEX only) */
 } orc_grid;
 
 /* Dirichlet iff a.B + c > 0 (strict) or >= 0 (not strict), evaluated at the closest point B. */
@@ -808,6 +812,7 @@ static void* setup_impl(const double* phi, const orc_bc_rule* bc, orc_bc_fn fn, 
   if (!phi || !g) return NULL;
   if (g->dim < 1 || g->dim > 3 || g->n < 2 || g->n_coarse < 2 || g->hi <= g->lo) return NULL;
   if (g->gamma < 1 || g->gamma > 2 || g->nu1 < 0 || g->nu2 < 0 || g->lambda < 0) return NULL;
+  if (g->smoother < 0 || g->smoother > 2 || (g->smoother != 0 && g->ordering != 0)) return NULL;
   int L = 0;
   int nn_ = g->n;
   while (nn_ > g->n_coarse) {
@@ -1002,8 +1007,158 @@ static void relax_pass(ohandle* H, int l, double* u, const double* rhs, int band
   }
 }
 
-/* one relaxation followed by lambda extra sweeps on the boundary band (Sec. 3.2) */
+/* Coefficients of the equation of node P of Eq. (discr) (interior: -Delta_h u = f, written
+ * as (2d u_P - sum of the neighbours) / h^2; ghost: L_h u = g): up to 3^d nodes and weights;
+ * returns their number. */
+static int row_of(const ohandle* H, const olev* L, int64_t P, int64_t* nd, double* w) {
+  const int d = H->g.dim;
+  if (L->cls[P] == ORC_IN) {
+    const double h2 = L->h * L->h;
+    int m = 0;
+    nd[m] = P;
+    w[m++] = 2.0 * d / h2;
+    for (int a = 0; a < d; ++a) {
+      nd[m] = P - L->st[a];
+      w[m++] = -1.0 / h2;
+      nd[m] = P + L->st[a];
+      w[m++] = -1.0 / h2;
+    }
+    return m;
+  }
+  const int64_t g = L->gid[P];
+  int m = 0;
+  for (int t = 0; t < H->K; ++t) {
+    if (L->gwn[H->K * g + t] < 0) continue;
+    nd[m] = L->gwn[H->K * g + t];
+    w[m++] = L->gw[H->K * g + t];
+  }
+  return m;
+}
+
+/* Kaczmarz step on the equation of node P (Sec. 3.3): u <- u + (f_P - <l_P, u>) / |l_P|^2 l_P,
+ * the orthogonal projection of u onto the hyperplane of that equation. */
+static void kaczmarz_row(const ohandle* H, const olev* L, int64_t P, double* u,
+                         const double* rhs) {
+  int64_t nd[27];
+  double w[27];
+  const int m = row_of(H, L, P, nd, w);
+  double dot = 0.0, n2 = 0.0;
+  for (int i = 0; i < m; ++i) {
+    dot += w[i] * u[nd[i]];
+    n2 += w[i] * w[i];
+  }
+  if (!(n2 > 0.0)) return;
+  const double a = (rhs[P] - dot) / n2;
+  for (int i = 0; i < m; ++i) u[nd[i]] += a * w[i];
+}
+
+/* Block relaxation at node P (Sec. 3.3): the unknowns of St_P (interior P: its 3^d
+ * neighbourhood within Omega_h u Gamma_h; ghost P: its stencil St_G) take the values that
+ * satisfy their own equations with every other unknown fixed, u_1 = A_11^{-1} (f_1 - A_12 u_2);
+ * dense elimination with partial pivoting; a singular block is left unchanged.  Returns 0 when
+ * it was solved. */
+static int block_solve(const ohandle* H, const olev* L, int64_t P, double* u, const double* rhs) {
+  const int d = H->g.dim;
+  int64_t blk[27];
+  int m = 0;
+  if (L->cls[P] == ORC_IN) {
+    int j[3];
+    to_j(L, d, P, j);
+    int nb = 1;
+    for (int a = 0; a < d; ++a) nb *= 3;
+    for (int o = 0; o < nb; ++o) {
+      int jj[3] = {j[0], j[1], j[2]}, oo = o;
+      for (int a = 0; a < d; ++a) {
+        jj[a] += oo % 3 - 1;
+        oo /= 3;
+      }
+      if (!in_box(L, d, jj)) continue;
+      const int64_t Q = to_idx(L, d, jj);
+      if (L->cls[Q] != ORC_OUT) blk[m++] = Q;
+    }
+  } else {
+    const int64_t g = L->gid[P];
+    for (int t = 0; t < H->K; ++t)
+      if (L->gwn[H->K * g + t] >= 0) blk[m++] = L->gwn[H->K * g + t];
+  }
+  double A[27][28];
+  for (int i = 0; i < m; ++i) {
+    int64_t nd[27];
+    double w[27];
+    const int q = row_of(H, L, blk[i], nd, w);
+    for (int c = 0; c <= m; ++c) A[i][c] = 0.0;
+    A[i][m] = rhs[blk[i]];
+    for (int k = 0; k < q; ++k) {
+      int c = -1;
+      for (int b = 0; b < m; ++b)
+        if (blk[b] == nd[k]) c = b;
+      if (c >= 0)
+        A[i][c] += w[k];
+      else
+        A[i][m] -= w[k] * u[nd[k]];
+    }
+  }
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    for (int i = k + 1; i < m; ++i)
+      if (fabs(A[i][k]) > fabs(A[p][k])) p = i;
+    if (A[p][k] == 0.0) return 1;
+    if (p != k)
+      for (int c = 0; c <= m; ++c) {
+        const double t = A[k][c];
+        A[k][c] = A[p][c];
+        A[p][c] = t;
+      }
+    for (int i = k + 1; i < m; ++i) {
+      const double f = A[i][k] / A[k][k];
+      for (int c = k; c <= m; ++c) A[i][c] -= f * A[k][c];
+    }
+  }
+  double x[27];
+  for (int i = m - 1; i >= 0; --i) {
+    double t = A[i][m];
+    for (int c = i + 1; c < m; ++c) t -= A[i][c] * x[c];
+    x[i] = t / A[i][i];
+  }
+  for (int i = 0; i < m; ++i) u[blk[i]] = x[i];
+  return 0;
+}
+
+/* nodes in GS-LEX order (x slowest, then y, then z; Sec. 2.4), as a callback walk */
+#define FOR_LEX(L, d, P)                                                   \
+  for (int64_t i0_ = 0; i0_ < (L)->np; ++i0_)                              \
+    for (int64_t i1_ = 0; i1_ < ((d) > 1 ? (L)->np : 1); ++i1_)            \
+      for (int64_t i2_ = 0; i2_ < ((d) > 2 ? (L)->np : 1); ++i2_)          \
+        for (int64_t P = i0_ + (L)->st[1] * i1_ + (L)->st[2] * i2_, once_ = 1; once_; once_ = 0)
+
+/* one relaxation followed by lambda extra sweeps on the boundary band (Sec. 3.2); or one of
+ * the two alternatives of Sec. 3.3 that the paper compares it with: a Gauss-Seidel sweep of
+ * the interior followed by lambda Kaczmarz sweeps over the band (ghosts and interior nodes
+ * within delta of the boundary), or a Gauss-Seidel sweep of the interior off the band
+ * followed by one block relaxation of every band node */
 static void relax(ohandle* H, int l, double* u, const double* rhs) {
+  olev* L = &H->lev[l];
+  const int d = H->g.dim;
+  if (H->g.smoother == 1) {
+    FOR_LEX(L, d, P) {
+      if (L->cls[P] == ORC_IN) relax_interior(H, L, P, u, rhs);
+    }
+    for (int k = 0; k < H->g.lambda; ++k) {
+      FOR_LEX(L, d, P) {
+        if (L->band[P]) kaczmarz_row(H, L, P, u, rhs);
+      }
+    }
+    return;
+  }
+  if (H->g.smoother == 2) {
+    FOR_LEX(L, d, P) {
+      if (L->cls[P] == ORC_IN && !L->band[P]) relax_interior(H, L, P, u, rhs);
+    }
+    FOR_LEX(L, d, P) {
+      if (L->band[P]) (void)block_solve(H, L, P, u, rhs);
+    }
+    return;
+  }
   relax_pass(H, l, u, rhs, 0);
   for (int k = 0; k < H->g.lambda; ++k) relax_pass(H, l, u, rhs, 1);
 }
@@ -1259,6 +1414,41 @@ int orc_relax(void* h, int l, double* u, const double* rhs, int band_only) {
     relax(H, l, u, rhs);
   else
     relax_pass(H, l, u, rhs, band_only);
+  return ORC_OK;
+}
+
+/* One Kaczmarz step (kind 1) or one block relaxation (kind 2) at node P of level l. */
+int orc_boundary_step(void* h, int l, int64_t P, double* u, const double* rhs, int kind) {
+  ohandle* H = (ohandle*)h;
+  if (l < 0 || l > H->L) return ORC_EINVAL;
+  const olev* L = &H->lev[l];
+  if (P < 0 || P >= L->nn || L->cls[P] == ORC_OUT) return ORC_EINVAL;
+  if (kind == 1) {
+    kaczmarz_row(H, L, P, u, rhs);
+    return ORC_OK;
+  }
+  if (kind == 2) return block_solve(H, L, P, u, rhs) ? ORC_EGEOM : ORC_OK;
+  return ORC_EINVAL;
+}
+
+/* Smoothing factor of Sec. 3.3: the relaxation alone (no coarse grid) on the homogeneous
+ * problem from u, mu^(m) = ||r^(m)||_inf / ||r^(m-1)||_inf for m = 1..iters (in hist). */
+int orc_smoothing(void* h, double* u, int iters, double* hist) {
+  ohandle* H = (ohandle*)h;
+  olev* F = &H->lev[0];
+  double* zero = (double*)calloc((size_t)F->nn, sizeof(double));
+  if (!zero) return ORC_ENOMEM;
+  double ni, ngh;
+  defect(H, 0, u, zero, F->r, &ni, &ngh);
+  double prev = ni > ngh ? ni : ngh;
+  for (int m = 0; m < iters; ++m) {
+    relax(H, 0, u, zero);
+    defect(H, 0, u, zero, F->r, &ni, &ngh);
+    const double rn = ni > ngh ? ni : ngh;
+    hist[m] = rn / prev;
+    prev = rn;
+  }
+  free(zero);
   return ORC_OK;
 }
 
