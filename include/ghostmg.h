@@ -65,6 +65,13 @@ typedef struct {
   int inner_cycles;   /* FP32 cycles per defect-correction step (MG_FP32_DC) */
   int max_cycles;     /* cycle budget of mg_solve (FP64 cycles, or FP32 cycles in DC) */
   int batch;          /* independent problems solved together (>= 1) */
+  int smoother;       /* boundary relaxation (Sec. 3.3): 0 = ghost relaxation with lambda
+                         extra band sweeps (the paper's method); 1 = lambda Kaczmarz sweeps
+                         over the band after the interior sweep; 2 = one block relaxation of
+                         every band node after a sweep of the interior off the band (2D).
+                         1 and 2 sweep the band colour by colour (colour (x mod M) + M (y mod M)
+                         + M^2 (z mod M), M = 5 / 7), one workgroup per problem: meant for the
+                         comparison of Sec. 3.3 on small grids */
 } mg_grid;
 
 /* Dirichlet at a ghost iff a . B + c > 0 (strict) or >= 0 (not strict), B its closest
@@ -137,6 +144,16 @@ int mg_solve(mg_handle_t h, const double* f, const double* g, double* u, double 
 
 /* Exactly ncycles cycles from u, no tolerance test (iterate-level checks). */
 int mg_cycles(mg_handle_t h, const double* f, const double* g, double* u, int ncycles);
+
+/* Warm start for a moving domain (a sequence of problems on one grid): u (device, batch *
+ * (n+1)^dim FP64, in place) holds the solution computed with handle `prev`; every node that
+ * is an unknown of h but was not one of prev (a node the boundary has moved over, typically
+ * a new ghost) takes the mean of the linear extrapolations 2 u(Q1) - u(Q2) from the axis
+ * directions where Q1, Q2 (one and two nodes inward) are unknowns of both handles, or the
+ * mean of such axis neighbours, or 0.  Other values are kept.  Without it the new nodes hold
+ * 0 and their interior neighbours' rows start with defects of order u / h^2.  Both handles
+ * must have the same grid and batch (MG_EINVAL otherwise). */
+int mg_warm_start(mg_handle_t h, mg_handle_t prev, double* u);
 
 /* Convergence factor of the cycle (Sec. 3): the homogeneous problem (f = g = 0) iterated
  * from u0 (device, batch * (n+1)^dim FP64, read only), rho^(m) = ||r^(m)||_inf /

@@ -68,8 +68,12 @@ typedef struct {
                        extended and restricted separately */
   int smoother;     /* boundary relaxation (Sec. 3.3): 0 = the paper's ghost relaxation with
                        lambda extra sweeps; 1 = lambda Kaczmarz sweeps over the band after an
-                       interior Gauss-Seidel sweep; 2 = block relaxation of the band after a
-                       Gauss-Seidel sweep of the interior off the band (GS-LEX only) */
+                       interior sweep; 2 = block relaxation of the band after a sweep of the
+                       interior off the band.  With ordering 0 every sweep is lexicographic;
+                       with ordering 1 the interior sweeps are red-black and the band is swept
+                       colour by colour (colour (x mod M) + M (y mod M) + M^2 (z mod M), M = 5
+                       for Kaczmarz, 7 for blocks: no two rows or blocks of a colour touch the
+                       same unknowns, so a colour may be swept in any order) */
 } orc_grid;
 
 /* Dirichlet iff a.B + c > 0 (strict) or >= 0 (not strict), evaluated at the closest point B. */
@@ -812,7 +816,7 @@ static void* setup_impl(const double* phi, const orc_bc_rule* bc, orc_bc_fn fn, 
   if (!phi || !g) return NULL;
   if (g->dim < 1 || g->dim > 3 || g->n < 2 || g->n_coarse < 2 || g->hi <= g->lo) return NULL;
   if (g->gamma < 1 || g->gamma > 2 || g->nu1 < 0 || g->nu2 < 0 || g->lambda < 0) return NULL;
-  if (g->smoother < 0 || g->smoother > 2 || (g->smoother != 0 && g->ordering != 0)) return NULL;
+  if (g->smoother < 0 || g->smoother > 2) return NULL;
   int L = 0;
   int nn_ = g->n;
   while (nn_ > g->n_coarse) {
@@ -1136,9 +1140,44 @@ static int block_solve(const ohandle* H, const olev* L, int64_t P, double* u, co
  * the interior followed by lambda Kaczmarz sweeps over the band (ghosts and interior nodes
  * within delta of the boundary), or a Gauss-Seidel sweep of the interior off the band
  * followed by one block relaxation of every band node */
+static int colour_of(const olev* L, int d, int64_t P, int M) {
+  int j[3] = {0, 0, 0};
+  to_j(L, d, P, j);
+  int c = 0;
+  for (int a = d - 1; a >= 0; --a) c = c * M + j[a] % M;
+  return c;
+}
+
+/* interior red-black sweep (ordering 1) over every interior node, or over those off the band */
+static void rb_interior(ohandle* H, olev* L, double* u, const double* rhs, int off_band) {
+  const int d = H->g.dim;
+  for (int colour = 0; colour < 2; ++colour)
+    for (int64_t P = 0; P < L->nn; ++P) {
+      if (L->cls[P] != ORC_IN || (off_band && L->band[P])) continue;
+      if (parity(L, d, P) != colour) continue;
+      relax_interior(H, L, P, u, rhs);
+    }
+}
+
 static void relax(ohandle* H, int l, double* u, const double* rhs) {
   olev* L = &H->lev[l];
   const int d = H->g.dim;
+  if (H->g.smoother != 0 && H->g.ordering == 1) {
+    const int kac = H->g.smoother == 1, M = kac ? 5 : 7;
+    int nc = 1;
+    for (int a = 0; a < d; ++a) nc *= M;
+    rb_interior(H, L, u, rhs, !kac);
+    for (int k = 0; k < (kac ? H->g.lambda : 1); ++k)
+      for (int c = 0; c < nc; ++c)
+        for (int64_t P = 0; P < L->nn; ++P) {
+          if (!L->band[P] || colour_of(L, d, P, M) != c) continue;
+          if (kac)
+            kaczmarz_row(H, L, P, u, rhs);
+          else
+            (void)block_solve(H, L, P, u, rhs);
+        }
+    return;
+  }
   if (H->g.smoother == 1) {
     FOR_LEX(L, d, P) {
       if (L->cls[P] == ORC_IN) relax_interior(H, L, P, u, rhs);

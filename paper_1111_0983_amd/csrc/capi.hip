@@ -120,6 +120,37 @@ int upload_level(mg_handle_s* H, int l) {
       }
     }
   }
+  if (H->grid.smoother != 0 && l < H->L) {
+    // band nodes and ghosts of every problem by colour (x mod M) + M (y mod M) + M^2 (z mod M)
+    const int M = H->grid.smoother == 1 ? 5 : 7;
+    int ncol = 1;
+    for (int a = 0; a < H->dim; ++a) ncol *= M;
+    const Geo& g = S.g;
+    auto colour = [&](int32_t v) {
+      const int64_t loc = v % g.npp;
+      const int64_t z = H->dim == 3 ? loc / g.st[2] : 0, rem = loc - z * (H->dim == 3 ? g.st[2] : 0);
+      const int64_t y = rem / g.st[1], x = rem - y * g.st[1];
+      return (int)(x % M + M * (y % M) + (int64_t)M * M * (z % M));
+    };
+    std::vector<std::vector<int2>> by(H->batch * (size_t)ncol);
+    auto add = [&](int32_t v, int gid) {
+      by[(size_t)(v / g.npp) * ncol + colour(v)].push_back(make_int2(v, gid));
+    };
+    for (int32_t v : S.red) add(v, -1);
+    for (int32_t v : S.black) add(v, -1);
+    for (size_t i = 0; i < S.ghosts.size(); ++i) add(S.ghosts[i].node, (int)i);
+    std::vector<int2> list;
+    std::vector<int32_t> off;
+    for (size_t k = 0; k < by.size(); ++k) {
+      if (k % ncol == 0 && k) off.push_back((int32_t)list.size());
+      off.push_back((int32_t)list.size());
+      list.insert(list.end(), by[k].begin(), by[k].end());
+    }
+    off.push_back((int32_t)list.size());
+    L.alt_ncol = ncol;
+    if ((rc = upload(&L.alt_list, list))) return rc;
+    if ((rc = upload(&L.alt_off, off))) return rc;
+  }
   if (!S.et_node.empty()) {
     L.net = (int)S.et_node.size();
     if ((rc = upload(&L.et_node, S.et_node))) return rc;
@@ -485,7 +516,7 @@ int rho_impl(mg_handle_s* H, const double* u0, int max_cycles, double rtol, doub
 }
 
 void free_level(DevLevel& L) {
-  void* ptrs[] = {L.bc_hdr, L.bc_data, L.z64, L.z32, L.band_list, L.ec_hdr, L.ec_data,
+  void* ptrs[] = {L.alt_list, L.alt_off, L.bc_hdr, L.bc_data, L.z64, L.z32, L.band_list, L.ec_hdr, L.ec_data,
                   L.et_node, L.et_off, L.et_src, L.et_wt, L.rcls, L.gw,
                   L.cls, L.phi, L.tiles, L.ghosts, L.ghost_off, L.red, L.black, L.red_off, L.black_off,
                   L.ext, L.ext_merged, L.ext_off, L.dag_off, L.dag_start, L.rcode, L.u64[0],
@@ -598,7 +629,8 @@ int setup_impl(const double* phi, const mg_bc_rule* bc, mg_bc_fn fn, void* ctx,
   if ((G.dim != 2 && G.dim != 3) || G.n < 4 || G.n_coarse < 2 || !(G.hi > G.lo) || G.batch < 1 ||
       G.nu1 < 0 || G.nu2 < 0 || G.gamma < 1 || G.gamma > 2 || G.lambda < 0 || G.max_cycles < 0 ||
       (G.precision != MG_FP64 && G.precision != MG_FP32_DC) ||
-      (G.precision == MG_FP32_DC && G.inner_cycles < 1))
+      (G.precision == MG_FP32_DC && G.inner_cycles < 1) || G.smoother < 0 || G.smoother > 2 ||
+      (G.smoother == 2 && G.dim != 2))
     return MG_EINVAL;
   int L = 0, nn = G.n;
   while (nn > G.n_coarse) {
@@ -647,7 +679,8 @@ int setup_impl(const double* phi, const mg_bc_rule* bc, mg_bc_fn fn, void* ctx,
       // one launch where possible)
       bool built = false;
       const int P = 3 + 3 * H->grid.lambda;
-      for (int R = P; R >= 3 && !built; R -= 3)
+      // the comparison relaxations sweep the band on their own (no chunks)
+      for (int R = P; R >= 3 && !built && H->grid.smoother == 0; R -= 3)
         if (P % R == 0 && P / R <= 7)
           built = build_band_chunks(H, l, kChunkOwn * (H->dim == 2 ? 1 : 2),
                                     H->dim == 2 ? kChunkRedundancy2D : kChunkRedundancy3D, R);
@@ -775,6 +808,20 @@ int mg_rho(mg_handle_t h, const double* u0, int max_cycles, double rtol, double*
       h->grid.precision != MG_FP64)
     return MG_EINVAL;
   return rho_impl(h, u0, max_cycles, rtol, rho, hist, ncycles);
+}
+
+int mg_warm_start(mg_handle_t h, mg_handle_t prev, double* u) {
+  if (!h || !prev || !u || h->dim != prev->dim || h->batch != prev->batch ||
+      h->grid.n != prev->grid.n || h->grid.lo != prev->grid.lo || h->grid.hi != prev->grid.hi)
+    return MG_EINVAL;
+  hipStream_t s = stream_of(h);
+  // the previous hierarchy's work must be done before its classes are read on this stream
+  if (prev->stream != s) HIP_TRY(hipStreamSynchronize(prev->stream));
+  if (h->dim == 2)
+    launch_warm_start<2>(h->dev[0], prev->dev[0], h->batch, u, s);
+  else
+    launch_warm_start<3>(h->dev[0], prev->dev[0], h->batch, u, s);
+  return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 
 int mg_residual(mg_handle_t h, const double* f, const double* g, const double* u, double* r,

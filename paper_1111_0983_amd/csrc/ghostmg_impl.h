@@ -214,6 +214,11 @@ struct DevLevel {
   int32_t *ext_off = nullptr, *dag_off = nullptr, *dag_start = nullptr;
   std::vector<int32_t> gdag_off;        // host copy for the per-DAG-level launches
   uint8_t* rcode = nullptr;
+  // boundary relaxations of the comparison (grid.smoother 1, 2): the band nodes and ghosts
+  // (node, ghost index or -1) by problem and colour; alt_off[p * (alt_ncol + 1) + c]
+  int alt_ncol = 0;
+  int2* alt_list = nullptr;
+  int32_t* alt_off = nullptr;
   // arrays [batch * npp]; the iterate has two buffers, a relaxation reads one and writes
   // the other
   double *u64[2] = {nullptr, nullptr}, *rhs64 = nullptr, *r64 = nullptr, *gtmp64 = nullptr;

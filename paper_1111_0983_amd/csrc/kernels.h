@@ -38,6 +38,7 @@ struct RelaxArgs {
   const T* uband;
   T h2, inv2d;
   int write_all;  // tiles also write band interior and ghost nodes (levels without chunks)
+  int skip_band;  // tiles leave the band interior nodes unrelaxed (block relaxation owns them)
   int nchunks, phases;
   // packed layout: chunk c's header at hdr[c * kBandHdr], offsets into data; fixed layout
   // (band_fixed_layout): chunk c's data at data + c * stride, the header is not read
@@ -132,6 +133,9 @@ void launch_pack(const DevLevel& L, const double* f, const double* g, const doub
                  double* rhs, double* u, hipStream_t s);
 template <int D>
 void launch_unpack(const DevLevel& L, int batch, const double* src, double* dst, hipStream_t s);
+template <int D>
+void launch_warm_start(const DevLevel& L, const DevLevel& Lprev, int batch, double* u,
+                       hipStream_t s);
 template <int D>
 void launch_dc_update(const DevLevel& L, double* u64, const float* u32, float* u32_zero,
                       hipStream_t s);

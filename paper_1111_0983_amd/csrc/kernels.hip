@@ -205,7 +205,8 @@ __device__ __forceinline__ void restrict_gather(const T* __restrict__ rf, int64_
 // of its row.  Nodes whose code is not an interior one (1, 3) are left alone.
 template <int D, typename T, int N, int HX, int HY, int O, int PAR>
 __device__ __forceinline__ void tile_colour_phase(T* su, const int8_t* sc, const T* sf, int FX,
-                                                  int FY, int SY, int SZ, T h2, T inv2d) {
+                                                  int FY, int SY, int SZ, T h2, T inv2d,
+                                                  int skip_band) {
   constexpr int K = (N + 255) / 256;
   int ui[K];
   int8_t cd[K];
@@ -225,14 +226,15 @@ __device__ __forceinline__ void tile_colour_phase(T* su, const int8_t* sc, const
     nb[k][1] = su[ui[k] + 1];
     nb[k][2] = su[ui[k] - SY];
     nb[k][3] = su[ui[k] + SY];
-    if (D == 3) {
+    if constexpr (D == 3) {
       nb[k][4] = su[ui[k] - SZ];
       nb[k][5] = su[ui[k] + SZ];
     }
   }
 #pragma unroll
   for (int k = 0; k < K; ++k)
-    if (cd[k] == 1 || cd[k] == 3) su[ui[k]] = interior_update<D, T>(cv[k], nb[k], fv[k], h2, inv2d);
+    if (cd[k] == 1 || (cd[k] == 3 && !skip_band))
+      su[ui[k]] = interior_update<D, T>(cv[k], nb[k], fv[k], h2, inv2d);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -459,9 +461,11 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   // colour, ghosts or outside nodes, which the phase leaves unchanged.
   constexpr int FXH = FX / 2, TXH = TX / 2;
   constexpr int NRED = FXH * FY * FZ, NBLK = TXH * TY * TZ;
-  tile_colour_phase<D, T, NRED, FXH, FY, 1, (D & 1)>(su, sc, sf, FX, FY, SY, SZ, a.h2, a.inv2d);
+  tile_colour_phase<D, T, NRED, FXH, FY, 1, (D & 1)>(su, sc, sf, FX, FY, SY, SZ, a.h2, a.inv2d,
+                                                     a.skip_band);
   __syncthreads();
-  tile_colour_phase<D, T, NBLK, TXH, TY, 2, 1>(su, sc, sf, FX, FY, SY, SZ, a.h2, a.inv2d);
+  tile_colour_phase<D, T, NBLK, TXH, TY, 2, 1>(su, sc, sf, FX, FY, SY, SZ, a.h2, a.inv2d,
+                                               a.skip_band);
   __syncthreads();
   // the block's nodes to uout: every code and value read before the first store
   constexpr int NST = TZ * TY * TX, KS = (NST + 255) / 256;
@@ -838,6 +842,207 @@ __global__ void __launch_bounds__(1024) k_band(BandArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------------------
+// the boundary relaxations the paper compares its own with (Sec. 3.3), one workgroup per
+// problem: the band (interior nodes within delta, and the ghosts) colour by colour, a
+// barrier between colours; no two rows (Kaczmarz) or blocks of a colour share an unknown, so
+// the threads of a colour never touch the same value
+// ---------------------------------------------------------------------------------------
+// the taps of a ghost's stencil St_G (every rung's template, also where a weight vanishes)
+template <int D>
+__device__ __forceinline__ uint32_t used_taps(const GhostRec& r) {
+  constexpr int K = Pow3<D>::value;
+  uint32_t m = 0;
+  if (r.rung <= 2) {
+    for (int t = 0; t < K; ++t) {
+      bool ok = true;
+      int tt = t;
+      for (int a = D - 1; a >= 0; --a) {
+        if (r.rung == 2 && tt % 3 == 2) ok = false;
+        tt /= 3;
+      }
+      if (ok) m |= 1u << t;
+    }
+  } else {
+    m |= 1u;
+    for (int a = 0; a < D; ++a) {
+      if (r.rung == 4 && a != r.axis) continue;
+      int ta = 1;
+      for (int c = D - 1; c > a; --c) ta *= 3;
+      m |= 1u << ta;
+    }
+  }
+  return m;
+}
+
+// the equation of one node of Eq. (discr) as (node, weight) pairs: interior -Delta_h u = f as
+// (2d u_P - sum of the neighbours) / h^2, ghost L_h u = g over its stencil; returns the count
+template <int D>
+__device__ __forceinline__ int node_row(int32_t P, int gid, const GhostRec* __restrict__ ghosts,
+                                        const double* __restrict__ gw, const Geo& g, double ih2,
+                                        int64_t* nd, double* w) {
+  constexpr int K = Pow3<D>::value;
+  if (gid < 0) {
+    nd[0] = P;
+    w[0] = 2.0 * D * ih2;
+    int m = 1;
+    for (int a = 0; a < D; ++a) {
+      nd[m] = P - g.st[a];
+      w[m++] = -ih2;
+      nd[m] = P + g.st[a];
+      w[m++] = -ih2;
+    }
+    return m;
+  }
+  const GhostRec r = ghosts[gid];
+  const uint32_t used = used_taps<D>(r);
+  int m = 0;
+  for (int t = 0; t < K; ++t) {
+    if (!((used >> t) & 1u)) continue;
+    nd[m] = r.node + template_offset<D>(t, r.s, g.st);
+    w[m++] = gw[(int64_t)gid * K + t];
+  }
+  return m;
+}
+
+// lambda Kaczmarz sweeps: u <- u + (f_j - <l_j, u>) / |l_j|^2 l_j row by row (the orthogonal
+// projection onto the row's hyperplane), in FP64
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_band_kaczmarz(Geo g, const int2* __restrict__ list,
+                                                       const int32_t* __restrict__ off, int ncol,
+                                                       const GhostRec* __restrict__ ghosts,
+                                                       const double* __restrict__ gw, T* u,
+                                                       const T* __restrict__ rhs, int sweeps) {
+  constexpr int K = Pow3<D>::value;
+  const int32_t* o = off + (int64_t)blockIdx.x * (ncol + 1);
+  const double ih2 = 1.0 / (g.h * g.h);
+  for (int k = 0; k < sweeps; ++k)
+    for (int c = 0; c < ncol; ++c) {
+      for (int i = o[c] + (int)threadIdx.x; i < o[c + 1]; i += 256) {
+        const int2 e = list[i];
+        int64_t nd[K];
+        double w[K];
+        const int m = node_row<D>(e.x, e.y, ghosts, gw, g, ih2, nd, w);
+        double dot = 0.0, n2 = 0.0;
+        for (int q = 0; q < m; ++q) {
+          dot += w[q] * (double)u[nd[q]];
+          n2 += w[q] * w[q];
+        }
+        if (!(n2 > 0.0)) continue;
+        const double a = ((double)rhs[e.x] - dot) / n2;
+        for (int q = 0; q < m; ++q) u[nd[q]] = (T)((double)u[nd[q]] + a * w[q]);
+      }
+      __syncthreads();
+    }
+}
+
+// index of the ghost at node P among ghosts [lo, hi) (ordered by node), or -1
+__device__ __forceinline__ int find_ghost(const GhostRec* __restrict__ ghosts, int lo, int hi,
+                                          int64_t P) {
+  const int end = hi;
+  while (lo < hi) {
+    const int mid = (lo + hi) / 2;
+    if (ghosts[mid].node < P)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < end && ghosts[lo].node == P ? lo : -1;
+}
+
+// one block relaxation of every band node (2D): the unknowns of St_P (interior P: its 3 x 3
+// neighbourhood within Omega_h u Gamma_h; ghost P: St_G) take the values that satisfy their
+// own equations with every other unknown fixed (dense elimination with partial pivoting, in
+// FP64 in LDS; a singular block is left unchanged)
+constexpr int kBlockThreads = 64;
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) k_band_block(Geo g, const int2* __restrict__ list,
+                                                              const int32_t* __restrict__ off,
+                                                              int ncol,
+                                                              const GhostRec* __restrict__ ghosts,
+                                                              const int32_t* __restrict__ ghost_off,
+                                                              const double* __restrict__ gw,
+                                                              const int8_t* __restrict__ cls, T* u,
+                                                              const T* __restrict__ rhs) {
+  constexpr int MB = 9;
+  __shared__ double sA[kBlockThreads][MB][MB + 1];
+  double(*A)[MB + 1] = sA[threadIdx.x];
+  const int p = blockIdx.x;
+  const int32_t* o = off + (int64_t)p * (ncol + 1);
+  const int g0 = ghost_off[p], g1 = ghost_off[p + 1];
+  const double ih2 = 1.0 / (g.h * g.h);
+  const int64_t base = (int64_t)p * g.npp;
+  for (int c = 0; c < ncol; ++c) {
+    for (int i = o[c] + (int)threadIdx.x; i < o[c + 1]; i += kBlockThreads) {
+      const int2 e = list[i];
+      int64_t blk[MB];
+      int m = 0;
+      if (e.y < 0) {
+        const int64_t loc = e.x - base;
+        const int y = (int)(loc / g.st[1]), x = (int)(loc - y * g.st[1]);
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int xx = x + dx, yy = y + dy;
+            if (xx < 0 || yy < 0 || xx > g.n || yy > g.n) continue;
+            const int64_t Q = base + xx + g.st[1] * yy;
+            if (cls[Q] != 0) blk[m++] = Q;
+          }
+      } else {
+        const GhostRec r = ghosts[e.y];
+        const uint32_t used = used_taps<2>(r);
+        for (int t = 0; t < 9; ++t)
+          if ((used >> t) & 1u) blk[m++] = r.node + template_offset<2>(t, r.s, g.st);
+      }
+      for (int q = 0; q < m; ++q) {
+        const int gid = cls[blk[q]] == 2 ? find_ghost(ghosts, g0, g1, blk[q]) : -1;
+        int64_t nd[9];
+        double w[9];
+        const int nr = node_row<2>((int32_t)blk[q], gid, ghosts, gw, g, ih2, nd, w);
+        for (int cc = 0; cc <= m; ++cc) A[q][cc] = 0.0;
+        A[q][m] = (double)rhs[blk[q]];
+        for (int k = 0; k < nr; ++k) {
+          int col = -1;
+          for (int b = 0; b < m; ++b)
+            if (blk[b] == nd[k]) col = b;
+          if (col >= 0)
+            A[q][col] += w[k];
+          else
+            A[q][m] -= w[k] * (double)u[nd[k]];
+        }
+      }
+      bool singular = false;
+      for (int k = 0; k < m && !singular; ++k) {
+        int pv = k;
+        for (int r = k + 1; r < m; ++r)
+          if (fabs(A[r][k]) > fabs(A[pv][k])) pv = r;
+        if (A[pv][k] == 0.0) {
+          singular = true;
+          break;
+        }
+        if (pv != k)
+          for (int cc = 0; cc <= m; ++cc) {
+            const double t = A[k][cc];
+            A[k][cc] = A[pv][cc];
+            A[pv][cc] = t;
+          }
+        for (int r = k + 1; r < m; ++r) {
+          const double f = A[r][k] / A[k][k];
+          for (int cc = k; cc <= m; ++cc) A[r][cc] -= f * A[k][cc];
+        }
+      }
+      if (singular) continue;
+      double x[MB];
+      for (int r = m - 1; r >= 0; --r) {
+        double t = A[r][m];
+        for (int cc = r + 1; cc < m; ++cc) t -= A[r][cc] * x[cc];
+        x[r] = t / A[r][r];
+      }
+      for (int q = 0; q < m; ++q) u[blk[q]] = (T)x[q];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // defect (Sec. 2.4 step 3) with per-problem infinity norms, and its extension outside
 // Omega_h, Eq. (exp) in its steady state
 // ---------------------------------------------------------------------------------------
@@ -959,11 +1164,15 @@ __global__ void __launch_bounds__(256) k_defect(DefectArgs<T, TO> a) {
   extern __shared__ __align__(16) unsigned char defect_smem[];
   __shared__ double red[4];
   int b = blockIdx.x;
-  if (b < a.nechunks) {
-    extend_chunk<D, T, TO>(a, b, defect_smem);
-    return;
+  // extension chunks exist in 2D only (3D extends with a gather after this launch); keeping
+  // their registers out of the 3D instantiation leaves its tiles at full occupancy
+  if constexpr (D == 2) {
+    if (b < a.nechunks) {
+      extend_chunk<D, T, TO>(a, b, defect_smem);
+      return;
+    }
+    b -= a.nechunks;
   }
-  b -= a.nechunks;
   const Geo& g = a.g;
   if (b < a.nbt) {
     const int tile = xcd_tile(b, a.nbt);
@@ -1457,6 +1666,66 @@ __global__ void __launch_bounds__(256) k_unpack(int64_t total, Geo g, const int8
   dst[i] = c ? v : 0.0;
 }
 
+// Warm start of a new hierarchy from the solution u of a previous one on the same grid (caller
+// layout, (n+1)^D values per problem): every node that is an unknown now but was not before
+// takes the mean of the linear extrapolations 2 u(Q1) - u(Q2) along the axis directions where
+// Q1 = P -+ e_a and Q2 = P -+ 2 e_a are unknowns of both hierarchies; with no such direction,
+// the mean of its axis neighbours that are; else 0.  Nodes that are unknowns of both keep
+// their value.  Writes happen only at new nodes and reads only at old ones, so the update is
+// in place.
+template <int D>
+__global__ void __launch_bounds__(256) k_warm_start(int64_t total, Geo g,
+                                                    const int8_t* __restrict__ cls,
+                                                    const int8_t* __restrict__ cls_prev,
+                                                    double* __restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int64_t nnu = D == 3 ? (int64_t)g.np * g.np * g.np : (int64_t)g.np * g.np;
+  const int64_t p = i / nnu;
+  int64_t q = i - p * nnu;
+  int j[3];
+  j[0] = (int)(q % g.np);
+  q /= g.np;
+  j[1] = (int)(q % g.np);
+  j[2] = (int)(q / g.np);
+  const int64_t base = p * g.npp;
+  const int64_t P = base + j[0] + g.st[1] * j[1] + g.st[2] * j[2];
+  if (!cls[P] || cls_prev[P]) return;
+  const int64_t ust[3] = {1, g.np, (int64_t)g.np * g.np};
+  double lin = 0.0, cst = 0.0;
+  int nlin = 0, ncst = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+#pragma unroll
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+      const int j1 = j[a] + sgn, j2 = j[a] + 2 * sgn;
+      if (j1 < 0 || j1 > g.n) continue;
+      const int64_t Q1 = P + sgn * g.st[a];
+      if (!(cls[Q1] && cls_prev[Q1])) continue;
+      const double u1 = u[i + sgn * ust[a]];
+      cst += u1;
+      ++ncst;
+      if (j2 < 0 || j2 > g.n) continue;
+      const int64_t Q2 = P + 2 * sgn * g.st[a];
+      if (!(cls[Q2] && cls_prev[Q2])) continue;
+      lin += 2.0 * u1 - u[i + 2 * sgn * ust[a]];
+      ++nlin;
+    }
+  }
+  u[i] = nlin ? lin / nlin : (ncst ? cst / ncst : 0.0);
+}
+
+template <int D>
+void launch_warm_start(const DevLevel& L, const DevLevel& Lprev, int batch, double* u,
+                       hipStream_t s) {
+  const int64_t nnu = D == 3 ? (int64_t)L.g.np * L.g.np * L.g.np : (int64_t)L.g.np * L.g.np;
+  const int64_t total = nnu * batch;
+  hipLaunchKernelGGL((k_warm_start<D>), dim3((int)((total + 255) / 256)), dim3(256), 0, s, total, L.g,
+                     L.cls, Lprev.cls, u);
+}
+template void launch_warm_start<2>(const DevLevel&, const DevLevel&, int, double*, hipStream_t);
+template void launch_warm_start<3>(const DevLevel&, const DevLevel&, int, double*, hipStream_t);
+
 // u64 += u32 at the unknowns (defect correction), and u32z (the buffer the next step's
 // FP32 cycles start from; it may be u32 itself) reset to zero
 template <int D>
@@ -1644,6 +1913,7 @@ void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, co
   a.inv2d = (T)(1.0 / (2.0 * D));
   a.uband = uin;
   a.write_all = L.nchunks ? 0 : 1;
+  a.skip_band = G.smoother == 2 ? 1 : 0;
   // 2D: the tiles and the first launch's chunks share a launch; 3D chunks (which hold the
   // 27-point ghost rows in registers) get launches of their own, so that the tiles keep
   // their occupancy
@@ -1672,7 +1942,17 @@ void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, co
   else
     launch_relax_kernel<D, T, kRelaxPlain>(a, L, s);
   if (!L.nchunks) {
-    launch_band<D, T>(L, G, uout, rhs, tmp, batch, s);
+    if (G.smoother == 1 && L.alt_ncol) {
+      hipLaunchKernelGGL((k_band_kaczmarz<D, T>), dim3(batch), dim3(256), 0, s, L.g, L.alt_list,
+                         L.alt_off, L.alt_ncol, L.ghosts, L.gw, uout, rhs, G.lambda);
+    } else if (G.smoother == 2 && L.alt_ncol) {
+      if constexpr (D == 2)
+        hipLaunchKernelGGL((k_band_block<T>), dim3(batch), dim3(kBlockThreads), 0, s, L.g,
+                           L.alt_list, L.alt_off, L.alt_ncol, L.ghosts, L.ghost_off, L.gw, L.cls,
+                           uout, rhs);
+    } else {
+      launch_band<D, T>(L, G, uout, rhs, tmp, batch, s);
+    }
     return;
   }
   // the relaxation's later launches (chunks only): launch k >= 1 reads the band and ghost
@@ -1765,7 +2045,7 @@ void launch_defect(const DevLevel& L, const T* u, const T* rhs, TO* r, uint64_t*
   a.r = r;
   a.inv_h2 = (T)(1.0 / (L.g.h * L.g.h));
   a.norms = norms;
-  a.nechunks = with_ext ? L.nechunks : 0;
+  a.nechunks = with_ext && D == 2 ? L.nechunks : 0;
   a.hdr = L.ec_hdr;
   a.data = L.ec_data;
   a.stride = L.ec_stride;

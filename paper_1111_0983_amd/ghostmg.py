@@ -27,7 +27,7 @@ class mg_grid(ctypes.Structure):
                 ("delta_h", ctypes.c_double), ("cD", ctypes.c_double), ("cN", ctypes.c_double),
                 ("split", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_cycles", ctypes.c_int), ("max_cycles", ctypes.c_int),
-                ("batch", ctypes.c_int)]
+                ("batch", ctypes.c_int), ("smoother", ctypes.c_int)]
 
 
 class mg_bc_rule(ctypes.Structure):
@@ -74,6 +74,7 @@ def _load():
     lib.mg_cycles.argtypes = [vp, vp, vp, vp, ctypes.c_int]
     lib.mg_residual.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mg_rho.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp, vp, vp]
+    lib.mg_warm_start.argtypes = [vp, vp, vp]
     lib.mg_reinit.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, vp, ctypes.c_int, vp, vp, vp]
     lib.mg_time_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -218,6 +219,11 @@ class Solver:
 
     def cycles(self, f, g, u, ncycles: int):
         _check(_lib.mg_cycles(self._h, _ptr(f), _ptr(g), _ptr(u), int(ncycles)), "mg_cycles")
+
+    def warm_start(self, prev: "Solver", u):
+        """Map the solution u of handle prev onto this handle's unknowns, in place
+        (mg_warm_start)."""
+        _check(_lib.mg_warm_start(self._h, prev._h, _ptr(u)), "mg_warm_start")
 
     def rho(self, u0, max_cycles: int = 100, rtol: float = 1e-3):
         """Convergence factor of the cycle on the homogeneous problem from u0 (mg_rho):

@@ -129,67 +129,90 @@ def build_batch(seeds, n=N_FINE, nc=N_COARSE, device="cuda:0", precision=gm.MG_F
     return None, None, None, []
 
 
-def generate(n_samples: int, seed0: int = 0, batch: int = 64, device="cuda:0", log=print):
+def _targets(solver, f, g, probs, device):
+    """Solve one built batch to 1e-8 for its training targets.  Problems on which the cycle
+    diverges (a few percent of the ellipse unions: concave corners, coarse components without
+    a Dirichlet condition) have no target: the batch is solved again without them.  Returns
+    (features, targets, masks, kept count, dropped count, cycles) or None."""
+    dropped = 0
+    u = torch.zeros_like(f)
+    # 1e-8 is far below what the network can reproduce; a batch whose slowest problem misses
+    # it within the cycle budget keeps the problems that reached it
+    info = solver.solve(f, g, u, tol=1e-8, check=False)
+    while info["status"] == gm.MG_EDIVERGED:
+        B0 = len(probs)
+        fmax = f.reshape(B0, -1).abs().max(dim=1).values.cpu().numpy()
+        rel = solver.residual(f, g, u).max(axis=1) / np.maximum(fmax, 1e-300)
+        keep = [p.seed for p, r in zip(probs, rel) if r < 1.0]
+        solver.close()
+        dropped += B0 - len(keep)
+        if not keep or len(keep) == B0:
+            return None, dropped
+        solver, f, g, probs = build_batch(keep, device=device)
+        if solver is None:
+            return None, dropped
+        u = torch.zeros_like(f)
+        info = solver.solve(f, g, u, tol=1e-8, check=False)
+    if info["status"] not in (gm.MG_OK, gm.MG_ENOCONV):
+        raise gm.GhostMGError(info["status"], "mg_solve")
+    B0 = len(probs)
+    norms = solver.residual(f, g, u).max(axis=1)
+    fmax = f.reshape(B0, -1).abs().max(dim=1).values.cpu().numpy()
+    good = torch.from_numpy(norms <= 1e-8 * np.maximum(fmax, 1e-300)).to(f.device)
+    x, scale, (B, H, W) = cnn.features(solver, LEVEL, f, g)
+    tgt, mask = cnn.target(solver, LEVEL, u, scale / cnn.GuessNet.GAIN)
+    solver.close()
+    return (x.reshape(B, H * W * 8)[good], tgt.reshape(B, H * W)[good],
+            mask.reshape(B, H * W)[good], (H, W), info["cycles"]), \
+        dropped + int(B0 - good.sum().item())
+
+
+def generate(n_samples: int, seed0: int = 0, batch: int = 64, device="cuda:0", log=print,
+             threads: int = 8):
+    """Solver-generated training samples.  The hierarchies of `threads` batches are built at
+    once (the host setup of a batch is the slow part, and mg_setup runs outside the Python
+    lock), then solved one after the other."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from workloads import ellipses as el
+
     xs, ts, ms = [], [], []
     seed = seed0
     t0 = time.time()
     total = 0
     rejected = 0
-    from workloads import ellipses as el
-
-    while total < n_samples:
-        want = min(batch, n_samples - total)
-        seeds = []
-        while len(seeds) < want:  # screen the box margin cheaply before building solvers
-            p = el.draw(seed)
-            if el.accept(el.nodal_phi(p, N_FINE, device=device), N_FINE, 3.0 * 2.0 / N_COARSE):
-                seeds.append(seed)
-            else:
-                rejected += 1
-            seed += 1
-        solver, f, g, probs = build_batch(seeds, device=device)
-        rejected += want - len(probs)
-        if solver is None:
-            continue
-        u = torch.zeros_like(f)
-        # training targets: 1e-8 is far below what the network can reproduce; a batch whose
-        # slowest problem misses it within the cycle budget keeps the problems that reached it.
-        # Problems on which the cycle diverges (a few percent of the ellipse unions: concave
-        # corners, coarse components without a Dirichlet condition) have no target: the batch
-        # is solved again without them.
-        info = solver.solve(f, g, u, tol=1e-8, check=False)
-        while info["status"] == gm.MG_EDIVERGED:
-            B0 = len(probs)
-            fmax = f.reshape(B0, -1).abs().max(dim=1).values.cpu().numpy()
-            rel = solver.residual(f, g, u).max(axis=1) / np.maximum(fmax, 1e-300)
-            keep = [p.seed for p, r in zip(probs, rel) if r < 1.0]
-            solver.close()
-            rejected += B0 - len(keep)
-            if not keep or len(keep) == B0:
-                solver = None
-                break
-            solver, f, g, probs = build_batch(keep, device=device)
-            u = torch.zeros_like(f)
-            info = solver.solve(f, g, u, tol=1e-8, check=False)
-        if solver is None:
-            continue
-        if info["status"] not in (gm.MG_OK, gm.MG_ENOCONV):
-            raise gm.GhostMGError(info["status"], "mg_solve")
-        B0 = len(probs)
-        norms = solver.residual(f, g, u).max(axis=1)
-        fmax = f.reshape(B0, -1).abs().max(dim=1).values.cpu().numpy()
-        good = torch.from_numpy(norms <= 1e-8 * np.maximum(fmax, 1e-300)).to(f.device)
-        x, scale, (B, H, W) = cnn.features(solver, LEVEL, f, g)
-        tgt, mask = cnn.target(solver, LEVEL, u, scale / cnn.GuessNet.GAIN)
-        rejected += int(B0 - good.sum().item())
-        xs.append(x.reshape(B, H * W * 8)[good])
-        ts.append(tgt.reshape(B, H * W)[good])
-        ms.append(mask.reshape(B, H * W)[good])
-        total += int(good.sum().item())
-        solver.close()
-        if log and len(xs) % 10 == 1:
-            log(f"[learned] generated {total}/{n_samples} ({rejected} rejected, "
-                f"last solve {info['cycles']} cycles) {time.time() - t0:.1f}s")
+    H = W = None
+    last = 0
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        while total < n_samples:
+            want = min(batch * threads, n_samples - total)
+            seeds = []
+            while len(seeds) < want:  # screen the box margin cheaply before building solvers
+                p = el.draw(seed)
+                if el.accept(el.nodal_phi(p, N_FINE, device=device), N_FINE,
+                             3.0 * 2.0 / N_COARSE):
+                    seeds.append(seed)
+                else:
+                    rejected += 1
+                seed += 1
+            groups = [seeds[i:i + batch] for i in range(0, len(seeds), batch)]
+            built = list(pool.map(lambda sd: build_batch(sd, device=device), groups))
+            for sd, (solver, f, g, probs) in zip(groups, built):
+                rejected += len(sd) - len(probs)
+                if solver is None:
+                    continue
+                out, drop = _targets(solver, f, g, probs, device)
+                rejected += drop
+                if out is None:
+                    continue
+                x, t, m, (H, W), last = out
+                xs.append(x)
+                ts.append(t)
+                ms.append(m)
+                total += x.shape[0]
+            if log:
+                log(f"[learned] generated {total}/{n_samples} ({rejected} rejected, "
+                    f"last solve {last} cycles) {time.time() - t0:.1f}s")
     return dict(x=torch.cat(xs)[:n_samples], t=torch.cat(ts)[:n_samples],
                 m=torch.cat(ms)[:n_samples], H=H, W=W, rejected=rejected,
                 seconds=time.time() - t0)
@@ -387,6 +410,40 @@ def evaluate_each(net, probs, f, g, tol=1e-10, device="cuda:0", reps=3):
     return res
 
 
+def mfma_rate(net: cnn.GuessNet, B: int = 64, reps: int = 20, device="cuda:0") -> dict:
+    """Measured throughput of the network's BF16 MFMA kernels at the training shape (B
+    problems of the 65 x 65 level): forward, and forward + backward (data and weight
+    gradients), in TFLOP/s counted as 2 x (multiply-adds of the 3 x 3 convolutions), against
+    the dense BF16 peak of 2.5 PFLOP/s."""
+    H = W = 65
+    x = torch.randn(B * H * W * 8, device=device).to(torch.bfloat16)
+    fwd = sum(2.0 * B * H * W * 9 * cin * cout for cin, cout, _ in net.layers)
+    tgt = torch.zeros(B * H * W, device=device)
+    mask = torch.ones_like(tgt)
+
+    def run(back):
+        pred = net.forward(x, B, H, W)
+        if back:
+            _, dy = cnn.loss(pred, tgt, mask)
+            net.backward(dy, B, H, W)
+
+    out = {}
+    for name, back, flops in (("forward", False, fwd), ("train_step", True, 3.0 * fwd)):
+        run(back)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run(back)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[f"{name}_ms"] = ms
+        out[f"{name}_tflops"] = flops / (ms * 1e-3) / 1e12
+        out[f"{name}_mfma_util"] = out[f"{name}_tflops"] / 2500.0
+    return out
+
+
 def main(argv=None):
     import argparse
     import json
@@ -394,12 +451,14 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser(description="train and evaluate the learned initial guess")
     ap.add_argument("--samples", type=int, default=20000)
+    ap.add_argument("--seed0", type=int, default=0, help="first training seed")
     ap.add_argument("--val", type=int, default=512)
     ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--eval", type=int, default=64)
+    ap.add_argument("--eval", type=int, default=64, help="evaluation problems (0: none)")
     ap.add_argument("--out", default="gpurun_out/learned")
+    ap.add_argument("--init", default=None, help="start training from these weights")
     ap.add_argument("--weights", default=None, help="skip training, load these weights")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
@@ -408,25 +467,32 @@ def main(argv=None):
     if args.weights:
         net.load(dict(np.load(args.weights)))
     else:
+        if args.init:
+            net.load(dict(np.load(args.init)))
         t0 = time.time()
-        data = generate(args.samples, seed0=0)
-        val = generate(args.val, seed0=20000)
+        data = generate(args.samples, seed0=args.seed0)
+        val = generate(args.val, seed0=20000) if args.val else None
         res["generate_s"] = time.time() - t0
+        res["samples"] = int(data["x"].shape[0])
         res["rejected"] = data["rejected"]
         t0 = time.time()
         res["train_hist"] = train(net, data, args.steps, batch=args.batch, lr=args.lr, val=val)
         res["train_s"] = time.time() - t0
         np.savez(os.path.join(args.out, "guessnet.npz"), **net.state())
-    seeds = []
-    s = 1_000_000
-    from workloads import ellipses as el
-    while len(seeds) < args.eval:
-        p = el.draw(s)
-        if el.accept(el.nodal_phi(p, N_FINE, device="cuda:0"), N_FINE, 3.0 * 2.0 / N_COARSE):
-            seeds.append(s)
-        s += 1
-    res["eval"] = evaluate(net, seeds)
-    print(json.dumps(res["eval"]))
+        del data
+    res["mfma"] = mfma_rate(net)
+    print(json.dumps({"mfma": res["mfma"]}), flush=True)
+    if args.eval:
+        seeds = []
+        s = 1_000_000
+        from workloads import ellipses as el
+        while len(seeds) < args.eval:
+            p = el.draw(s)
+            if el.accept(el.nodal_phi(p, N_FINE, device="cuda:0"), N_FINE, 3.0 * 2.0 / N_COARSE):
+                seeds.append(s)
+            s += 1
+        res["eval"] = evaluate(net, seeds)
+        print(json.dumps(res["eval"]))
     with open(os.path.join(args.out, "learned.json"), "w") as f:
         json.dump(res, f, indent=1)
 

@@ -1,9 +1,9 @@
 """3D projection-style sequence: one pressure solve per step of a moving ellipsoidal tank.
 
 Every step builds the hierarchy of the tank's current position (mg_setup), takes the
-previous step's solution as the initial iterate on the unknowns the two steps share (new
-unknowns start at 0), and solves with FP32 cycles inside FP64 defect correction to the
-tolerance.  Inputs come from workloads/tank.py; every arithmetic step of the solve runs in
+previous step's solution as the initial iterate (mg_warm_start extrapolates it linearly to
+the nodes the boundary has moved over), and solves with FP32 cycles inside FP64 defect
+correction to the tolerance.  Inputs come from workloads/tank.py; every arithmetic step of the solve runs in
 the HIP library.
 
   python -m paper_1111_0983_amd.sequence --steps 4 --n 384
@@ -26,7 +26,7 @@ def run(steps: int = 4, n: int = 384, n_coarse: int = 24, warm: bool = True,
 
     seq = tank.TankSequence(n)
     rows = dict(setup_s=[], solve_ms=[], cycles=[], outer=[], rel=[], unknowns=[])
-    prev_u = prev_c = None
+    prev_u = prev_s = None
     out = {}
     for t in range(start, start + steps):
         t0 = time.perf_counter()
@@ -41,7 +41,8 @@ def run(steps: int = 4, n: int = 384, n_coarse: int = 24, warm: bool = True,
         setup = time.perf_counter() - t0
         u = torch.zeros_like(f)
         if warm and prev_u is not None:
-            u = torch.where((c > 0) & (prev_c > 0), prev_u, u).contiguous()
+            u.copy_(prev_u)
+            s.warm_start(prev_s, u)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         info = s.solve(f, g, u, tol=tol)
@@ -56,10 +57,13 @@ def run(steps: int = 4, n: int = 384, n_coarse: int = 24, warm: bool = True,
         if log:
             log(f"[sequence] step {t}: setup {setup:.1f}s, solve {ms:.1f} ms, "
                 f"{info['cycles']} cycles, rel {info['rel']:.2e}")
-        prev_u, prev_c = u, c
+        if prev_s is not None:
+            prev_s.close()
+        prev_u, prev_s = u, s
         if keep_last and t == start + steps - 1:
             out["phi"], out["f"], out["u"] = phi, f, u
-        s.close()
+    if prev_s is not None:
+        prev_s.close()
     out.update(rows)
     return out
 

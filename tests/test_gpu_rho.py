@@ -71,3 +71,56 @@ def test_gpu_rho_rejects_bad_arguments():
     with pytest.raises(gm.GhostMGError):
         s.rho(torch.zeros((33 * 33,), dtype=torch.float64, device=DEV))
     s.close()
+
+
+@pytest.mark.parametrize("smoother,lam,nu1,nu2", [(1, 3, 1, 1), (1, 6, 2, 1), (2, 0, 1, 1),
+                                                  (2, 0, 2, 1)])
+def test_gpu_comparison_smoothers_match_oracle(smoother, lam, nu1, nu2):
+    """The boundary relaxations of the paper's comparison (Sec. 3.3) on the GPU: Kaczmarz
+    sweeps (smoother 1) and block relaxation (smoother 2) of the band, swept colour by colour
+    after a red-black interior sweep, against the oracle's same ordering, on the paper's
+    circle with the two-grid cycle at N = 64 (Fig. convFactLambda) and a V-cycle down to 8:
+    the factors agree cycle by cycle."""
+    from paper_1111_0983_amd import ghostmg as gm
+
+    phi = geo.paper_circle().nodal_phi(64)
+    rule = pr.paper_rule()
+    for nc, gamma in ((32, 1), (8, 1)):
+        o = Oracle(phi, default_grid(2, 64, nc, nu1=nu1, nu2=nu2, gamma=gamma, lam=lam,
+                                     smoother=smoother), rule)
+        c, _ = o.cls(0)
+        u0 = np.where(c > 0, np.random.default_rng(9).uniform(-1, 1, c.size), 0.0)
+        grid = gm.mg_grid_default(2, 64, nc, nu1=nu1, nu2=nu2, gamma=gamma, lam=lam,
+                                  smoother=smoother)
+        s = gm.Solver(torch.from_numpy(phi).to(DEV), [rule], grid)
+        rg, hg = s.rho(torch.from_numpy(u0).to(DEV), max_cycles=10, rtol=0.0)
+        ro, ho = o.rho(u0, max_cycles=10, rtol=0.0)
+        print(f"smoother {smoother} lambda {lam} nu {nu1 + nu2} Nc {nc}: GPU {np.round(hg[-3:], 4)}"
+              f" oracle {np.round(ho[-3:], 4)}")
+        assert np.allclose(hg, ho, rtol=1e-8, atol=0.0), (hg, ho)
+        s.close()
+
+
+def test_gpu_comparison_smoother_solves():
+    """A full solve with each comparison relaxation reaches the tolerance and the same
+    discrete solution as the paper's relaxation."""
+    from paper_1111_0983_amd import ghostmg as gm
+
+    w = pr.disk64()
+    phi = w.domain.nodal_phi(64)
+    sols = []
+    for smoother, lam in ((0, 5), (1, 5), (2, 0)):
+        s = gm.Solver(torch.from_numpy(phi).to(DEV), [w.rule],
+                      gm.mg_grid_default(2, 64, 8, smoother=smoother, lam=lam))
+        c = s.classes()
+        G = s.ghosts()
+        P = geo.grid_points(2, 64)
+        f = np.where(c == 1, w.solution.f(P), 0.0)
+        g = pr.rhs_from_ghosts(2, 64, c, G["node"], G["B"], G["type"], w.solution, w.domain)
+        u = torch.zeros(f.size, dtype=torch.float64, device=DEV)
+        info = s.solve(torch.from_numpy(f).to(DEV), torch.from_numpy(g).to(DEV), u, tol=1e-10)
+        assert info["status"] == 0
+        sols.append(u.cpu().numpy())
+        s.close()
+    for x in sols[1:]:
+        assert np.abs(x - sols[0]).max() <= 1e-9 * np.abs(sols[0]).max()

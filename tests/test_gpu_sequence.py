@@ -1,9 +1,9 @@
 """The 3D projection-style sequence at its full size (384^3, moving ellipsoidal tank, FP32
 cycles inside FP64 defect correction): every step reaches the tolerance from the warm start
-(the previous step's solution) and from a cold start, and the oracle's own evaluation of the
-discrete system (Eq. (discr)) confirms the defect of the last solution.  The cycle counts of
-warm and cold starts are printed, not asserted: the previous solution differs from the new
-one mostly at the moved boundary, which the cycle reduces no faster than a zero guess."""
+(the previous step's solution, extended by mg_warm_start to the nodes the boundary moved
+over) and from a cold start; the warm start takes no more cycles than the cold one; the
+oracle's own evaluation of the discrete system (Eq. (discr)) confirms the defect of the last
+solution.  And mg_warm_start itself on a small 2D case: linear data is extended exactly."""
 import numpy as np
 import pytest
 
@@ -11,6 +11,56 @@ torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 from oracle import Oracle, default_grid  # noqa: E402
+from workloads import geometry as geo, problems as pr  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def test_warm_start_extends_linear_data_exactly():
+    """New unknowns with a linear extrapolation direction reproduce linear data exactly;
+    every new value follows the rule of ghostmg.h (mean of 2 u(Q1) - u(Q2) over the axis
+    directions where Q1, Q2 are unknowns of both hierarchies, else the mean of such Q1, else
+    0), recomputed here; old unknowns keep their values."""
+    from paper_1111_0983_amd import ghostmg as gm
+
+    n = 64
+    P = geo.grid_points(2, n)
+    a = gm.Solver(torch.from_numpy(geo.Disk((0.0, 0.0), 0.50).nodal_phi(n)).to(DEV),
+                  [pr.paper_rule()], gm.mg_grid_default(2, n, 8))
+    b = gm.Solver(torch.from_numpy(geo.Disk((0.04, 0.0), 0.53).nodal_phi(n)).to(DEV),
+                  [pr.paper_rule()], gm.mg_grid_default(2, n, 8))
+    ca, cb = a.classes(), b.classes()
+    lin = 0.3 + 1.7 * P[:, 0] - 0.9 * P[:, 1]
+    u0 = np.where(ca > 0, lin, 0.0)
+    u = torch.from_numpy(u0).to(DEV)
+    b.warm_start(a, u)
+    got = u.cpu().numpy()
+    both = (cb > 0) & (ca > 0)
+    new = np.flatnonzero((cb > 0) & (ca == 0))
+    assert len(new) > 20
+    assert np.array_equal(got[both], u0[both])
+    exact = 0
+    for i in new:
+        y, x = divmod(int(i), n + 1)
+        ls, cs = [], []
+        for dx, dy in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+            x1, y1, x2, y2 = x + dx, y + dy, x + 2 * dx, y + 2 * dy
+            if not (0 <= x1 <= n and 0 <= y1 <= n):
+                continue
+            q1 = x1 + (n + 1) * y1
+            if not both[q1]:
+                continue
+            cs.append(u0[q1])
+            if 0 <= x2 <= n and 0 <= y2 <= n and both[x2 + (n + 1) * y2]:
+                ls.append(2 * u0[q1] - u0[x2 + (n + 1) * y2])
+        want = np.mean(ls) if ls else (np.mean(cs) if cs else 0.0)
+        assert abs(got[i] - want) <= 1e-13, (i, got[i], want)
+        if ls:
+            exact += 1
+            assert abs(got[i] - lin[i]) <= 1e-13
+    assert exact >= len(new) // 2
+    a.close()
+    b.close()
 
 
 def test_tank_sequence_warm_start():
@@ -21,6 +71,7 @@ def test_tank_sequence_warm_start():
     cold = sequence.run(steps=1, n=384, start=1, warm=False, log=None)
     assert all(r <= 1e-10 for r in warm["rel"]) and cold["rel"][0] <= 1e-10
     print("cycles: steps 0, 1 warm", warm["cycles"], "step 1 cold", cold["cycles"])
+    assert warm["cycles"][1] <= cold["cycles"][0]
     phi = warm["phi"].cpu().numpy()
     o = Oracle(phi, default_grid(3, 384, 24), tank.RULE)
     c, _ = o.cls(0)
