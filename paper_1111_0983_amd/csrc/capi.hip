@@ -880,16 +880,19 @@ int mg_time_kernel(mg_handle_t h, int kernel, int level, int reps, double* avg_m
     // written, right-hand side and node code read per unknown; ghost row weights)
     const double nu = (double)S.nint + (double)S.nghost, ng = (double)S.nghost;
     const double K = h->dim == 2 ? 9.0 : 27.0;
+    // the relaxation chunks hold the ghost weights in the cycle's precision, the per-phase
+    // launches of levels without chunks read the FP64 rows
+    const double gws = L.nchunks > 0 ? sz : 8.0;
     double b = 0.0;
-    if (kernel == 0) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0;
+    if (kernel == 0) b = nu * (3.0 * sz + 1.0) + ng * K * gws;
     if (kernel == 5) {
       const HostLevel& C = h->host[level + 1];
-      b = nu * (3.0 * sz + 1.0) + ng * K * 8.0 + (double)(C.nint + C.nghost) * (sz + 1.0);
+      b = nu * (3.0 * sz + 1.0) + ng * K * gws + (double)(C.nint + C.nghost) * (sz + 1.0);
     }
     if (kernel == 6) {
       // no iterate read; the right-hand side is written; the finer defect is read
       const HostLevel& F = h->host[level - 1];
-      b = nu * (2.0 * sz + 2.0) + ng * K * 8.0 +
+      b = nu * (2.0 * sz + 2.0) + ng * K * gws +
           ((double)F.nint + (double)F.nghost + (double)F.ext.size()) * sz;
     }
     if (kernel == 1) b = nu * (3.0 * sz + 1.0) + ng * K * 8.0 + (double)S.ext.size() * (sz + 24.0);

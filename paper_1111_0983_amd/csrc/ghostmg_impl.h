@@ -58,9 +58,10 @@ constexpr ExtFixed ext_fixed(int D) {
 }
 // Offsets (int32 words) of the fixed layout: slots S = 1 + 2 band_colour_slots(D) +
 // band_halo_slots(D), W = band_chunk_threads(D), NSW = S W entries: node (-1 where empty),
-// mask, D neighbour words per entry, then the ghost rows (ids, FP64 weights, tap-major with
-// stride W), c_G per ghost slot, the interpolation candidates and the restriction pairs (per
-// entry, where the level has them).
+// mask, D neighbour words per entry, then the ghost rows (LDS tap addresses two per word, and
+// weights in the cycle's precision, tap-major with stride W; the regions keep the size of
+// one word per tap and FP64 weights), c_G per ghost slot, the interpolation candidates and
+// the restriction pairs (per entry, where the level has them).
 struct BandFixed {
   int NSW, W, GID, GW, GC, PC, RS, stride;
 };
@@ -142,8 +143,11 @@ struct HostLevel {
   // interpolation candidate m exists and carries an unknown; bit 30: band or ghost node;
   // bit 31: owned, written to the output); D words of
   // (minus, plus) int16 local neighbour ids per axis.  Per ghost (tap-major, ghost fastest):
-  // Pow3<D> local stencil ids (the ghost's own id for taps of zero weight) and FP64 weights
-  // (0 for those taps); one FP64 constant c_G.  That is the packed layout (3D); in 2D
+  // the LDS addresses of its Pow3<D> taps, two 16-bit addresses per word (a tap on a ghost
+  // entry reads that ghost's value before the ghost phase, held at ns + its id; any other tap
+  // the entry's value at its id; taps of zero weight name the ghost's own earlier value), and
+  // the weights (0 for those taps) in the precision of the cycles (FP32 with FP32 cycles);
+  // one FP64 constant c_G.  That is the packed layout (3D); in 2D
   // (band_fixed_layout) the same arrays sit at the fixed offsets of band_fixed(), entry i of a
   // run at its slot position, the ghost rows with stride W, and the header's first word is
   // the slot count.

@@ -682,19 +682,20 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
   // there, so that a ghost phase can store its new values into su without a second barrier)
   T* gs = su + ns;
   if (ghost) gs[tid] = uv[0];
-  // the ghost rows are first needed in phase 2: loaded after the values (registers)
-  int32_t gid[K];
-  double gwt[K];
+  // the ghost rows are first needed in phase 2: loaded after the values (registers): the
+  // LDS address of every tap (two per word) and the weights in the cycle's precision
+  constexpr int KP = (K + 1) / 2;
+  uint32_t gadp[KP];
+  T gwt[K];
   double gc = 0.0;
   if (ng > 0) {
     const int tg = ghost ? tid : 0;
-    const int32_t* gi = a.data + hd[3];
-    const double* gw = (const double*)(a.data + hd[4]);
+    const uint32_t* gi = (const uint32_t*)(a.data + hd[3]);
+    const T* gw = (const T*)(a.data + hd[4]);
 #pragma unroll
-    for (int q = 0; q < K; ++q) {
-      gid[q] = gi[q * ng + tg];
-      gwt[q] = gw[q * ng + tg];
-    }
+    for (int q = 0; q < KP; ++q) gadp[q] = gi[q * ng + tg];
+#pragma unroll
+    for (int q = 0; q < K; ++q) gwt[q] = gw[q * ng + tg];
     gc = ((const double*)(a.data + hd[5]))[tg];
   }
   __syncthreads();
@@ -709,11 +710,6 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
     }
   // phases p, p + 1, p + 2 of every sweep: red, black, ghosts (the colour of a phase is
   // fixed, so every slot index below is a compile-time constant)
-  // taps on ghost entries (ids below ng) read gs, the others su; taps of zero weight name
-  // the ghost itself
-  int gad[K];
-#pragma unroll
-  for (int q = 0; q < K; ++q) gad[q] = gid[q] < ng ? ns + gid[q] : gid[q];
   for (int p = 0; p < a.phases; p += 3) {
     // the previous ghost phase's values become the snapshot (nothing reads gs until the
     // next ghost phase, two barriers later)
@@ -723,13 +719,22 @@ __device__ void relax_chunk(const RelaxArgs<T>& a, int c, unsigned char* lds) {
     band_colour_phase<D, T, NC, 1 + NC, NS>(p + 1, mask, nbi, e_of, uv, rv, su, a.h2, a.inv2d);
     __syncthreads();
     if (ghost && ((mask[0] >> (p + 2)) & 1u)) {
-      T gv[K];
+      // the row in groups of 9 taps, in tap order: the values of one group are read before
+      // its products, and no more than one group is held (the whole 27-tap row would double
+      // the registers of the 3D kernel and halve its occupancy)
+      constexpr int KG = 9;
+      T acc = 0;
 #pragma unroll
-      for (int q = 0; q < K; ++q) gv[q] = su[gad[q]];
-      double acc = 0.0;
+      for (int q0 = 0; q0 < K; q0 += KG) {
+        T gv[KG];
 #pragma unroll
-      for (int q = 0; q < K; ++q) acc += gwt[q] * (double)gv[q];
-      uv[0] = ghost_update<T>(uv[0], rv[0], acc, gc);
+        for (int q = 0; q < KG; ++q)
+          gv[q] = su[(gadp[(q0 + q) >> 1] >> (16 * ((q0 + q) & 1))) & 0xffffu];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) acc += gwt[q0 + q] * gv[q];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      uv[0] = ghost_update<T>(uv[0], rv[0], (double)acc, gc);
       su[tid] = uv[0];
     }
     __syncthreads();

@@ -801,10 +801,11 @@ int32_t pack16(int a, int b) { return (int32_t)(((uint32_t)(uint16_t)a) | ((uint
 // The chunk data just written from Dv[off] (packed layout: ns entries in runs of ng ghosts,
 // nr red, nbk black, then read-only ones) rewritten in the fixed layout (band_fixed): entry i of
 // run r moves to local id (first slot of r + i / W) W + i mod W, and every local id it stores
-// (neighbour pairs, ghost stencil ids) is renumbered the same way.
+// (neighbour pairs, ghost tap addresses) is renumbered the same way; the earlier ghost values
+// move from ns + j to NSW + j.  w32: the ghost weights are FP32.
 void to_fixed_layout(std::vector<int32_t>& Dv, int32_t off, int D, int ns, int ng, int nr, int nbk,
                      int32_t gid_off, int32_t gw_off, int32_t gc_off, int32_t pc_off,
-                     int32_t rs_off, bool pc, bool rs) {
+                     int32_t rs_off, bool pc, bool rs, bool w32) {
   const BandFixed F = band_fixed(D, pc, rs);
   const int W = F.W, NC = band_colour_slots(D), K = D == 2 ? 9 : 27;
   const int first_slot[4] = {0, 1, 1 + NC, 1 + 2 * NC};
@@ -832,11 +833,20 @@ void to_fixed_layout(std::vector<int32_t>& Dv, int32_t off, int D, int ns, int n
       X[F.RS + 2 * id + 1] = Dv[rs_off + 2 * e + 1];
     }
   }
+  auto remap = [&](int a) { return a >= ns ? F.NSW + map[a - ns] : map[a]; };
+  for (int q2 = 0; q2 < (K + 1) / 2; ++q2)
+    for (int j = 0; j < ng; ++j) {
+      const uint32_t w = (uint32_t)Dv[gid_off + q2 * ng + j];
+      X[F.GID + q2 * W + j] = pack16(remap((int)(w & 0xffffu)), remap((int)(w >> 16)));
+    }
   for (int q = 0; q < K; ++q)
     for (int j = 0; j < ng; ++j) {
-      X[F.GID + q * W + j] = map[Dv[gid_off + q * ng + j]];
-      X[F.GW + 2 * (q * W + j)] = Dv[gw_off + 2 * (q * ng + j)];
-      X[F.GW + 2 * (q * W + j) + 1] = Dv[gw_off + 2 * (q * ng + j) + 1];
+      if (w32) {
+        X[F.GW + q * W + j] = Dv[gw_off + q * ng + j];
+      } else {
+        X[F.GW + 2 * (q * W + j)] = Dv[gw_off + 2 * (q * ng + j)];
+        X[F.GW + 2 * (q * W + j) + 1] = Dv[gw_off + 2 * (q * ng + j) + 1];
+      }
     }
   for (int j = 0; j < ng; ++j) {
     X[F.GC + 2 * j] = Dv[gc_off + 2 * j];
@@ -883,6 +893,8 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
   const int K = D == 2 ? 9 : 27;
   const int P = 3 + 3 * lambda;
   const size_t nn = HL.cls.size();
+  // FP32 cycles read FP32 ghost weights
+  const bool w32 = H->grid.precision == MG_FP32_DC;
   HL.bc_hdr.clear();
   HL.bc_data.clear();
   HL.bc_nchunks = 0;
@@ -1068,18 +1080,36 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
         Dv.push_back((int32_t)(p * HC.g.npp + jb[0] + HC.g.st[1] * jb[1] + HC.g.st[2] * jb[2]));
       }
     }
+    // ghost rows: the LDS address each tap reads, two taps per word (tap pair major, ghost
+    // fastest): a tap on a ghost entry (local id below ng) reads that ghost's value before the
+    // ghost phase, kept at ns + id; any other tap reads the entry's current value at its id;
+    // taps of zero weight name the ghost's own earlier value
     const int32_t gid_off = (int32_t)Dv.size();
-    for (int t = 0; t < K; ++t)
-      for (int j = 0; j < ng; ++j) {
-        const double w = HL.gw[(size_t)gidx[touched[j]] * K + t];
-        Dv.push_back(w != 0.0 ? lid[tap_node(touched[j], t)] : j);
-      }
+    auto tap_addr = [&](int j, int t) {
+      if (t >= K) return 0;
+      const double w = HL.gw[(size_t)gidx[touched[j]] * K + t];
+      const int id = w != 0.0 ? lid[tap_node(touched[j], t)] : j;
+      return id < ng ? ns + id : id;
+    };
+    for (int t = 0; t < K; t += 2)
+      for (int j = 0; j < ng; ++j) Dv.push_back(pack16(tap_addr(j, t), tap_addr(j, t + 1)));
     pad_even(Dv);
+    // the weights in the precision of the cycles that read them
     const int32_t gw_off = (int32_t)Dv.size();
     std::vector<double> wv;
     for (int t = 0; t < K; ++t)
       for (int j = 0; j < ng; ++j) wv.push_back(HL.gw[(size_t)gidx[touched[j]] * K + t]);
-    put_doubles(Dv, wv);
+    if (w32) {
+      for (double w : wv) {
+        const float f = (float)w;
+        int32_t bits;
+        std::memcpy(&bits, &f, sizeof bits);
+        Dv.push_back(bits);
+      }
+      pad_even(Dv);
+    } else {
+      put_doubles(Dv, wv);
+    }
     const int32_t gc_off = (int32_t)Dv.size();
     wv.clear();
     for (int j = 0; j < ng; ++j) wv.push_back(HL.ghosts[gidx[touched[j]]].type ? H->grid.cD : cNh);
@@ -1102,7 +1132,7 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
       // the header keeps the counts; the data sits at chunk * bc_stride
       const BandFixed F = band_fixed(D, l < H->L, l > 0);
       to_fixed_layout(Dv, off, D, ns, ng, nr, nbk, gid_off, gw_off, gc_off, pc_off, rs_off,
-                      l < H->L, l > 0);
+                      l < H->L, l > 0, w32);
       HL.bc_stride = F.stride;
       const int32_t hdr[kBandHdr] = {F.NSW, (int32_t)counts, off, off + F.GID, off + F.GW,
                                      off + F.GC, l < H->L ? off + F.PC : -1, l > 0 ? off + F.RS : -1};

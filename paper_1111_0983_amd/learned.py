@@ -22,6 +22,10 @@ import torch
 from . import cnn, ghostmg as gm
 
 N_FINE, N_COARSE, LEVEL = 512, 32, 3   # the network works on the 65 x 65 level
+# cycle budget of a training-target solve (to 1e-8; the median problem needs about 15)
+GEN_CYCLES = 150
+# first validation seed (training draws from seed0 upwards, evaluation from 1,000,000)
+VAL_SEED0 = 500_000
 
 
 def _components_ok(cls: np.ndarray, ghosts: dict, n: int) -> bool:
@@ -73,7 +77,7 @@ def _merges(solver, problem: int) -> bool:
 
 
 def build_batch(seeds, n=N_FINE, nc=N_COARSE, device="cuda:0", precision=gm.MG_FP64,
-                inner_cycles=2, screen=True):
+                inner_cycles=2, screen=True, max_cycles=1000):
     """Solver handle plus f, g for the accepted problems among `seeds`."""
     from workloads import ellipses as el
 
@@ -88,9 +92,9 @@ def build_batch(seeds, n=N_FINE, nc=N_COARSE, device="cuda:0", precision=gm.MG_F
         fs.append(el.nodal_f(p, n, device=device))
     while probs:
         # a few accepted problems converge slowly (rho 0.9-0.95: concave corners where two
-        # ellipses meet, around 500 cycles to 1e-10); the budget lets every one finish
+        # ellipses meet, around 500 cycles to 1e-10); the default budget lets every one finish
         grid = gm.mg_grid_default(2, n, nc, batch=len(probs), precision=precision,
-                                  inner_cycles=inner_cycles, max_cycles=1000)
+                                  inner_cycles=inner_cycles, max_cycles=max_cycles)
         try:
             solver = gm.Solver(torch.cat(phis), [p.rule for p in probs], grid)
         except gm.GhostMGError as e:
@@ -129,7 +133,7 @@ def build_batch(seeds, n=N_FINE, nc=N_COARSE, device="cuda:0", precision=gm.MG_F
     return None, None, None, []
 
 
-def _targets(solver, f, g, probs, device):
+def _targets(solver, f, g, probs, device, max_cycles=1000):
     """Solve one built batch to 1e-8 for its training targets.  Problems on which the cycle
     diverges (a few percent of the ellipse unions: concave corners, coarse components without
     a Dirichlet condition) have no target: the batch is solved again without them.  Returns
@@ -148,7 +152,7 @@ def _targets(solver, f, g, probs, device):
         dropped += B0 - len(keep)
         if not keep or len(keep) == B0:
             return None, dropped
-        solver, f, g, probs = build_batch(keep, device=device)
+        solver, f, g, probs = build_batch(keep, device=device, max_cycles=max_cycles)
         if solver is None:
             return None, dropped
         u = torch.zeros_like(f)
@@ -168,10 +172,13 @@ def _targets(solver, f, g, probs, device):
 
 
 def generate(n_samples: int, seed0: int = 0, batch: int = 64, device="cuda:0", log=print,
-             threads: int = 8):
+             threads: int = 12, max_cycles: int = GEN_CYCLES):
     """Solver-generated training samples.  The hierarchies of `threads` batches are built at
     once (the host setup of a batch is the slow part, and mg_setup runs outside the Python
-    lock), then solved one after the other."""
+    lock), then solved one after the other.  A batch is solved together, so its slowest
+    problem sets its cycle count: a problem that has not reached the target tolerance within
+    max_cycles gives no sample (counted as rejected), instead of holding its batch for
+    hundreds of cycles."""
     from concurrent.futures import ThreadPoolExecutor
 
     from workloads import ellipses as el
@@ -196,12 +203,13 @@ def generate(n_samples: int, seed0: int = 0, batch: int = 64, device="cuda:0", l
                     rejected += 1
                 seed += 1
             groups = [seeds[i:i + batch] for i in range(0, len(seeds), batch)]
-            built = list(pool.map(lambda sd: build_batch(sd, device=device), groups))
+            built = list(pool.map(
+                lambda sd: build_batch(sd, device=device, max_cycles=max_cycles), groups))
             for sd, (solver, f, g, probs) in zip(groups, built):
                 rejected += len(sd) - len(probs)
                 if solver is None:
                     continue
-                out, drop = _targets(solver, f, g, probs, device)
+                out, drop = _targets(solver, f, g, probs, device, max_cycles)
                 rejected += drop
                 if out is None:
                     continue
@@ -471,7 +479,8 @@ def main(argv=None):
             net.load(dict(np.load(args.init)))
         t0 = time.time()
         data = generate(args.samples, seed0=args.seed0)
-        val = generate(args.val, seed0=20000) if args.val else None
+        # validation seeds far from the training seeds (about 3.5 seeds are drawn per sample)
+        val = generate(args.val, seed0=VAL_SEED0) if args.val else None
         res["generate_s"] = time.time() - t0
         res["samples"] = int(data["x"].shape[0])
         res["rejected"] = data["rejected"]
