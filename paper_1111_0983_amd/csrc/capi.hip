@@ -156,7 +156,19 @@ int upload_level(mg_handle_s* H, int l) {
     if ((rc = upload(&L.et_node, S.et_node))) return rc;
     if ((rc = upload(&L.et_off, S.et_off))) return rc;
     if ((rc = upload(&L.et_src, S.et_src))) return rc;
-    if ((rc = upload(&L.et_wt, S.et_wt))) return rc;
+    if (H->grid.precision == MG_FP32_DC) {
+      std::vector<float> w32(S.et_wt.begin(), S.et_wt.end());
+      float* w = nullptr;
+      rc = upload(&w, w32);
+      L.et_wt = w;
+    } else {
+      double* w = nullptr;
+      rc = upload(&w, S.et_wt);
+      L.et_wt = w;
+    }
+    if (rc) return rc;
+    if (S.nghost && hipMalloc(&L.et_rg, (size_t)S.nghost * sizeof(double)) != hipSuccess)
+      return MG_ENOMEM;
   }
   if (S.ec_nchunks) {
     L.nechunks = S.ec_nchunks;
@@ -517,7 +529,7 @@ int rho_impl(mg_handle_s* H, const double* u0, int max_cycles, double rtol, doub
 
 void free_level(DevLevel& L) {
   void* ptrs[] = {L.alt_list, L.alt_off, L.bc_hdr, L.bc_data, L.z64, L.z32, L.band_list, L.ec_hdr, L.ec_data,
-                  L.et_node, L.et_off, L.et_src, L.et_wt, L.rcls, L.gw,
+                  L.et_node, L.et_off, L.et_src, L.et_wt, L.et_rg, L.rcls, L.gw,
                   L.cls, L.phi, L.tiles, L.ghosts, L.ghost_off, L.red, L.black, L.red_off, L.black_off,
                   L.ext, L.ext_merged, L.ext_off, L.dag_off, L.dag_start, L.rcode, L.u64[0],
                   L.u64[1], L.rhs64, L.r64, L.gtmp64, L.u32[0], L.u32[1], L.rhs32, L.r32, L.gtmp32,

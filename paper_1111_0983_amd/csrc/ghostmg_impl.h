@@ -176,8 +176,8 @@ struct HostLevel {
   std::vector<int32_t> ec_data;
   int ec_nchunks = 0, ec_smax = 0, ec_stride = 0;
   // the same composed terms as flat arrays (3D: a gather after the defect, which has already
-  // written the ghost defects): extension node, term offsets (records + 1), ghost node and
-  // weight of every term
+  // written the ghost defects): extension node, term offsets (records + 1), ghost index (in
+  // the level's ghost list) and weight of every term
   std::vector<int32_t> et_node, et_off, et_src;
   std::vector<double> et_wt;
   // coarsest level
@@ -205,7 +205,10 @@ struct DevLevel {
   int32_t *ec_hdr = nullptr, *ec_data = nullptr;
   int net = 0;
   int32_t *et_node = nullptr, *et_off = nullptr, *et_src = nullptr;
-  double* et_wt = nullptr;
+  // term weights in the precision of the cycles (FP32 with FP32 cycles), and the ghost
+  // defects by ghost id (nghost values of that precision), written by the defect launch
+  void* et_wt = nullptr;
+  void* et_rg = nullptr;
   int8_t* rcls = nullptr;
   double* gw = nullptr;
   int8_t* cls = nullptr;

@@ -91,6 +91,7 @@ struct DefectArgs {
   const T* u;
   const T* rhs;
   TO* r;
+  TO* rg;  // when not null: the ghost defects also stored by ghost id (extension gather)
   T inv_h2;
   uint64_t* norms;
   int nechunks;

@@ -1231,6 +1231,7 @@ __global__ void __launch_bounds__(256) k_defect(DefectArgs<T, TO> a) {
     const GhostRec rec = a.ghosts[i];
     const double v = (double)a.rhs[rec.node] - ghost_apply<D, T>(rec, a.gw + (size_t)i * K, g, a.u);
     a.r[rec.node] = (TO)v;
+    if (a.rg) a.rg[i] = (TO)v;
     p = (int)(rec.node / g.npp);
     m = fabs(v);
     if (!(m == m)) m = __longlong_as_double(0x7ff0000000000000LL);
@@ -2002,35 +2003,37 @@ static void launch_extend(const DevLevel& L, T* r, int batch, hipStream_t s) {
   }
 }
 
-// every extension node takes its composed combination of the ghost defects in r: the
-// kExtLanes lanes of a node take every kExtLanes-th term (FP64, four loads in flight each),
-// then their partial sums are added pairwise across the lanes
+// every extension node takes its composed combination of the ghost defects (rg, by ghost
+// id: a compact array that stays in the L2 cache): the kExtLanes lanes of a node take every
+// kExtLanes-th term (four loads in flight each), then their partial sums are added pairwise
+// across the lanes; weights and sums in the precision of the cycle
 constexpr int kExtLanes = 16;
 template <typename TO>
 __global__ void __launch_bounds__(256) k_ext_terms(int n, const int32_t* __restrict__ node,
                                                    const int32_t* __restrict__ off,
                                                    const int32_t* __restrict__ src,
-                                                   const double* __restrict__ wt, TO* r) {
+                                                   const TO* __restrict__ wt,
+                                                   const TO* __restrict__ rg, TO* r) {
   const int gid = blockIdx.x * 256 + threadIdx.x;
   const int i = gid / kExtLanes, lane = gid % kExtLanes;
   const int ic = i < n ? i : n - 1;
   const int t0 = off[ic], t1 = i < n ? off[ic + 1] : t0;
-  double v = 0.0;
+  TO v = 0;
   int t = t0 + lane;
   for (; t + 3 * kExtLanes < t1; t += 4 * kExtLanes) {
-    double w[4], x[4];
+    TO w[4], x[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       w[q] = wt[t + q * kExtLanes];
-      x[q] = (double)r[src[t + q * kExtLanes]];
+      x[q] = rg[src[t + q * kExtLanes]];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) v += w[q] * x[q];
   }
-  for (; t < t1; t += kExtLanes) v += wt[t] * (double)r[src[t]];
+  for (; t < t1; t += kExtLanes) v += wt[t] * rg[src[t]];
 #pragma unroll
   for (int o = kExtLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kExtLanes);
-  if (i < n && lane == 0) r[node[i]] = (TO)v;
+  if (i < n && lane == 0) r[node[i]] = v;
 }
 
 template <int D, typename T, typename TO>
@@ -2051,6 +2054,10 @@ void launch_defect(const DevLevel& L, const T* u, const T* rhs, TO* r, uint64_t*
   a.inv_h2 = (T)(1.0 / (L.g.h * L.g.h));
   a.norms = norms;
   a.nechunks = with_ext && D == 2 ? L.nechunks : 0;
+  // the extension gather reads the ghost defects from the compact array (its weights are in
+  // the cycle's precision, which is TO whenever the extension is asked for)
+  const bool gather = with_ext && !a.nechunks && L.net > 0;
+  a.rg = gather ? (TO*)L.et_rg : nullptr;
   a.hdr = L.ec_hdr;
   a.data = L.ec_data;
   a.stride = L.ec_stride;
@@ -2058,13 +2065,11 @@ void launch_defect(const DevLevel& L, const T* u, const T* rhs, TO* r, uint64_t*
   if (nb)
     hipLaunchKernelGGL((k_defect<D, T, TO>), dim3(nb), dim3(256),
                        a.nechunks ? defect_lds(L) : 0, s, a);
-  if (with_ext && !a.nechunks) {
-    if (L.net)
-      hipLaunchKernelGGL((k_ext_terms<TO>), dim3(lin_grid((int64_t)L.net * kExtLanes)), dim3(256), 0, s, L.net,
-                         L.et_node, L.et_off, L.et_src, L.et_wt, r);
-    else
-      launch_extend<TO>(L, r, batch, s);
-  }
+  if (gather)
+    hipLaunchKernelGGL((k_ext_terms<TO>), dim3(lin_grid((int64_t)L.net * kExtLanes)), dim3(256), 0, s,
+                       L.net, L.et_node, L.et_off, L.et_src, (const TO*)L.et_wt, (const TO*)L.et_rg, r);
+  else if (with_ext && !a.nechunks)
+    launch_extend<TO>(L, r, batch, s);
 }
 
 template <int D>

@@ -1209,9 +1209,9 @@ void compose_extension(const HostLevel& HL, const std::vector<int32_t>& eid,
 }
 
 // Composed extension terms of level l as flat arrays, for a gather launch after the defect
-// (the ghost defects are then read from r): per extension record its node and term range,
-// per term the ghost node and weight.  Returns false when a source is neither extension
-// node nor ghost.
+// (which also stores the ghost defects by ghost id in a compact array): per extension record
+// its node and term range, per term the ghost's index in the level's ghost list and the
+// weight.  Returns false when a source is neither extension node nor ghost.
 bool build_ext_terms(mg_handle_s* H, int l) {
   HostLevel& HL = H->host[l];
   HL.et_node.clear();
@@ -1227,6 +1227,7 @@ bool build_ext_terms(mg_handle_s* H, int l) {
     for (int a = 0; a < 3; ++a)
       if (r.src[a] >= 0 && eid[r.src[a]] < 0 && gidx[r.src[a]] < 0) return false;
   compose_extension(HL, eid, HL.et_off, HL.et_src, HL.et_wt);
+  for (int32_t& q : HL.et_src) q = gidx[q];
   for (const ExtRec& r : HL.ext) HL.et_node.push_back(r.node);
   return true;
 }

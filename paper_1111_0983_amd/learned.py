@@ -172,13 +172,14 @@ def _targets(solver, f, g, probs, device, max_cycles=1000):
 
 
 def generate(n_samples: int, seed0: int = 0, batch: int = 64, device="cuda:0", log=print,
-             threads: int = 12, max_cycles: int = GEN_CYCLES):
+             threads: int = 12, max_cycles: int = GEN_CYCLES, max_seconds: float = 0.0):
     """Solver-generated training samples.  The hierarchies of `threads` batches are built at
     once (the host setup of a batch is the slow part, and mg_setup runs outside the Python
     lock), then solved one after the other.  A batch is solved together, so its slowest
     problem sets its cycle count: a problem that has not reached the target tolerance within
     max_cycles gives no sample (counted as rejected), instead of holding its batch for
-    hundreds of cycles."""
+    hundreds of cycles.  max_seconds > 0: stop after the round that passes that time, with
+    the samples generated so far."""
     from concurrent.futures import ThreadPoolExecutor
 
     from workloads import ellipses as el
@@ -192,6 +193,8 @@ def generate(n_samples: int, seed0: int = 0, batch: int = 64, device="cuda:0", l
     last = 0
     with ThreadPoolExecutor(max_workers=threads) as pool:
         while total < n_samples:
+            if max_seconds > 0 and time.time() - t0 > max_seconds:
+                break
             want = min(batch * threads, n_samples - total)
             seeds = []
             while len(seeds) < want:  # screen the box margin cheaply before building solvers
@@ -459,6 +462,8 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser(description="train and evaluate the learned initial guess")
     ap.add_argument("--samples", type=int, default=20000)
+    ap.add_argument("--gen-seconds", type=float, default=0.0,
+                    help="stop generating training samples after this many seconds (0: no limit)")
     ap.add_argument("--seed0", type=int, default=0, help="first training seed")
     ap.add_argument("--val", type=int, default=512)
     ap.add_argument("--steps", type=int, default=6000)
@@ -478,7 +483,7 @@ def main(argv=None):
         if args.init:
             net.load(dict(np.load(args.init)))
         t0 = time.time()
-        data = generate(args.samples, seed0=args.seed0)
+        data = generate(args.samples, seed0=args.seed0, max_seconds=args.gen_seconds)
         # validation seeds far from the training seeds (about 3.5 seeds are drawn per sample)
         val = generate(args.val, seed0=VAL_SEED0) if args.val else None
         res["generate_s"] = time.time() - t0
