@@ -21,10 +21,16 @@ __device__ __forceinline__ bool in_box(int x, int y, int z, int np, int D) {
   return x >= 0 && x < np && y >= 0 && y < np && (D == 2 || (z >= 0 && z < np));
 }
 
-// Max of non-negative doubles through their IEEE bit patterns (order preserving).
+// Max of non-negative doubles through their IEEE bit patterns (order preserving).  The
+// stored maximum only grows, so a value not above the one read first cannot change it: the
+// atomic is skipped then (thousands of tiles of one problem would otherwise queue on one
+// address), and the result is the same.
 __device__ __forceinline__ void atomic_max_pos(uint64_t* dst, double v) {
   if (!(v == v)) v = __longlong_as_double(0x7ff0000000000000LL);  // NaN -> +inf
-  atomicMax((unsigned long long*)dst, (unsigned long long)__double_as_longlong(v));
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  const unsigned long long cur =
+      __hip_atomic_load((unsigned long long*)dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (bits > cur) atomicMax((unsigned long long*)dst, bits);
 }
 
 __device__ __forceinline__ double block_max(double v, double* red) {
