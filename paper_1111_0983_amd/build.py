@@ -20,7 +20,8 @@ SOURCES = [("setup.cpp", ["-ffp-contract=off", "-x", "hip"]),
            ("kernels.hip", []),
            ("capi.hip", []),
            ("cnn.hip", []),
-           ("reinit.hip", [])]
+           ("reinit.hip", []),
+           ("classify.hip", ["-ffp-contract=off"])]
 
 
 def build(verbose: bool = False) -> str:

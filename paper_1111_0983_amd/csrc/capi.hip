@@ -665,23 +665,27 @@ int setup_impl(const double* phi, const mg_bc_rule* bc, mg_bc_fn fn, void* ctx,
   H->L = L;
   H->batch = G.batch;
   H->dim = G.dim;
-  // phi may live in device memory
-  std::vector<double> phi_h((size_t)nodes * G.batch);
+  // the classification runs on the GPU: phi in host memory is uploaded first
   hipPointerAttribute_t attr;
   bool on_device = false;
   if (hipPointerGetAttributes(&attr, phi) == hipSuccess && attr.type == hipMemoryTypeDevice)
     on_device = true;
   (void)hipGetLastError();
-  if (on_device) {
-    if (hipMemcpy(phi_h.data(), phi, phi_h.size() * sizeof(double), hipMemcpyDeviceToHost) !=
-        hipSuccess) {
+  double* phi_up = nullptr;
+  if (!on_device) {
+    const size_t bytes = (size_t)nodes * G.batch * sizeof(double);
+    if (hipMalloc((void**)&phi_up, bytes) != hipSuccess) {
+      delete H;
+      return MG_ENOMEM;
+    }
+    if (hipMemcpy(phi_up, phi, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(phi_up);
       delete H;
       return MG_EHIP;
     }
-  } else {
-    std::memcpy(phi_h.data(), phi, phi_h.size() * sizeof(double));
   }
-  int rc = build_hierarchy(H, phi_h.data());
+  int rc = build_hierarchy(H, on_device ? phi : phi_up);
+  if (phi_up) (void)hipFree(phi_up);
   // relaxation and extension chunks (levels that relax: all but the coarsest); a level
   // whose chunks cannot be built keeps the per-phase boundary launches
   if (!rc)

@@ -187,6 +187,22 @@ struct HostLevel {
   std::vector<double> ainv;             // explicit inverse of each coarsest matrix
 };
 
+// One level of one problem classified on the GPU: the level's phi (unpadded node order, x
+// fastest), node classes (0 outside, 1 interior, 2 ghost), ghost records in node order (node =
+// unpadded local index) and their closest points B (3 per ghost).  phi0: the level-0 phi of
+// every problem in device memory; rule: the problem's half-space rule, or null when a caller's
+// partition decides the types (the records then have type 0, a normal for every ghost that
+// has one, and pad0 = 1 where it has none).  MG_EINVAL for a non-finite phi, MG_EGEOM for
+// geometry the discretisation does not cover.
+struct LevelClass {
+  std::vector<double> phi;
+  std::vector<int8_t> cls;
+  std::vector<GhostRec> gh;
+  std::vector<double> B;
+};
+int classify_level_gpu(const double* phi0, int D, int n0, int l, int problem, double lo, double h,
+                       const mg_bc_rule* rule, LevelClass& out);
+
 struct DevLevel {
   Geo g;
   int ntiles = 0, nghost = 0, nred = 0, nblack = 0, next = 0, ndag = 0;

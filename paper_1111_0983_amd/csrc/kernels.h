@@ -144,6 +144,7 @@ void launch_dc_update(const DevLevel& L, double* u64, const float* u32, float* u
 // dynamic LDS bytes of launch_defect for a level
 size_t defect_lds(const DevLevel& L);
 
+// phi: device memory
 int build_hierarchy(mg_handle_s* H, const double* phi);
 bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redundancy, int R);
 bool build_ext_chunks(mg_handle_s* H, int l, int own_target);

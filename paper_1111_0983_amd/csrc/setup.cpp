@@ -80,181 +80,32 @@ struct BcPartition {
   }
 };
 
-// Does the stencil of the rung (signs s) stay inside the box and on unknowns?
-bool contained(const PL& L, const int jG[3], const int8_t* s, int rung) {
-  int K = 1;
-  for (int a = 0; a < L.D; ++a) K *= 3;
-  for (int t = 0; t < K; ++t) {
-    int k[3] = {0, 0, 0}, tt = t;
-    for (int a = L.D - 1; a >= 0; --a) {
-      k[a] = tt % 3;
-      tt /= 3;
-    }
-    bool need;
-    if (rung == 1) {
-      need = true;
-    } else if (rung == 2) {
-      need = true;
-      for (int a = 0; a < L.D; ++a)
-        if (k[a] == 2) need = false;
-    } else {
-      int nz = 0, big = 0;
-      for (int a = 0; a < L.D; ++a) {
-        nz += k[a] != 0;
-        big += k[a] > 1;
-      }
-      need = nz <= 1 && big == 0;
-    }
-    if (!need) continue;
-    int j[3] = {jG[0], jG[1], jG[2]};
-    for (int a = 0; a < L.D; ++a) j[a] += s[a] * k[a];
-    if (!inbox(L, j)) return false;
-    const int8_t c = L.cls[iof(L, j)];
-    if (c != IN && c != GHOST) return false;
-  }
-  return true;
-}
-
 template <int D>
 void row_weights(const GhostRec& g, double inv_h, double* w) {
   ghost_row<D>(g, inv_h, w);
 }
 
-int classify(PL& L, const mg_grid& G, const BcPartition& part) {
-  const int D = L.D;
-  L.cls.assign(L.nn, OUT);
-  int64_t nin = 0;
-  for (int64_t i = 0; i < L.nn; ++i)
-    if (L.phi[i] < 0.0) {
-      L.cls[i] = IN;
-      ++nin;
-    }
-  if (nin == 0) return MG_EGEOM;
-  for (int64_t i = 0; i < L.nn; ++i) {
-    if (L.cls[i] != IN) continue;
-    int j[3];
-    jof(L, i, j);
-    for (int a = 0; a < D; ++a)
-      if (j[a] == 0 || j[a] == L.n) return MG_EGEOM;  // the domain must not touch the box
-  }
-  for (int64_t i = 0; i < L.nn; ++i) {
-    if (L.cls[i] == IN) continue;
-    int j[3];
-    jof(L, i, j);
-    for (int a = 0; a < D && L.cls[i] != GHOST; ++a)
-      for (int dir = -1; dir <= 1; dir += 2) {
-        int q[3] = {j[0], j[1], j[2]};
-        q[a] += dir;
-        if (inbox(L, q) && L.phi[iof(L, q)] < 0.0) L.cls[i] = GHOST;
-      }
-  }
+// The host side of a level's classification (the classes, ghost records and closest points
+// come from classify_level_gpu): the node -> ghost index map, the boundary-condition labels of
+// the ghosts and, with a caller's partition, the ghosts' types (Dirichlet ghosts keep no
+// normal; a Neumann ghost needs one).
+int finish_classes(PL& L, const BcPartition& part) {
   L.gid.assign(L.nn, -1);
   L.lab.assign(L.nn, -1);
-  L.gh.clear();
-  L.B.clear();
-  const double inv_h = 1.0 / L.h;
-  for (int64_t Gi = 0; Gi < L.nn; ++Gi) {
-    if (L.cls[Gi] != GHOST) continue;
-    int jG[3];
-    jof(L, Gi, jG);
-    double gr[3];
-    gradient(L, jG, gr);
-    double n2 = 0.0;
-    for (int a = 0; a < D; ++a) n2 += gr[a] * gr[a];
-    const double nrm = std::sqrt(n2);
-    if (!(nrm > 0.0)) return MG_EGEOM;
-    double B[3] = {0, 0, 0}, xG[3] = {0, 0, 0};
-    for (int a = 0; a < D; ++a) {
-      const double na = gr[a] / nrm;
-      xG[a] = L.lo + L.h * (double)jG[a];
-      B[a] = xG[a] - na * L.phi[Gi];  // closest boundary point, Eq. (clpt)
-    }
-    GhostRec r;
-    std::memset(&r, 0, sizeof(r));
-    r.node = (int32_t)Gi;
-    r.type = part.dirichlet(D, B) ? 1 : 0;
-    // upwind signs of Eq. (St_G); a tie goes to the side of the smaller-phi neighbour
-    int8_t pref[3] = {1, 1, 1};
-    int tiedax[3], ntied = 0;
-    for (int a = 0; a < D; ++a) {
-      const double df = B[a] - xG[a];
-      if (std::fabs(df) > 1e-12 * L.h) {
-        pref[a] = df > 0.0 ? 1 : -1;
-      } else {
-        tiedax[ntied++] = a;
-        const double pm = jG[a] > 0 ? L.phi[Gi - L.st[a]] : INFINITY;
-        const double pp = jG[a] < L.n ? L.phi[Gi + L.st[a]] : INFINITY;
-        pref[a] = pm < pp ? -1 : 1;
+  for (size_t q = 0; q < L.gh.size(); ++q) {
+    GhostRec& r = L.gh[q];
+    if (part.fn) {
+      r.type = part.dirichlet(L.D, &L.B[3 * q]) ? 1 : 0;
+      if (r.type) {
+        for (int a = 0; a < 3; ++a) r.nb[a] = 0.0;
+      } else if (r.pad0) {
+        return MG_EGEOM;  // no normal at B
       }
     }
-    // reduced-stencil ladder (Remark 3 of Sec. 2.3)
-    int rung = 0, axis = 0;
-    int8_t s[3] = {1, 1, 1};
-    for (int rg = 1; rg <= 3 && !rung; ++rg)
-      for (int m = 0; m < (1 << ntied) && !rung; ++m) {
-        for (int a = 0; a < 3; ++a) s[a] = pref[a];
-        for (int b = 0; b < ntied; ++b)
-          if (m & (1 << b)) s[tiedax[b]] = (int8_t)-pref[tiedax[b]];
-        if (contained(L, jG, s, rg)) rung = rg;
-      }
-    if (!rung) {
-      double best = INFINITY;
-      int ba = -1, bs = 0;
-      for (int a = 0; a < D; ++a)
-        for (int dir = -1; dir <= 1; dir += 2) {
-          int q[3] = {jG[0], jG[1], jG[2]};
-          q[a] += dir;
-          if (!inbox(L, q)) continue;
-          const int64_t Q = iof(L, q);
-          if (L.cls[Q] != IN) continue;
-          if (L.phi[Q] < best) {
-            best = L.phi[Q];
-            ba = a;
-            bs = dir;
-          }
-        }
-      if (ba < 0) return MG_EGEOM;
-      for (int a = 0; a < 3; ++a) s[a] = pref[a];
-      s[ba] = (int8_t)bs;
-      axis = ba;
-      rung = 4;
-    }
-    r.rung = (int8_t)rung;
-    r.axis = (int8_t)axis;
-    for (int a = 0; a < 3; ++a) r.s[a] = a < D ? s[a] : 0;
-    for (int a = 0; a < D; ++a) r.xi[a] = (double)s[a] * (B[a] - xG[a]) / L.h;
-    if (!r.type) {
-      // unit normal at B from the same interpolant of phi (Eq. (neu2d))
-      double gp[3] = {0, 0, 0};
-      for (int a = 0; a < D; ++a) {
-        double e[3] = {0, 0, 0};
-        e[a] = 1.0;
-        double w[27];
-        uint32_t used = D == 2 ? stencil_weights<2>(rung, axis, s, r.xi, inv_h, 0, e, w)
-                               : stencil_weights<3>(rung, axis, s, r.xi, inv_h, 0, e, w);
-        int K = D == 2 ? 9 : 27;
-        for (int t = 0; t < K; ++t) {
-          if (!(used >> t & 1u)) continue;
-          int64_t off = 0, tt = t;
-          for (int c = D - 1; c >= 0; --c) {
-            off += (int64_t)s[c] * (tt % 3) * L.st[c];
-            tt /= 3;
-          }
-          gp[a] += w[t] * L.phi[Gi + off];
-        }
-      }
-      double g2 = 0.0;
-      for (int a = 0; a < D; ++a) g2 += gp[a] * gp[a];
-      const double gn = std::sqrt(g2);
-      if (!(gn > 0.0)) return MG_EGEOM;
-      for (int a = 0; a < D; ++a) r.nb[a] = gp[a] / gn;
-    }
-    L.gid[Gi] = (int32_t)L.gh.size();
-    L.lab[Gi] = r.type;
-    L.gh.push_back(r);
-    for (int a = 0; a < 3; ++a) L.B.push_back(a < D ? B[a] : 0.0);
+    r.pad0 = 0;
+    L.gid[r.node] = (int32_t)q;
+    L.lab[r.node] = r.type;
   }
-  (void)G;
   return MG_OK;
 }
 
@@ -495,7 +346,7 @@ int invert(std::vector<double>& A, int n, std::vector<double>& inv) {
 
 }  // namespace
 
-// Build every level of every problem; phi is host memory, batch * (n+1)^D values.
+// Build every level of every problem; phi is device memory, batch * (n+1)^D values.
 int build_hierarchy(mg_handle_s* H, const double* phi) {
   const mg_grid& G = H->grid;
   const int D = G.dim, batch = G.batch, L = H->L;
@@ -520,9 +371,6 @@ int build_hierarchy(mg_handle_s* H, const double* phi) {
     H->host[l].umap_off.assign(1, 0);
     H->host[l].ainv_off.assign(1, 0);
   }
-  const int64_t np0 = (int64_t)G.n + 1;
-  int64_t nn0 = 1;
-  for (int a = 0; a < D; ++a) nn0 *= np0;
   for (int p = 0; p < batch; ++p) {
     const BcPartition part{H->bc_fn ? nullptr : &H->bc[p], H->bc_fn, H->bc_ctx, p};
     std::vector<PL> lev(L + 1);
@@ -538,19 +386,15 @@ int build_hierarchy(mg_handle_s* H, const double* phi) {
         V.st[a] = V.nn;
         V.nn *= V.np;
       }
-      V.phi.resize(V.nn);
-      const int64_t stride = (int64_t)1 << l;
-      for (int64_t i = 0; i < V.nn; ++i) {
-        int j[3];
-        jof(V, i, j);
-        int64_t fi = 0;
-        for (int a = D - 1; a >= 0; --a) fi = fi * np0 + (int64_t)j[a] * stride;
-        const double v = phi[(size_t)p * nn0 + fi];
-        if (!std::isfinite(v)) return MG_EINVAL;
-        V.phi[i] = v;
-      }
-      int rc = classify(V, G, part);
+      // classes, ghost records and closest points on the GPU (Sec. 2.2-2.3)
+      LevelClass lc;
+      int rc = classify_level_gpu(phi, D, G.n, l, p, G.lo, V.h, H->bc_fn ? nullptr : &H->bc[p], lc);
       if (rc) return rc;
+      V.phi = std::move(lc.phi);
+      V.cls = std::move(lc.cls);
+      V.gh = std::move(lc.gh);
+      V.B = std::move(lc.B);
+      if ((rc = finish_classes(V, part))) return rc;
     }
     for (int l = 0; l <= L; ++l) {
       PL& V = lev[l];
