@@ -4,6 +4,7 @@
 // (interior / ghost, boundary-condition type, upwind signs, processing order) is an exact
 // function of phi.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <thread>
@@ -794,16 +795,34 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
   for (size_t v = 0; v < nn; ++v)
     if (role[v] >= 1 && role[v] <= 3) U.push_back({morton_key(g, D, (int64_t)v), (int32_t)v});
   std::sort(U.begin(), U.end());
+  const double cNh = H->grid.cN * g.h;
+  // every launch's chunk set (phases [p0, p0 + R)) is built on a thread of its own, into its
+  // own arrays, then appended in launch order with its offsets moved: the data is that of a
+  // sequential build
+  struct RangeOut {
+    std::vector<int32_t> hdr, data;
+    int nchunks = 0, smax = 0, stride = 0;
+    int64_t entries = 0, nown = 0;
+    bool ok = true;
+  };
+  const int S = P / R;
+  std::vector<RangeOut> outs(S);
+  // a failed range ends the others early (the build fails as a whole)
+  std::atomic<bool> failed{false};
+  auto build_range = [&](int r) {
+  RangeOut& O = outs[r];
+  const int p0 = r * R, p1 = p0 + R;
   std::vector<int16_t> need(nn, -2);
   std::vector<int32_t> lid(nn, -1);
   std::vector<char> owned(nn, 0);
   std::vector<int32_t> touched, rd;
   std::vector<int64_t> keyed;
-  const double cNh = H->grid.cN * g.h;
-  for (int p0 = 0; p0 < P; p0 += R) {
-  const int p1 = p0 + R;
   std::vector<std::pair<size_t, size_t>> pending = initial_runs(U, own_target);
   while (!pending.empty()) {
+    if (failed.load(std::memory_order_relaxed)) {
+      O.ok = false;
+      return;
+    }
     const auto [a, b] = pending.back();
     pending.pop_back();
     touched.clear();
@@ -865,7 +884,11 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
         lid[v] = -1;
         owned[v] = 0;
       }
-      if (b - a <= 16) return false;
+      if (b - a <= 16) {
+        O.ok = false;
+        failed = true;
+        return;
+      }
       const size_t m = a + (b - a) / 2;
       pending.push_back({m, b});
       pending.push_back({a, m});
@@ -873,7 +896,7 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     }
     // per-chunk data: node, phase mask (bit 31: owned), interior neighbour pairs, ghost
     // stencil ids and weights (transposed: tap-major), ghost constants
-    std::vector<int32_t>& Dv = HL.bc_data;
+    std::vector<int32_t>& Dv = O.data;
     pad_even(Dv);
     const int32_t off = (int32_t)Dv.size();
     for (int32_t v : touched) Dv.push_back(v);
@@ -977,31 +1000,59 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
       const BandFixed F = band_fixed(D, l < H->L, l > 0);
       to_fixed_layout(Dv, off, D, ns, ng, nr, nbk, gid_off, gw_off, gc_off, pc_off, rs_off,
                       l < H->L, l > 0, w32);
-      HL.bc_stride = F.stride;
+      O.stride = F.stride;
       const int32_t hdr[kBandHdr] = {F.NSW, (int32_t)counts, off, off + F.GID, off + F.GW,
                                      off + F.GC, l < H->L ? off + F.PC : -1, l > 0 ? off + F.RS : -1};
-      HL.bc_hdr.insert(HL.bc_hdr.end(), hdr, hdr + kBandHdr);
-      HL.bc_smax = F.NSW;
+      O.hdr.insert(O.hdr.end(), hdr, hdr + kBandHdr);
+      O.smax = F.NSW;
     } else {
       const int32_t hdr[kBandHdr] = {ns, (int32_t)counts, off, gid_off, gw_off, gc_off,
                                      l < H->L ? pc_off : -1, l > 0 ? rs_off : -1};
-      HL.bc_hdr.insert(HL.bc_hdr.end(), hdr, hdr + kBandHdr);
-      HL.bc_smax = std::max(HL.bc_smax, ns);
+      O.hdr.insert(O.hdr.end(), hdr, hdr + kBandHdr);
+      O.smax = std::max(O.smax, ns);
     }
-    ++HL.bc_nchunks;
-    HL.bc_entries += ns;
-    HL.bc_nown += (int)(b - a);
-    // over the redundancy budget already: this phase range fails (early exit)
-    if ((double)HL.bc_entries > max_redundancy * (double)(P / R) * (double)U.size()) return false;
+    ++O.nchunks;
+    O.entries += ns;
+    O.nown += (int64_t)(b - a);
+    // over the whole redundancy budget already: the build fails (early exit)
+    if ((double)O.entries > max_redundancy * (double)S * (double)U.size()) {
+      O.ok = false;
+      failed = true;
+      return;
+    }
     for (int32_t v : touched) {
       need[v] = -2;
       lid[v] = -1;
       owned[v] = 0;
     }
   }
-  HL.bc_sub.push_back(HL.bc_nchunks);
+  };
+  if (S == 1) {
+    build_range(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int r = 0; r < S; ++r) th.emplace_back(build_range, r);
+    for (auto& t : th) t.join();
   }
-  const int S = P / R;
+  for (const RangeOut& O : outs)
+    if (!O.ok) return false;
+  for (const RangeOut& O : outs) {
+    pad_even(HL.bc_data);
+    const int32_t base = (int32_t)HL.bc_data.size();
+    HL.bc_data.insert(HL.bc_data.end(), O.data.begin(), O.data.end());
+    // header words 2.. are offsets into the data (-1: absent)
+    for (int c = 0; c < O.nchunks; ++c)
+      for (int q = 0; q < kBandHdr; ++q) {
+        const int32_t v = O.hdr[(size_t)c * kBandHdr + q];
+        HL.bc_hdr.push_back(q >= 2 && v >= 0 ? v + base : v);
+      }
+    HL.bc_nchunks += O.nchunks;
+    HL.bc_entries += O.entries;
+    HL.bc_nown += (int)O.nown;
+    HL.bc_smax = std::max(HL.bc_smax, O.smax);
+    if (O.stride) HL.bc_stride = O.stride;
+    HL.bc_sub.push_back(HL.bc_nchunks);
+  }
   if (!U.empty() && (double)HL.bc_entries > max_redundancy * (double)S * (double)U.size())
     return false;
   return true;
