@@ -494,17 +494,30 @@ int build_hierarchy(mg_handle_s* H, const double* phi) {
         HF.ext.push_back(r);
       }
       HF.ext_off.push_back((int32_t)HF.ext.size());
-      // restriction codes of the coarse nodes
+      // restriction codes of the coarse nodes (each node's own box search: split over
+      // threads, every thread writing its own nodes)
       const Geo& gc = HC.g;
       const int64_t basec = (int64_t)p * gc.npp;
-      for (int64_t X = 0; X < C.nn; ++X) {
-        if (C.cls[X] == OUT) continue;
-        int jc[3], jf[3] = {0, 0, 0};
-        jof(C, X, jc);
-        for (int a = 0; a < D; ++a) jf[a] = 2 * jc[a];
-        const bool inside = C.cls[X] == IN;
-        const int lab = (!inside && G.split) ? F.lab[iof(F, jf)] : -1;
-        HC.rcode[basec + jc[0] + gc.st[1] * jc[1] + gc.st[2] * jc[2]] = box_code(F, jf, inside, lab);
+      auto codes = [&](int64_t X0, int64_t X1) {
+        for (int64_t X = X0; X < X1; ++X) {
+          if (C.cls[X] == OUT) continue;
+          int jc[3], jf[3] = {0, 0, 0};
+          jof(C, X, jc);
+          for (int a = 0; a < D; ++a) jf[a] = 2 * jc[a];
+          const bool inside = C.cls[X] == IN;
+          const int lab = (!inside && G.split) ? F.lab[iof(F, jf)] : -1;
+          HC.rcode[basec + jc[0] + gc.st[1] * jc[1] + gc.st[2] * jc[2]] = box_code(F, jf, inside, lab);
+        }
+      };
+      const int nt = C.nn < ((int64_t)1 << 16)
+                         ? 1
+                         : (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+      if (nt == 1) {
+        codes(0, C.nn);
+      } else {
+        std::vector<std::thread> th;
+        for (int t = 0; t < nt; ++t) th.emplace_back(codes, C.nn * t / nt, C.nn * (t + 1) / nt);
+        for (auto& x : th) x.join();
       }
     }
     // the coarsest system and its inverse
