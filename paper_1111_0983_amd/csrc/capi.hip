@@ -692,14 +692,13 @@ int setup_impl(const double* phi, const mg_bc_rule* bc, mg_bc_fn fn, void* ctx,
     for (int l = 0; l < L; ++l) {
       HostLevel& S = H->host[l];
       // the largest number of phases per launch whose chunks fit (all of a relaxation in
-      // one launch where possible)
-      bool built = false;
+      // one launch where possible); the comparison relaxations sweep the band on their own
+      // (no chunks)
       const int P = 3 + 3 * H->grid.lambda;
-      // the comparison relaxations sweep the band on their own (no chunks)
-      for (int R = P; R >= 3 && !built && H->grid.smoother == 0; R -= 3)
-        if (P % R == 0 && P / R <= 7)
-          built = build_band_chunks(H, l, kChunkOwn * (H->dim == 2 ? 1 : 2),
-                                    H->dim == 2 ? kChunkRedundancy2D : kChunkRedundancy3D, R);
+      const bool built =
+          H->grid.smoother == 0 &&
+          build_band_chunks(H, l, kChunkOwn * (H->dim == 2 ? 1 : 2),
+                            H->dim == 2 ? kChunkRedundancy2D : kChunkRedundancy3D, P);
       if (!built) {
         S.bc_nchunks = 0;
         S.bc_hdr.clear();

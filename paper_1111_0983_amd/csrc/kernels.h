@@ -146,7 +146,9 @@ size_t defect_lds(const DevLevel& L);
 
 // phi: device memory
 int build_hierarchy(mg_handle_s* H, const double* phi);
-bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redundancy, int R);
+// relaxation chunks of level l with the largest phase count per launch, at most Rmax, that
+// fits (HostLevel::bc_range); false when none fits
+bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redundancy, int Rmax);
 bool build_ext_chunks(mg_handle_s* H, int l, int own_target);
 bool build_ext_terms(mg_handle_s* H, int l);
 

@@ -744,7 +744,7 @@ std::vector<std::pair<size_t, size_t>> initial_runs(const std::vector<std::pair<
 // not fit, or when the redundant work exceeds max_redundancy times the owned nodes per launch
 // (the caller then tries fewer phases per launch, and the level finally relaxes its boundary
 // part with one launch per phase).
-bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redundancy, int R) {
+bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redundancy, int Rmax) {
   HostLevel& HL = H->host[l];
   const int D = H->dim, lambda = H->grid.lambda;
   const Geo& g = HL.g;
@@ -753,18 +753,6 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
   const size_t nn = HL.cls.size();
   // FP32 cycles read FP32 ghost weights
   const bool w32 = H->grid.precision == MG_FP32_DC;
-  HL.bc_hdr.clear();
-  HL.bc_data.clear();
-  HL.bc_nchunks = 0;
-  HL.bc_smax = 0;
-  HL.bc_stride = 0;
-  HL.bc_entries = 0;
-  HL.bc_nown = 0;
-  HL.bc_range = R;
-  HL.bc_sub.assign(1, 0);
-  // launches of R phases each (whole sweeps); mask bits: R phases, then D + 2^D
-  // interpolation bits, bit 30 band or ghost node, bit 31 owned
-  if (R % 3 != 0 || P % R != 0 || R + D + (1 << D) > 30) return false;
   // role of a node: 1 red band, 2 black band, 3 ghost, 4 red interior off the band,
   // 5 black interior off the band
   std::vector<int8_t> role(nn, 0);
@@ -809,7 +797,22 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     if (role[v] >= 1 && role[v] <= 3) U.push_back({morton_key(g, D, (int64_t)v), (int32_t)v});
   std::sort(U.begin(), U.end());
   const double cNh = H->grid.cN * g.h;
-  // every launch's chunk set (phases [p0, p0 + R)) is built on a thread of its own, into its
+  // the scratch marks of a closure are indexed by a compact id over the interior and ghost
+  // nodes (the only nodes a closure reaches); every run restores the marks it set, so a
+  // thread's marks serve every attempt below
+  const int hw = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const std::vector<std::pair<size_t, size_t>> runs0 = initial_runs(U, own_target);
+  std::vector<int32_t> cid(nn, -1);
+  int32_t ncid = 0;
+  for (size_t v = 0; v < nn; ++v)
+    if (role[v] != 0) cid[v] = ncid++;
+  struct Scratch {
+    std::vector<int16_t> need;
+    std::vector<int32_t> lid;
+    std::vector<char> owned;
+  };
+  std::vector<Scratch> pool;
+  // every launch's chunk set (phases [p0, p0 + R)) is built on threads of its own, into its
   // own arrays, then appended in launch order with its offsets moved: the data is that of a
   // sequential build
   struct RangeOut {
@@ -818,19 +821,42 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     int64_t entries = 0, nown = 0;
     bool ok = true;
   };
+  // one attempt: launches of R phases each (whole sweeps); mask bits: R phases, then D + 2^D
+  // interpolation bits, bit 30 band or ghost node, bit 31 owned
+  auto attempt = [&](int R) -> bool {
+  HL.bc_hdr.clear();
+  HL.bc_data.clear();
+  HL.bc_nchunks = 0;
+  HL.bc_smax = 0;
+  HL.bc_stride = 0;
+  HL.bc_entries = 0;
+  HL.bc_nown = 0;
+  HL.bc_range = R;
+  HL.bc_sub.assign(1, 0);
   const int S = P / R;
-  std::vector<RangeOut> outs(S);
-  // a failed range ends the others early (the build fails as a whole)
+  // within a launch, its initial owned runs split in NG groups, one thread each
+  const int NG = std::max(1, std::min(hw / S, (int)(runs0.size() / 64)));
+  if (pool.size() < (size_t)S * NG) pool.resize((size_t)S * NG);
+  std::vector<RangeOut> outs((size_t)S * NG);
+  // a failed group ends the others early (the build fails as a whole)
   std::atomic<bool> failed{false};
-  auto build_range = [&](int r) {
-  RangeOut& O = outs[r];
+  auto build_group = [&](int r, int grp) {
+  RangeOut& O = outs[(size_t)r * NG + grp];
   const int p0 = r * R, p1 = p0 + R;
-  std::vector<int16_t> need(nn, -2);
-  std::vector<int32_t> lid(nn, -1);
-  std::vector<char> owned(nn, 0);
+  Scratch& sc = pool[(size_t)r * NG + grp];
+  if (sc.need.empty()) {
+    sc.need.assign(ncid, -2);
+    sc.lid.assign(ncid, -1);
+    sc.owned.assign(ncid, 0);
+  }
+  std::vector<int16_t>& need = sc.need;
+  std::vector<int32_t>& lid = sc.lid;
+  std::vector<char>& owned = sc.owned;
   std::vector<int32_t> touched, rd;
   std::vector<int64_t> keyed;
-  std::vector<std::pair<size_t, size_t>> pending = initial_runs(U, own_target);
+  // this group's initial runs, processed from the last as the sequential build does
+  const size_t g0 = runs0.size() * grp / NG, g1 = runs0.size() * (grp + 1) / NG;
+  std::vector<std::pair<size_t, size_t>> pending(runs0.begin() + g0, runs0.begin() + g1);
   while (!pending.empty()) {
     if (failed.load(std::memory_order_relaxed)) {
       O.ok = false;
@@ -840,27 +866,46 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     pending.pop_back();
     touched.clear();
     for (size_t i = a; i < b; ++i) {
-      need[U[i].second] = (int16_t)(p1 - 1);
-      owned[U[i].second] = 1;
+      need[cid[U[i].second]] = (int16_t)(p1 - 1);
+      owned[cid[U[i].second]] = 1;
       touched.push_back(U[i].second);
     }
-    for (int p = p1 - 1; p >= p0; --p) {
+    // a closure with more entries than a chunk holds cannot fit (the slot checks below would
+    // reject it): it stops growing there and the run is split at once
+    bool over = false;
+    for (int p = p1 - 1; p >= p0 && !over; --p) {
       const size_t nt = touched.size();
-      for (size_t i = 0; i < nt; ++i) {
+      for (size_t i = 0; i < nt && !over; ++i) {
         const int32_t v = touched[i];
-        if (!updates(role[v], p) || need[v] < p) continue;
+        if (!updates(role[v], p) || need[cid[v]] < p) continue;
         reads(v, rd);
         for (int32_t w : rd) {
-          if (need[w] == -2) touched.push_back(w);
-          if (need[w] < p - 1) need[w] = (int16_t)(p - 1);
+          if (need[cid[w]] == -2) touched.push_back(w);
+          if (need[cid[w]] < p - 1) need[cid[w]] = (int16_t)(p - 1);
         }
+        over = touched.size() > (size_t)band_max_entries(D);
       }
+    }
+    if (over) {
+      for (int32_t v : touched) {
+        need[cid[v]] = -2;
+        owned[cid[v]] = 0;
+      }
+      if (b - a <= 16) {
+        O.ok = false;
+        failed = true;
+        return;
+      }
+      const size_t m = a + (b - a) / 2;
+      pending.push_back({m, b});
+      pending.push_back({a, m});
+      continue;
     }
     // entries: the updated ghosts, the red-updated, the black-updated, the read-only nodes;
     // each run by node index
     auto run_of = [&](int32_t v) {
       for (int p = p0; p < p1; ++p)
-        if (updates(role[v], p) && need[v] >= p) return p % 3 == 2 ? 0 : (p % 3 == 0 ? 1 : 2);
+        if (updates(role[v], p) && need[cid[v]] >= p) return p % 3 == 2 ? 0 : (p % 3 == 0 ? 1 : 2);
       return 3;
     };
     // (run, node) keys, each run computed once
@@ -878,24 +923,24 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     bool ok = ng <= W && nr <= band_colour_slots(D) * W && nbk <= band_colour_slots(D) * W &&
               cnt[3] <= band_halo_slots(D) * W;
     for (int i = ns - cnt[3]; i < ns; ++i)
-      if (owned[touched[i]]) ok = false;  // an owned node is always updated
+      if (owned[cid[touched[i]]]) ok = false;  // an owned node is always updated
     if (ok) {
-      for (int i = 0; i < ns; ++i) lid[touched[i]] = i;
+      for (int i = 0; i < ns; ++i) lid[cid[touched[i]]] = i;
       for (int i = 0; i < ns - cnt[3] && ok; ++i) {
         const int32_t v = touched[i];
         if (role[v] == 3) continue;
         for (int a2 = 0; a2 < D; ++a2)
-          if (lid[v - g.st[a2]] < 0 || lid[v + g.st[a2]] < 0) ok = false;
+          if (lid[cid[v - g.st[a2]]] < 0 || lid[cid[v + g.st[a2]]] < 0) ok = false;
       }
       for (int j = 0; j < ng && ok; ++j)
         for (int t = 0; t < K; ++t)
-          if (HL.gw[(size_t)gidx[touched[j]] * K + t] != 0.0 && lid[tap_node(touched[j], t)] < 0) ok = false;
+          if (HL.gw[(size_t)gidx[touched[j]] * K + t] != 0.0 && lid[cid[tap_node(touched[j], t)]] < 0) ok = false;
     }
     if (!ok) {
       for (int32_t v : touched) {
-        need[v] = -2;
-        lid[v] = -1;
-        owned[v] = 0;
+        need[cid[v]] = -2;
+        lid[cid[v]] = -1;
+        owned[cid[v]] = 0;
       }
       if (b - a <= 16) {
         O.ok = false;
@@ -914,17 +959,17 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     const int32_t off = (int32_t)Dv.size();
     for (int32_t v : touched) Dv.push_back(v);
     for (int32_t v : touched) {
-      uint32_t m = owned[v] ? 0x80000000u : 0u;
+      uint32_t m = owned[cid[v]] ? 0x80000000u : 0u;
       if (role[v] >= 1 && role[v] <= 3) m |= 0x40000000u;
       for (int p = p0; p < p1; ++p)
-        if (updates(role[v], p) && need[v] >= p) m |= 1u << (p - p0);
+        if (updates(role[v], p) && need[cid[v]] >= p) m |= 1u << (p - p0);
       Dv.push_back((int32_t)m);
     }
     for (int32_t v : touched)
       for (int a2 = 0; a2 < D; ++a2) {
         const bool relaxed = role[v] != 3 && role[v] != 0;
-        const int lo = relaxed && lid[v - g.st[a2]] >= 0 ? lid[v - g.st[a2]] : 0;
-        const int hi = relaxed && lid[v + g.st[a2]] >= 0 ? lid[v + g.st[a2]] : 0;
+        const int lo = relaxed && lid[cid[v - g.st[a2]]] >= 0 ? lid[cid[v - g.st[a2]]] : 0;
+        const int hi = relaxed && lid[cid[v + g.st[a2]]] >= 0 ? lid[cid[v + g.st[a2]]] : 0;
         Dv.push_back(pack16(lo, hi));
       }
     // interpolation candidates of every entry (Sec. 2.6.1): one word, the coarse node index
@@ -968,7 +1013,7 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     auto tap_addr = [&](int j, int t) {
       if (t >= K) return 0;
       const double w = HL.gw[(size_t)gidx[touched[j]] * K + t];
-      const int id = w != 0.0 ? lid[tap_node(touched[j], t)] : j;
+      const int id = w != 0.0 ? lid[cid[tap_node(touched[j], t)]] : j;
       return id < ng ? ns + id : id;
     };
     for (int t = 0; t < K; t += 2)
@@ -1027,29 +1072,34 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     ++O.nchunks;
     O.entries += ns;
     O.nown += (int64_t)(b - a);
-    // over the whole redundancy budget already: the build fails (early exit)
+    for (int32_t v : touched) {
+      need[cid[v]] = -2;
+      lid[cid[v]] = -1;
+      owned[cid[v]] = 0;
+    }
+    // over the whole redundancy budget already: the build fails (early exit; the marks are
+    // restored, so the thread's scratch serves the next attempt)
     if ((double)O.entries > max_redundancy * (double)S * (double)U.size()) {
       O.ok = false;
       failed = true;
       return;
     }
-    for (int32_t v : touched) {
-      need[v] = -2;
-      lid[v] = -1;
-      owned[v] = 0;
-    }
   }
   };
-  if (S == 1) {
-    build_range(0);
+  if (S * NG == 1) {
+    build_group(0, 0);
   } else {
     std::vector<std::thread> th;
-    for (int r = 0; r < S; ++r) th.emplace_back(build_range, r);
+    for (int r = 0; r < S; ++r)
+      for (int grp = 0; grp < NG; ++grp) th.emplace_back(build_group, r, grp);
     for (auto& t : th) t.join();
   }
   for (const RangeOut& O : outs)
     if (!O.ok) return false;
-  for (const RangeOut& O : outs) {
+  // launch by launch; within a launch the groups from the last (the sequential order)
+  for (int r = 0; r < S; ++r) {
+  for (int grp = NG - 1; grp >= 0; --grp) {
+    const RangeOut& O = outs[(size_t)r * NG + grp];
     pad_even(HL.bc_data);
     const int32_t base = (int32_t)HL.bc_data.size();
     HL.bc_data.insert(HL.bc_data.end(), O.data.begin(), O.data.end());
@@ -1064,11 +1114,22 @@ bool build_band_chunks(mg_handle_s* H, int l, int own_target, double max_redunda
     HL.bc_nown += (int)O.nown;
     HL.bc_smax = std::max(HL.bc_smax, O.smax);
     if (O.stride) HL.bc_stride = O.stride;
-    HL.bc_sub.push_back(HL.bc_nchunks);
+  }
+  HL.bc_sub.push_back(HL.bc_nchunks);
   }
   if (!U.empty() && (double)HL.bc_entries > max_redundancy * (double)S * (double)U.size())
     return false;
   return true;
+  };
+  // the largest number of phases per launch (whole sweeps dividing the relaxation's phases,
+  // at most 7 launches) whose chunks fit
+  for (int R = std::min(Rmax, P); R >= 3; R -= 3)
+    if (P % R == 0 && P / R <= 7 && R + D + (1 << D) <= 30 && attempt(R)) return true;
+  HL.bc_hdr.clear();
+  HL.bc_data.clear();
+  HL.bc_sub.clear();
+  HL.bc_nchunks = 0;
+  return false;
 }
 
 // Composed extension weights of level l.  The records are stored in DAG order per problem,

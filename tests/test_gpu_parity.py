@@ -146,6 +146,30 @@ def test_cycle_iterates_match_oracle(name, kw):
         assert err <= 1e-12, (k, err)
 
 
+def test_tank_cycle_iterates_match_oracle():
+    """The moving tank at 128^3 (FP64), a hierarchy on which the chunk builder's attempts
+    fail in both ways before one fits (level 0: 18 phases per launch, then 9 over the
+    redundancy budget, then 6; level 2: 9 after 18): red-black V(2,1) iterates after each of
+    three cycles against the oracle's, from a random start and right-hand side."""
+    gm = _gm()
+    from workloads import tank
+    phi = np.ascontiguousarray(tank.TankSequence(128).phi(2, "cpu").numpy(), dtype=np.float64)
+    s = gm.Solver(torch.from_numpy(phi).to(DEV), [tank.RULE], gm.mg_grid_default(3, 128, 16))
+    o = Oracle(phi, default_grid(3, 128, 16, ordering=1), tank.RULE)
+    assert [s.level(l)["nghost"] for l in range(s.nlev)] == [o.ghosts(l)["node"].size
+                                                            for l in range(o.nlev)]
+    c, _ = o.cls(0)
+    rng = np.random.default_rng(4)
+    rhs = np.where(c > 0, rng.normal(size=c.size), 0.0)
+    uo = np.where(c > 0, rng.uniform(-1, 1, c.size), 0.0)
+    ug = _t(uo)
+    for k in range(3):
+        o.cycle(uo, rhs)
+        s.cycles(_t(rhs), _t(rhs), ug, 1)
+        err = np.abs(ug.cpu().numpy() - uo).max() / np.abs(uo).max()
+        assert err <= 1e-12, (k, err)
+
+
 @pytest.mark.parametrize("name", ["disk64", "flower256", "flower200ish", "torus32"])
 def test_fp64_solution_matches_oracle(name):
     s, o, dom, dim, n, rule, sol = _build(name)
