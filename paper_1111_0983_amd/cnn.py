@@ -35,6 +35,10 @@ _lib.mg_cnn_target.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]
 _lib.mg_cnn_apply.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
 
 LAYERS = ((4, 32, 1), (32, 32, 2), (32, 32, 4), (32, 32, 8), (32, 1, 1))
+# a deeper variant whose receptive field (131 nodes) covers the whole 65 x 65 level: every
+# prediction sees the whole domain, its boundary data and its right-hand side
+LAYERS_LARGE = ((4, 32, 1), (32, 32, 2), (32, 32, 4), (32, 32, 8), (32, 32, 16), (32, 32, 32),
+                (32, 32, 1), (32, 1, 1))
 
 
 def _p(t):

@@ -473,9 +473,11 @@ def main(argv=None):
     ap.add_argument("--out", default="gpurun_out/learned")
     ap.add_argument("--init", default=None, help="start training from these weights")
     ap.add_argument("--weights", default=None, help="skip training, load these weights")
+    ap.add_argument("--arch", choices=["base", "large"], default="base",
+                    help="base: 5 layers, receptive field 33; large: 8 layers, field 131")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
-    net = cnn.GuessNet(seed=0)
+    net = cnn.GuessNet(seed=0, layers=cnn.LAYERS_LARGE if args.arch == "large" else cnn.LAYERS)
     res = {}
     if args.weights:
         net.load(dict(np.load(args.weights)))
