@@ -27,12 +27,18 @@ def _rounded(a):
     return _bf(a).float().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("cin,cout,dil,f32", [(4, 32, 1, False), (32, 32, 4, False),
-                                              (32, 1, 1, True), (32, 32, 8, False)])
-def test_conv_forward_matches_reference(cin, cout, dil, f32):
+@pytest.mark.parametrize("cin,cout,dil,f32,hw", [(4, 32, 1, False, (33, 29)),
+                                                 (32, 32, 4, False, (33, 29)),
+                                                 (32, 1, 1, True, (33, 29)),
+                                                 (32, 32, 8, False, (33, 29)),
+                                                 # the large network's dilations on its 65 x 65
+                                                 # grid (taps 32 nodes away reach the padding)
+                                                 (32, 32, 16, False, (65, 65)),
+                                                 (32, 32, 32, False, (65, 65))])
+def test_conv_forward_matches_reference(cin, cout, dil, f32, hw):
     from paper_1111_0983_amd import cnn
     rng = np.random.default_rng(cin + cout + dil)
-    B, H, W = 2, 33, 29
+    B, (H, W) = 2, hw
     x = _rounded(rng.normal(size=(B, H, W, cin)))
     w = rng.normal(0, (2.0 / (9 * cin)) ** 0.5, (cout, 3, 3, cin))
     b = rng.normal(0, 0.1, cout)
@@ -106,16 +112,19 @@ def test_training_reduces_loss():
     assert losses[-1] < 0.5 * losses[0], losses[::10]
 
 
-def test_gradients_elementwise_at_training_shape():
-    """Weight and bias gradients of every layer, element by element, at the training shape
-    (64 problems of 65 x 65 nodes, the 4 -> 32 -> 32 -> 32 -> 32 -> 1 network) against the
-    FP64 reference with BF16 rounding at the points where the kernels store BF16 (weights,
-    hidden activations, loss gradient, data gradients): the remaining differences are FP32
-    accumulation and the rare BF16 rounding decision it flips."""
+@pytest.mark.parametrize("arch", ["base", "large"])
+def test_gradients_elementwise_at_training_shape(arch):
+    """Weight and bias gradients of every layer at the training shape (64 problems of 65 x 65
+    nodes; the 4 -> 32 -> 32 -> 32 -> 32 -> 1 network element by element, and the 8-layer one
+    with dilations up to 32 layer by layer) against the FP64 reference with BF16 rounding at
+    the points where the kernels store BF16 (weights, hidden activations, loss gradient, data
+    gradients): the remaining differences are FP32 accumulation and the rare BF16 rounding
+    decision it flips."""
     from paper_1111_0983_amd import cnn
     rng = np.random.default_rng(11)
     B, H, W = 64, 65, 65
-    net = cnn.GuessNet(seed=5, device=DEV)
+    net = cnn.GuessNet(seed=5, device=DEV,
+                       layers=cnn.LAYERS_LARGE if arch == "large" else cnn.LAYERS)
     cin, cout, _ = net.layers[-1]
     net.w[-1].copy_(torch.from_numpy(rng.normal(0.0, (2.0 / (9 * cin)) ** 0.5,
                                                 size=cout * 9 * cin).astype(np.float32)))
@@ -138,8 +147,14 @@ def test_gradients_elementwise_at_training_shape():
     loss, rgrads, rpred = co.loss_and_grads(params, x, tgt, mask, dils, bf16_points=True)
     assert abs(out[0].item() - loss) <= 1e-4 * loss
     gp = pred.cpu().numpy().reshape(B, H, W)
-    assert np.abs(gp - rpred).max() <= 2e-3 * np.abs(rpred).max()
     L = len(net.layers)
+    # the prediction passes through L - 1 hidden activations stored in BF16; at each, FP32
+    # accumulation in another order can flip a rounding decision (one BF16 step, 2^-7
+    # relative, on that activation), and an output sums the flips of its receptive field:
+    # the check allows 2^-10 of the largest prediction per stored stage
+    e_pred = np.abs(gp - rpred).max() / np.abs(rpred).max()
+    print(f"prediction: max error {e_pred:.2e} of the largest value")
+    assert e_pred <= (L - 1) * 2.0 ** -10, e_pred
     errs = []
     for i, ((dw, db), (rdw, rdb)) in enumerate(zip(grads, rgrads)):
         ci, co_, _ = net.layers[i]
@@ -147,15 +162,100 @@ def test_gradients_elementwise_at_training_shape():
         gb = db.cpu().numpy()
         ew = np.abs(gw - rdw) / (np.abs(rdw) + 1e-2 * np.abs(rdw).max())
         eb = np.abs(gb - rdb) / (np.abs(rdb) + 1e-2 * np.abs(rdb).max())
+        en = np.linalg.norm(gw - rdw) / np.linalg.norm(rdw)
         print(f"layer {i}: max per-weight error {ew.max():.2e} (median {np.median(ew):.1e}), "
-              f"bias {eb.max():.2e}")
-        errs.append((i, ew.max(), eb.max()))
-    for i, e_w, e_b in errs:
+              f"bias {eb.max():.2e}, norm-wise {en:.1e}")
+        errs.append((i, ew.max(), eb.max(), en))
+    for i, e_w, e_b, e_n in errs:
         # the gradient of layer i passes through L - i BF16-rounded stages (the loss gradient
         # and one data gradient per later layer); each can differ by one BF16 rounding step
         # (2^-7 relative) where FP32 accumulation flips a rounding decision
         bound = (L - i) * 2.0 ** -7
-        assert e_w <= bound and e_b <= bound, (i, e_w, e_b, bound)
+        assert e_n <= bound, (i, e_n, bound)
+        # per weight, for the 5-layer network; in the 8-layer one an output gathers the flips
+        # of a 131-node field through 7 stored stages, and single weights whose gradient is
+        # near the 1 % floor exceed this (each kernel is checked element by element on its
+        # own inputs in test_every_stage_on_its_own_inputs)
+        if arch == "base":
+            assert e_w <= bound and e_b <= bound, (i, e_w, e_b, bound)
+
+
+U32 = 2.0 ** -24  # unit roundoff of FP32
+
+
+@pytest.mark.parametrize("arch", ["base", "large"])
+def test_every_stage_on_its_own_inputs(arch):
+    """Each kernel of the forward and backward pass, fed the values the GPU itself stored for
+    that stage (layer input, incoming data gradient, BF16 weights), against the FP64
+    reference element by element.  No rounding decision upstream can differ here, so the
+    bound is that of the stage alone at any depth and dilation: FP32 accumulation over the
+    kernel's longest chain of additions (a relative error of chain x 2^-24 of the sum of
+    absolute terms) and, where the kernel stores BF16, one rounding to nearest (2^-8
+    relative).  16 problems of 65 x 65 nodes, so that taps 32 nodes away reach the
+    padding."""
+    from paper_1111_0983_amd import cnn
+    rng = np.random.default_rng(12)
+    B, H, W = 16, 65, 65
+    net = cnn.GuessNet(seed=6, device=DEV,
+                       layers=cnn.LAYERS_LARGE if arch == "large" else cnn.LAYERS)
+    cin, cout, _ = net.layers[-1]
+    net.w[-1].copy_(torch.from_numpy(rng.normal(0.0, (2.0 / (9 * cin)) ** 0.5,
+                                                size=cout * 9 * cin).astype(np.float32)))
+    for b in net.b:
+        b.copy_(torch.from_numpy(rng.normal(0.0, 0.05, size=b.numel()).astype(np.float32)))
+    net.repack()
+    x = _rounded(rng.normal(size=(B, H, W, 4)))
+    pred = net.forward(_bf(_to_nhwc_padded(x, 8)).to(DEV).reshape(-1), B, H, W)
+    tgt = rng.normal(size=(B, H, W)).astype(np.float32)
+    mask = (rng.uniform(size=(B, H, W)) > 0.3).astype(np.float32)
+    _, dy = cnn.loss(pred, torch.from_numpy(tgt).to(DEV).reshape(-1),
+                     torch.from_numpy(mask).to(DEV).reshape(-1))
+
+    def host(t, c):
+        return t.float().cpu().numpy().astype(np.float64).reshape(B, H, W, -1)[..., :c]
+
+    def check(got, ref, acc_err, bf16_out, what):
+        bound = acc_err + (2.0 ** -8 * (np.abs(ref) + acc_err) if bf16_out else 0.0)
+        bad = np.abs(got - ref) > bound
+        assert not bad.any(), (what, int(bad.sum()), float(np.abs(got - ref).max()))
+
+    L = len(net.layers)
+    # one MFMA's 32 products, then its K-steps over the padded 9 x channels, then the bias
+    ks_conv = lambda c: 32 + cnn.kpad(cnn.cpad(c)) // 32 + 1
+    for i, (ci, co_, dil) in enumerate(net.layers):
+        a = host(net.acts[i], ci)
+        wq = _rounded(net.w[i].cpu().numpy().reshape(co_, 3, 3, ci))
+        bias = net.b[i].cpu().numpy().astype(np.float64)
+        z = co.conv(a, wq, bias, dil)
+        err = ks_conv(ci) * U32 * (co.conv(np.abs(a), np.abs(wq), np.abs(bias), dil) + 1e-30)
+        if i < L - 1:
+            check(host(net.acts[i + 1], co_), np.maximum(z, 0.0), err, True, ("forward", i))
+        else:
+            check(pred.cpu().numpy().reshape(B, H, W), z[..., 0], err[..., 0], False,
+                  ("output", i))
+    dz = host(dy, 1)
+    for i in range(L - 1, -1, -1):
+        ci, co_, dil = net.layers[i]
+        a = host(net.acts[i], ci)
+        dw, db = cnn.wgrad(net.acts[i], dy, B, H, W, ci, co_, dil)
+        rdw, rdb = co.conv_wgrad(a, dz, dil)
+        sdw, sdb = co.conv_wgrad(np.abs(a), np.abs(dz), dil)
+        # a weight's sum: 32 products inside one MFMA, 32 K-steps over the workgroup's 1024
+        # pixels, then the workgroups' partials added in order
+        nblk = cnn._lib.cnn_wgrad_work(B, H, W, ci, co_) // (co_ * 9 * cnn.cpad(ci) + co_)
+        kw = 32 + 32 + nblk
+        check(dw.cpu().numpy().reshape(co_, 3, 3, ci), rdw, kw * U32 * sdw, False, ("dw", i))
+        check(db.cpu().numpy(), rdb, (1024 + nblk) * U32 * sdb, False, ("db", i))
+        if i == 0:
+            break
+        wq = _rounded(net.w[i].cpu().numpy().reshape(co_, 3, 3, ci))
+        dy = cnn.conv(dy, B, H, W, co_, net.wb[i], None, ci, dil, relu=False,
+                      relu_of=net.acts[i])
+        gate = a > 0.0
+        ref = co.conv_dgrad(dz, wq, dil) * gate
+        err = ks_conv(co_) * U32 * co.conv_dgrad(np.abs(dz), np.abs(wq), dil) * gate
+        dz = host(dy, ci)
+        check(dz, ref, err, True, ("data gradient", i))
 
 
 def test_adam_matches_reference():
