@@ -62,7 +62,9 @@ typedef struct {
   int split;          /* 1: Dirichlet and Neumann defects are extended and restricted
                          separately; 0: one outside pass over D_h - Omega_h */
   int precision;      /* mg_precision */
-  int inner_cycles;   /* FP32 cycles per defect-correction step (MG_FP32_DC) */
+  int inner_cycles;   /* FP32 cycles per defect-correction step (MG_FP32_DC); mg_solve's
+                         last step runs fewer when the measured convergence factor says
+                         they reach tol with a factor 2 to spare */
   int max_cycles;     /* cycle budget of mg_solve (FP64 cycles, or FP32 cycles in DC) */
   int batch;          /* independent problems solved together (>= 1) */
   int smoother;       /* boundary relaxation (Sec. 3.3): 0 = ghost relaxation with lambda

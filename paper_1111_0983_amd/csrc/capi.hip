@@ -293,12 +293,12 @@ void record_cycle(mg_handle_s* H, int c, bool norm, hipStream_t s) {
   if (norm) defect_norm64<D>(H, H->cur[0], s);
 }
 
-// inner_cycles FP32 cycles on the correction (from zero in FP32 buffer 0), u64 += the
-// correction, FP32 buffer 0 cleared for the next step, then the new FP64 defect
+// ncyc FP32 cycles on the correction (from zero in FP32 buffer 0), u64 += the correction,
+// FP32 buffer 0 cleared for the next step, then the new FP64 defect
 template <int D>
-void record_dc(mg_handle_s* H, hipStream_t s) {
+void record_dc(mg_handle_s* H, int ncyc, hipStream_t s) {
   H->cur[0] = 0;
-  for (int k = 0; k < H->grid.inner_cycles; ++k) cycle<D, float>(H, 0, s);
+  for (int k = 0; k < ncyc; ++k) cycle<D, float>(H, 0, s);
   DevLevel& L = H->dev[0];
   launch_dc_update<D>(L, L.u64[0], L.u32[H->cur[0]], L.u32[0], s);
   dc_defect<D>(H, s);
@@ -307,16 +307,16 @@ void record_dc(mg_handle_s* H, hipStream_t s) {
 hipStream_t stream_of(mg_handle_s* H) { return H->stream; }
 
 // Record one cycle (FP64 from finest buffer c, with or without the defect norm, or one
-// defect-correction step) into a graph.
-int capture(mg_handle_s* H, bool dc, int c, bool norm, hipGraphExec_t* out) {
+// defect-correction step of dc FP32 cycles) into a graph.
+int capture(mg_handle_s* H, int dc, int c, bool norm, hipGraphExec_t* out) {
   if (*out) return MG_OK;
   hipStream_t s = stream_of(H);
   hipGraph_t graph;
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   if (H->dim == 2)
-    dc ? record_dc<2>(H, s) : record_cycle<2>(H, c, norm, s);
+    dc ? record_dc<2>(H, dc, s) : record_cycle<2>(H, c, norm, s);
   else
-    dc ? record_dc<3>(H, s) : record_cycle<3>(H, c, norm, s);
+    dc ? record_dc<3>(H, dc, s) : record_cycle<3>(H, c, norm, s);
   if (hipStreamEndCapture(s, &graph) != hipSuccess) return MG_EHIP;
   const hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
   const hipError_t d = hipGraphDestroy(graph);  // the executable graph does not need it
@@ -380,11 +380,14 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
   rc = H->dim == 2 ? pack<2>(H, f, g, u) : pack<3>(H, f, g, u);
   if (rc) return rc;
   if (dc) {
-    if ((rc = capture(H, true, 0, true, &H->graph_dc))) return rc;
+    if ((rc = capture(H, H->grid.inner_cycles, 0, true, &H->graph_dc))) return rc;
+    H->graph_dc_short.resize(H->grid.inner_cycles, nullptr);
+    for (int r = 1; r < H->grid.inner_cycles; ++r)
+      if ((rc = capture(H, r, 0, true, &H->graph_dc_short[r]))) return rc;
   } else {
     for (int c = 0; c < (after_cycle(H, 0) == 1 ? 2 : 1); ++c)
       for (int nm = 0; nm < 2; ++nm)
-        if ((rc = capture(H, false, c, nm == 1, &H->graph_cycle[c][nm]))) return rc;
+        if ((rc = capture(H, 0, c, nm == 1, &H->graph_cycle[c][nm]))) return rc;
   }
   // defect of the initial guess
   if (H->dim == 2)
@@ -395,7 +398,7 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
   if ((rc = read_rel(H, &rel))) return rc;
   H->history.clear();
   H->history.push_back(rel);
-  int cycles = 0, steps = 0, grew = 0, status = MG_OK, last_k = 1;
+  int cycles = 0, steps = 0, grew = 0, status = MG_OK, last_cycles = 1;
   double prev = rel;
   const int per = dc ? H->grid.inner_cycles : 1;
   for (;;) {
@@ -412,32 +415,44 @@ int solve_impl(mg_handle_s* H, const double* f, const double* g, double* u, doub
         break;
       }
     }
-    // Once the history gives a convergence factor per step (the last read-back's reduction
-    // over the steps queued before it), queue the steps that the factor says are still
+    // Once the history gives a convergence factor per cycle (the last read-back's reduction
+    // over the cycles queued before it), queue the steps that the factor says are still
     // needed, minus one, before reading the residual back: the stopping test is unchanged,
-    // only host round trips are saved.  A fixed number of cycles is queued at once, with one
-    // read-back at the end.
+    // only host round trips are saved.  In defect correction, a last step that needs fewer
+    // cycles than a full one (with a factor 2 on the tolerance to spare) runs only those.
+    // A fixed number of steps is queued at once, with one read-back at the end.
     int k = fixed_cycles >= 0 ? std::max(1, fixed_cycles - steps) : 1;
+    int r_short = 0;
     if (fixed_cycles < 0 && H->history.size() >= 3) {
       const double r1 = H->history[H->history.size() - 1], r2 = H->history[H->history.size() - 2];
-      const double rho = std::pow(r1 / r2, 1.0 / last_k);
-      if (rho > 0.0 && rho < 0.9 && rel > tol) {
-        const int need = (int)std::ceil(std::log(tol / rel) / std::log(rho));
+      const double rho = std::pow(r1 / r2, 1.0 / last_cycles);
+      if (rho > 0.0 && std::pow(rho, per) < 0.9 && rel > tol) {
+        const double need_c = std::log(tol / rel) / std::log(rho);
+        const int need = (int)std::ceil(need_c / per);
         k = std::max(1, std::min(need - 1, 16));
+        if (need == 1 && per > 1) {
+          const int r = (int)std::ceil(std::log(0.5 * tol / rel) / std::log(rho));
+          if (r >= 1 && r < per) r_short = r;
+        }
       }
       k = std::min(k, std::max(1, (H->grid.max_cycles - cycles) / per));
     }
-    last_k = k;
-    for (int i = 0; i < k; ++i) {
-      if (dc) {
-        HIP_TRY(hipGraphLaunch(H->graph_dc, s));
-      } else {
-        // only the last cycle before a read-back needs its defect norm
-        HIP_TRY(hipGraphLaunch(H->graph_cycle[H->cur0][i == k - 1 ? 1 : 0], s));
-        H->cur0 = after_cycle(H, H->cur0);
+    if (r_short) {
+      HIP_TRY(hipGraphLaunch(H->graph_dc_short[r_short], s));
+      k = 1;
+    } else {
+      for (int i = 0; i < k; ++i) {
+        if (dc) {
+          HIP_TRY(hipGraphLaunch(H->graph_dc, s));
+        } else {
+          // only the last cycle before a read-back needs its defect norm
+          HIP_TRY(hipGraphLaunch(H->graph_cycle[H->cur0][i == k - 1 ? 1 : 0], s));
+          H->cur0 = after_cycle(H, H->cur0);
+        }
       }
     }
-    cycles += per * k;
+    last_cycles = r_short ? r_short : per * k;
+    cycles += last_cycles;
     steps += k;
     if ((rc = read_rel(H, &rel))) return rc;
     H->history.push_back(rel);
@@ -478,7 +493,7 @@ int rho_impl(mg_handle_s* H, const double* u0, int max_cycles, double rtol, doub
   const int64_t nn = (int64_t)H->batch * L.g.npp;
   launch_fill<double>(L.rhs64, nn, 0.0, s);
   for (int c = 0; c < (after_cycle(H, 0) == 1 ? 2 : 1); ++c)
-    if ((rc = capture(H, false, c, true, &H->graph_cycle[c][1]))) return rc;
+    if ((rc = capture(H, 0, c, true, &H->graph_cycle[c][1]))) return rc;
   auto norm = [&](double* out) -> int {
     HIP_TRY(hipMemcpyAsync(H->norms_host, H->norms, 2 * H->batch * sizeof(uint64_t),
                            hipMemcpyDeviceToHost, s));
@@ -945,6 +960,8 @@ void mg_free(mg_handle_t h) {
     for (int k = 0; k < 2; ++k)
       if (h->graph_cycle[c][k]) (void)hipGraphExecDestroy(h->graph_cycle[c][k]);
   if (h->graph_dc) (void)hipGraphExecDestroy(h->graph_dc);
+  for (hipGraphExec_t gx : h->graph_dc_short)
+    if (gx) (void)hipGraphExecDestroy(gx);
   for (DevLevel& L : h->dev) free_level(L);
   if (h->norms) (void)hipFree(h->norms);
   if (h->norms_host) (void)hipHostFree(h->norms_host);

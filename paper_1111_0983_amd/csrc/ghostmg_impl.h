@@ -280,6 +280,9 @@ struct mg_handle_s {
   // its result, [c][0] without it
   hipGraphExec_t graph_cycle[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   hipGraphExec_t graph_dc = nullptr;     // one defect-correction step + defect norm
+  // the same step with r < inner_cycles FP32 cycles at index r (a last step that needs
+  // less than a full one)
+  std::vector<hipGraphExec_t> graph_dc_short;
   int cur0 = 0;                          // buffer holding the finest FP64 iterate
   int cur[ghostmg::kMaxLevels] = {};     // per level current buffer while recording
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

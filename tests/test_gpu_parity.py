@@ -197,6 +197,31 @@ def test_fp32_defect_correction_matches_oracle(name):
     assert np.abs(u.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
+def test_defect_correction_last_step_runs_only_the_cycles_it_needs():
+    """In defect correction only the last step may run fewer FP32 cycles than inner_cycles
+    (when the measured factor per cycle says they reach the tolerance); the solve still
+    meets the tolerance and the oracle's discrete solution.  Over these cases and
+    tolerances a short last step occurs."""
+    gm = _gm()
+    short = 0
+    for name in ("disk64", "flower256", "torus32"):
+        for inner in (2, 3):
+            s, o, dom, dim, n, rule, sol = _build(name, precision=gm.MG_FP32_DC,
+                                                  inner_cycles=inner)
+            f, g = _rhs_gpu(s, dom, dim, n, sol)
+            ref = o.direct_solve(_rhs_oracle(o, dom, dim, n, sol))
+            for tol in (1e-10, 3e-11, 1e-11, 3e-12):
+                u = torch.zeros(f.size, dtype=torch.float64, device=DEV)
+                info = s.solve(_t(f), _t(g), u, tol=tol)
+                assert info["status"] == 0 and info["rel"] <= tol, (name, inner, tol, info)
+                k, c = info["outer"], info["cycles"]
+                assert inner * (k - 1) < c <= inner * k, (name, inner, tol, k, c)
+                short += c < inner * k
+                assert np.abs(u.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+            s.close()
+    assert short > 0
+
+
 def test_batch_of_problems_matches_single_solves():
     gm = _gm()
     n, nc = 128, 16
