@@ -267,7 +267,7 @@ def bench_flower(args, gm, pr, geo, np, torch, dev):
     for name, prec in (("fp64", gm.MG_FP64), ("fp32dc", gm.MG_FP32_DC)):
         t0 = time.time()
         s = gm.Solver(torch.from_numpy(phi).to(dev), [w.rule],
-                      gm.mg_grid_default(2, n, nc, precision=prec, inner_cycles=2))
+                      gm.mg_grid_default(2, n, nc, precision=prec, inner_cycles=args.inner))
         setup = time.time() - t0
         if ref is None:
             c = s.classes()
@@ -321,7 +321,7 @@ def bench_torus(args, gm, pr, geo, np, torch, dev):
     for name, prec in (("fp64", gm.MG_FP64), ("fp32dc", gm.MG_FP32_DC)):
         t0 = time.time()
         s = gm.Solver(torch.from_numpy(phi).to(dev), [w.rule],
-                      gm.mg_grid_default(3, n, 16, precision=prec, inner_cycles=2))
+                      gm.mg_grid_default(3, n, 16, precision=prec, inner_cycles=args.inner))
         setup = time.time() - t0
         if ref is None:
             c = s.classes()
@@ -468,8 +468,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n3", type=int, default=384, help="tank sequence grid (intervals per axis)")
     ap.add_argument("--nc2d", type=int, default=128, help="flower coarsest grid")
-    ap.add_argument("--inner", type=int, default=2,
-                    help="FP32 cycles per defect-correction step of the tank sequence")
+    ap.add_argument("--inner", type=int, default=3,
+                    help="FP32 cycles per defect-correction step (every FP32-DC leg)")
     ap.add_argument("--cpu-cycles", type=int, default=40,
                     help="cycle budget of the CPU oracle's solve (scaled beyond it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

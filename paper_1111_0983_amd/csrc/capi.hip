@@ -620,7 +620,7 @@ int mg_grid_default(mg_grid* g, int dim, int n, int n_coarse) {
   g->cN = 0.9 * 2.0 / (3.0 * std::sqrt((double)dim));
   g->split = 1;
   g->precision = MG_FP64;
-  g->inner_cycles = 2;
+  g->inner_cycles = 3;
   g->max_cycles = 100;
   g->batch = 1;
   return MG_OK;

@@ -41,7 +41,7 @@ def main(argv=None):
 
         n, nc = args.n or 384, args.nc or 24
         seq = tank.TankSequence(n)
-        grid = gm.mg_grid_default(3, n, nc, precision=gm.MG_FP32_DC, inner_cycles=2)
+        grid = gm.mg_grid_default(3, n, nc, precision=gm.MG_FP32_DC, inner_cycles=3)
         s = gm.Solver(seq.phi(0, "cuda"), [seq.rule], grid)
     else:
         n, nc = args.n or 2048, args.nc or 128

@@ -32,7 +32,7 @@ def run(steps: int = 4, n: int = 384, n_coarse: int = 24, warm: bool = True,
         t0 = time.perf_counter()
         phi = seq.phi(t, device)
         s = gm.Solver(phi, [seq.rule],
-                      gm.mg_grid_default(3, n, n_coarse, precision=precision, inner_cycles=2,
+                      gm.mg_grid_default(3, n, n_coarse, precision=precision, inner_cycles=3,
                                          max_cycles=300))
         c = torch.from_numpy(s.classes()).to(device)
         f = torch.where(c == 1, seq.f(t, device), torch.zeros((), dtype=torch.float64,
