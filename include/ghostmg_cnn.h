@@ -47,7 +47,9 @@ int cnn_conv(const void* x, int B, int H, int W, int cin_pad, const void* wt, co
 
 /* Weight and bias gradients of y = conv3x3_dil(x): dw FP32 [cout][3][3][cin],
  * db FP32 [cout] (both overwritten).  x: BF16 [B][H][W][cin_pad]; dy: BF16
- * [B][H][W][cout_pad].  work: FP32 scratch of cnn_wgrad_work(...) floats. */
+ * [B][H][W][cout_pad].  work: FP32 scratch of cnn_wgrad_work(...) floats.  Shapes: cout <= 32
+ * and cin <= 48 (cin <= 32 when cout > 16), else MG_EINVAL.  The sums are taken in a fixed
+ * order: repeated calls give identical results. */
 int64_t cnn_wgrad_work(int B, int H, int W, int cin, int cout);
 int cnn_wgrad(const void* x, const void* dy, int B, int H, int W, int cin, int cin_pad,
               int cout, int cout_pad, int dil, float* work, float* dw, float* db, void* stream);

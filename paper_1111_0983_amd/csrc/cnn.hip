@@ -114,104 +114,138 @@ __global__ void __launch_bounds__(256) k_conv(const __bf16* __restrict__ x, int 
 
 // ---------------------------------------------------------------------------------------
 // weight gradient: dW[co][tap][ci] = sum_p dy[p][co] x[p + d(tap)][ci], MFMA with
-// M = output channels, N = (tap, ci), K = pixels; per-workgroup partials, reduced in order
+// M = output channels, N = (tap, ci), K = pixels.  Workgroup (block, group) takes the
+// kWgradPix pixels of its block and the taps of its group (tpg consecutive taps; 9 / tpg
+// groups), 32 pixels per step: each thread stages at most one 16-byte vector of x or dy per
+// step, and loads the next step's vector into registers while the step's MFMAs run.  The
+// per-workgroup partials (the group's columns of its block's row) are reduced in order.
 // ---------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_wgrad(const __bf16* __restrict__ x,
                                                const __bf16* __restrict__ dy, int B, int H, int W,
                                                int cin_pad, int cout, int cout_pad, int dil,
-                                               int mt_n, int nt_n, float* __restrict__ work,
-                                               int64_t wstride) {
+                                               int tpg, int mt_n, int nt_n,
+                                               float* __restrict__ work, int64_t wstride) {
   extern __shared__ __bf16 lds[];
-  __bf16* xs = lds;                        // [32][9][cin_pad]
-  __bf16* ds = lds + 32 * 9 * cin_pad;     // [32][cout_pad]
+  const int ntg = 9 / tpg;
+  const int blk = blockIdx.x / ntg, grp = blockIdx.x % ntg, tap0 = grp * tpg;
+  __bf16* xs = lds;                          // [32][tpg][cin_pad]
+  __bf16* ds = lds + 32 * tpg * cin_pad;     // [32][cout_pad]
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t P = (int64_t)B * H * W;
-  const int64_t p_begin = (int64_t)blockIdx.x * kWgradPix;
-  const int tiles = mt_n * nt_n;
-  const int ntile_w = (tiles + 3) / 4;
-  f32x4 acc[9];
-#pragma unroll
-  for (int j = 0; j < 9; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int64_t p_begin = (int64_t)blk * kWgradPix;
+  // output tile of the wave (at most 4 tiles, one per wave: the host checks it), held in
+  // registers
+  const bool has_tile = wave < mt_n * nt_n;
+  const int mt = wave / nt_n, nt = wave % nt_n;
+  const int ncg = tpg * cin_pad;  // the group's columns
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   float dbacc = 0.f;
-  const int chunks_x = 32 * 9 * (cin_pad / 8), chunks_d = 32 * (cout_pad / 8);
-  for (int kp = 0; kp < kWgradPix; kp += 32) {
-    __syncthreads();
-    for (int c = threadIdx.x; c < chunks_x + chunks_d; c += 256) {
-      bf16x8 v = {};
-      if (c < chunks_x) {
-        const int pl = c / (9 * (cin_pad / 8)), rem = c % (9 * (cin_pad / 8));
-        const int tap = rem / (cin_pad / 8), cc = rem % (cin_pad / 8);
-        const int64_t p = p_begin + kp + pl;
-        if (p < P) {
-          const int b = (int)(p / ((int64_t)H * W));
-          const int r = (int)(p - (int64_t)b * H * W);
-          const int yy = r / W + dil * (tap / 3 - 1), xx = r % W + dil * (tap % 3 - 1);
-          if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-            v = *(const bf16x8*)(x + (((int64_t)b * H + yy) * W + xx) * cin_pad + 8 * cc);
-        }
-        *(bf16x8*)(xs + (pl * 9 + tap) * cin_pad + 8 * cc) = v;
-      } else {
-        const int c2 = c - chunks_x;
-        const int pl = c2 / (cout_pad / 8), cc = c2 % (cout_pad / 8);
-        const int64_t p = p_begin + kp + pl;
-        if (p < P) v = *(const bf16x8*)(dy + p * cout_pad + 8 * cc);
-        *(bf16x8*)(ds + pl * cout_pad + 8 * cc) = v;
+  const int chunks_x = 32 * tpg * (cin_pad / 8), chunks_d = 32 * (cout_pad / 8);
+  // the thread's vector (at most one: the host checks chunks_x + chunks_d <= 256): a
+  // position in xs or ds, and its source for the step at pixel offset kp
+  const int c = threadIdx.x;
+  const bool has = c < chunks_x + chunks_d;
+  auto fetch = [&](int kp) -> bf16x8 {
+    bf16x8 v = {};
+    if (!has) return v;
+    if (c < chunks_x) {
+      const int pl = c / (tpg * (cin_pad / 8)), rem = c % (tpg * (cin_pad / 8));
+      const int tap = tap0 + rem / (cin_pad / 8), cc = rem % (cin_pad / 8);
+      const int64_t p = p_begin + kp + pl;
+      if (p < P) {
+        const int b = (int)(p / ((int64_t)H * W));
+        const int r = (int)(p - (int64_t)b * H * W);
+        const int yy = r / W + dil * (tap / 3 - 1), xx = r % W + dil * (tap % 3 - 1);
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+          v = *(const bf16x8*)(x + (((int64_t)b * H + yy) * W + xx) * cin_pad + 8 * cc);
       }
+    } else {
+      const int c2 = c - chunks_x;
+      const int pl = c2 / (cout_pad / 8), cc = c2 % (cout_pad / 8);
+      const int64_t p = p_begin + kp + pl;
+      if (p < P) v = *(const bf16x8*)(dy + p * cout_pad + 8 * cc);
+    }
+    return v;
+  };
+  bf16x8 nxt = fetch(0);
+  for (int kp = 0; kp < kWgradPix; kp += 32) {
+    __syncthreads();  // the previous step's reads of xs / ds are done
+    if (has) {
+      if (c < chunks_x)
+        *(bf16x8*)(xs + c * 8) = nxt;
+      else
+        *(bf16x8*)(ds + (c - chunks_x) * 8) = nxt;
     }
     __syncthreads();
-    if ((int)threadIdx.x < cout_pad)
+    if (kp + 32 < kWgradPix) nxt = fetch(kp + 32);
+    if (grp == 0 && (int)threadIdx.x < cout_pad)
       for (int pl = 0; pl < 32; ++pl) dbacc += from_bf16(ds[pl * cout_pad + threadIdx.x]);
-    for (int j = 0; j < ntile_w; ++j) {
-      const int tile = wave * ntile_w + j;
-      if (tile >= tiles) break;
-      const int mt = tile / nt_n, nt = tile % nt_n;
+    if (has_tile) {
       const int co = mt * 16 + (lane & 15);
-      const int n = nt * 16 + (lane & 15);
-      const int tap = n / cin_pad, ci = n % cin_pad;
+      const int n = nt * 16 + (lane & 15);  // column within the group
       bf16x8 a, bb;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int pl = 8 * (lane >> 4) + i;
         a[i] = co < cout_pad ? ds[pl * cout_pad + co] : (__bf16)0.f;
-        bb[i] = tap < 9 ? xs[(pl * 9 + tap) * cin_pad + ci] : (__bf16)0.f;
+        bb[i] = n < ncg ? xs[pl * ncg + n] : (__bf16)0.f;
       }
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[j], 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
     }
   }
-  float* out = work + (int64_t)blockIdx.x * wstride;
+  float* out = work + (int64_t)blk * wstride;
   const int ncol = 9 * cin_pad;
-  for (int j = 0; j < ntile_w; ++j) {
-    const int tile = wave * ntile_w + j;
-    if (tile >= tiles) break;
-    const int mt = tile / nt_n, nt = tile % nt_n;
+  if (has_tile) {
     const int n = nt * 16 + (lane & 15);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int co = mt * 16 + 4 * (lane >> 4) + i;
-      if (co < cout && n < ncol) out[(int64_t)co * ncol + n] = acc[j][i];
+      if (co < cout && n < ncg) out[(int64_t)co * ncol + tap0 * cin_pad + n] = acc[i];
     }
   }
-  if ((int)threadIdx.x < cout) out[(int64_t)cout * ncol + threadIdx.x] = dbacc;
+  if (grp == 0 && (int)threadIdx.x < cout) out[(int64_t)cout * ncol + threadIdx.x] = dbacc;
 }
 
+// 64 outputs per workgroup, 4 threads per output: thread s of an output sums the partials of
+// blocks s, s + 4, ... in order, then the four sums are added in order (deterministic)
 __global__ void __launch_bounds__(256) k_wgrad_reduce(const float* __restrict__ work, int nblk,
                                                       int64_t wstride, int cin, int cin_pad,
                                                       int cout, float* __restrict__ dw,
                                                       float* __restrict__ db) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  __shared__ float part[4][64];
+  const int o = blockIdx.x * 64 + (threadIdx.x & 63), sl = threadIdx.x >> 6;
   const int nw = cout * 9 * cin;
   const int ncol = 9 * cin_pad;
-  if (i < nw) {
-    const int co = i / (9 * cin), r = i % (9 * cin), tap = r / cin, ci = r % cin;
-    const int64_t off = (int64_t)co * ncol + tap * cin_pad + ci;
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += work[(int64_t)b * wstride + off];
-    dw[i] = s;
-  } else if (i < nw + cout) {
-    const int co = i - nw;
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += work[(int64_t)b * wstride + (int64_t)cout * ncol + co];
-    db[co] = s;
+  int64_t off = -1;
+  if (o < nw) {
+    const int co = o / (9 * cin), r = o % (9 * cin), tap = r / cin, ci = r % cin;
+    off = (int64_t)co * ncol + tap * cin_pad + ci;
+  } else if (o < nw + cout) {
+    off = (int64_t)cout * ncol + (o - nw);
+  }
+  float s = 0.f;
+  if (off >= 0) {
+    const float* src = work + off;
+    int b = sl;
+    for (; b + 12 < nblk; b += 16) {
+      const float v0 = src[(int64_t)b * wstride], v1 = src[(int64_t)(b + 4) * wstride];
+      const float v2 = src[(int64_t)(b + 8) * wstride], v3 = src[(int64_t)(b + 12) * wstride];
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; b < nblk; b += 4) s += src[(int64_t)b * wstride];
+  }
+  part[sl][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (sl == 0 && off >= 0) {
+    const int t = threadIdx.x;
+    const float v = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+    if (o < nw)
+      dw[o] = v;
+    else
+      db[o - nw] = v;
   }
 }
 
@@ -495,16 +529,20 @@ int cnn_wgrad(const void* x, const void* dy, int B, int H, int W, int cin, int c
     return MG_EINVAL;
   const int64_t P = (int64_t)B * H * W;
   const int nblk = (int)((P + kWgradPix - 1) / kWgradPix);
-  const int mt = (cout + 15) / 16, ntn = (9 * cin_pad + 15) / 16;
-  if ((mt * ntn + 3) / 4 > 9) return MG_EINVAL;
+  // taps per workgroup: one where a tap's columns fill MFMA tiles, a stencil row otherwise
+  const int tpg = cin_pad >= 16 ? 1 : 3;
+  const int mt = (cout + 15) / 16, ntn = (tpg * cin_pad + 15) / 16;
+  // one output tile per wave, and one staged vector per thread and step
+  if (mt * ntn > 4 || 32 * tpg * (cin_pad / 8) + 32 * (cout_pad / 8) > 256) return MG_EINVAL;
   const int64_t wstride = (int64_t)cout * 9 * cin_pad + cout;
-  const size_t lds = (size_t)(32 * 9 * cin_pad + 32 * cout_pad) * sizeof(__bf16);
+  const size_t lds = (size_t)(32 * tpg * cin_pad + 32 * cout_pad) * sizeof(__bf16);
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_wgrad, dim3(nblk), dim3(256), lds, s, (const __bf16*)x, (const __bf16*)dy, B,
-                     H, W, cin_pad, cout, cout_pad, dil, mt, ntn, work, wstride);
+  hipLaunchKernelGGL(k_wgrad, dim3(nblk * (9 / tpg)), dim3(256), lds, s, (const __bf16*)x,
+                     (const __bf16*)dy, B, H, W, cin_pad, cout, cout_pad, dil, tpg, mt, ntn, work,
+                     wstride);
   const int nout = cout * 9 * cin + cout;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(lin(nout)), dim3(256), 0, s, (const float*)work, nblk,
-                     wstride, cin, cin_pad, cout, dw, db);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 63) / 64), dim3(256), 0, s, (const float*)work,
+                     nblk, wstride, cin, cin_pad, cout, dw, db);
   return hipGetLastError() == hipSuccess ? MG_OK : MG_EHIP;
 }
 

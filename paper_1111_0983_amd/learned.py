@@ -475,9 +475,15 @@ def main(argv=None):
     ap.add_argument("--weights", default=None, help="skip training, load these weights")
     ap.add_argument("--arch", choices=["base", "large"], default="base",
                     help="base: 5 layers, receptive field 33; large: 8 layers, field 131")
+    ap.add_argument("--rate-only", action="store_true",
+                    help="print the MFMA kernels' measured throughput at the training shape "
+                         "(randomly initialised network) and exit")
     args = ap.parse_args(argv)
-    os.makedirs(args.out, exist_ok=True)
     net = cnn.GuessNet(seed=0, layers=cnn.LAYERS_LARGE if args.arch == "large" else cnn.LAYERS)
+    if args.rate_only:
+        print(json.dumps({"arch": args.arch, "mfma": mfma_rate(net)}), flush=True)
+        return
+    os.makedirs(args.out, exist_ok=True)
     res = {}
     if args.weights:
         net.load(dict(np.load(args.weights)))
