@@ -118,18 +118,23 @@ __global__ void __launch_bounds__(256) k_conv(const __bf16* __restrict__ x, int 
 // kWgradPix pixels of its block and the taps of its group (tpg consecutive taps; 9 / tpg
 // groups), 32 pixels per step: each thread stages at most one 16-byte vector of x or dy per
 // step, and loads the next step's vector into registers while the step's MFMAs run.  The
-// per-workgroup partials (the group's columns of its block's row) are reduced in order.
+// step's tiles are staged transposed (a row per channel, its 32 pixels contiguous), so that
+// a lane reads its 8 K-values of an MFMA operand in one 16-byte read.  The per-workgroup
+// partials (the group's columns of its block's row) are reduced in order.
+constexpr int kWgradRow = 40;  // row stride (bf16) of the transposed tiles: 80 bytes, so that
+                               // the 16-byte reads of 8 consecutive rows hit distinct banks
 // ---------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_wgrad(const __bf16* __restrict__ x,
                                                const __bf16* __restrict__ dy, int B, int H, int W,
                                                int cin_pad, int cout, int cout_pad, int dil,
                                                int tpg, int mt_n, int nt_n,
                                                float* __restrict__ work, int64_t wstride) {
-  extern __shared__ __bf16 lds[];
+  extern __shared__ __align__(16) __bf16 lds[];
+  constexpr int RS = kWgradRow;
   const int ntg = 9 / tpg;
   const int blk = blockIdx.x / ntg, grp = blockIdx.x % ntg, tap0 = grp * tpg;
-  __bf16* xs = lds;                          // [32][tpg][cin_pad]
-  __bf16* ds = lds + 32 * tpg * cin_pad;     // [32][cout_pad]
+  __bf16* xs = lds;                           // [tpg * cin_pad][RS]: column n, its pixels
+  __bf16* ds = lds + tpg * cin_pad * RS;      // [cout_pad][RS]
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t P = (int64_t)B * H * W;
   const int64_t p_begin = (int64_t)blk * kWgradPix;
@@ -171,25 +176,30 @@ __global__ void __launch_bounds__(256) k_wgrad(const __bf16* __restrict__ x,
   for (int kp = 0; kp < kWgradPix; kp += 32) {
     __syncthreads();  // the previous step's reads of xs / ds are done
     if (has) {
-      if (c < chunks_x)
-        *(bf16x8*)(xs + c * 8) = nxt;
-      else
-        *(bf16x8*)(ds + (c - chunks_x) * 8) = nxt;
+      // the vector holds 8 channels of one pixel: 8 rows of the transposed tile
+      if (c < chunks_x) {
+        const int pl = c / (tpg * (cin_pad / 8)), rem = c % (tpg * (cin_pad / 8));
+        const int n0 = (rem / (cin_pad / 8)) * cin_pad + 8 * (rem % (cin_pad / 8));
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xs[(n0 + j) * RS + pl] = nxt[j];
+      } else {
+        const int c2 = c - chunks_x;
+        const int pl = c2 / (cout_pad / 8), ch0 = 8 * (c2 % (cout_pad / 8));
+#pragma unroll
+        for (int j = 0; j < 8; ++j) ds[(ch0 + j) * RS + pl] = nxt[j];
+      }
     }
     __syncthreads();
     if (kp + 32 < kWgradPix) nxt = fetch(kp + 32);
     if (grp == 0 && (int)threadIdx.x < cout_pad)
-      for (int pl = 0; pl < 32; ++pl) dbacc += from_bf16(ds[pl * cout_pad + threadIdx.x]);
+      for (int pl = 0; pl < 32; ++pl) dbacc += from_bf16(ds[threadIdx.x * RS + pl]);
     if (has_tile) {
       const int co = mt * 16 + (lane & 15);
       const int n = nt * 16 + (lane & 15);  // column within the group
-      bf16x8 a, bb;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int pl = 8 * (lane >> 4) + i;
-        a[i] = co < cout_pad ? ds[pl * cout_pad + co] : (__bf16)0.f;
-        bb[i] = n < ncg ? xs[pl * ncg + n] : (__bf16)0.f;
-      }
+      const int k0 = 8 * (lane >> 4);       // the lane's 8 pixels of the step
+      const bf16x8 zero = {};
+      const bf16x8 a = co < cout_pad ? *(const bf16x8*)(ds + co * RS + k0) : zero;
+      const bf16x8 bb = n < ncg ? *(const bf16x8*)(xs + n * RS + k0) : zero;
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
     }
   }
@@ -535,7 +545,7 @@ int cnn_wgrad(const void* x, const void* dy, int B, int H, int W, int cin, int c
   // one output tile per wave, and one staged vector per thread and step
   if (mt * ntn > 4 || 32 * tpg * (cin_pad / 8) + 32 * (cout_pad / 8) > 256) return MG_EINVAL;
   const int64_t wstride = (int64_t)cout * 9 * cin_pad + cout;
-  const size_t lds = (size_t)(32 * tpg * cin_pad + 32 * cout_pad) * sizeof(__bf16);
+  const size_t lds = (size_t)(tpg * cin_pad + cout_pad) * kWgradRow * sizeof(__bf16);
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_wgrad, dim3(nblk * (9 / tpg)), dim3(256), lds, s, (const __bf16*)x,
                      (const __bf16*)dy, B, H, W, cin_pad, cout, cout_pad, dil, tpg, mt, ntn, work,
