@@ -209,17 +209,17 @@ __device__ __forceinline__ void restrict_gather(const T* __restrict__ rf, int64_
 // O nodes inside the U region along every axis and whose rows (y, z) hold HX nodes of that
 // colour, HY rows per z: node r of the phase lies at x = 2 (r mod HX) + ((y + z + PAR) & 1)
 // of its row.  Nodes whose code is not an interior one (1, 3) are left alone.
-template <int D, typename T, int N, int HX, int HY, int O, int PAR>
+template <int D, typename T, int N, int HX, int HY, int O, int PAR, int NT = 256>
 __device__ __forceinline__ void tile_colour_phase(T* su, const int8_t* sc, const T* sf, int FX,
                                                   int FY, int SY, int SZ, T h2, T inv2d,
                                                   int skip_band) {
-  constexpr int K = (N + 255) / 256;
+  constexpr int K = (N + NT - 1) / NT;
   int ui[K];
   int8_t cd[K];
   T cv[K], fv[K], nb[K][2 * D];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int r0 = (int)threadIdx.x + 256 * k, r = r0 < N ? r0 : 0;
+    const int r0 = (int)threadIdx.x + NT * k, r = r0 < N ? r0 : 0;
     const int row = r / HX, y = row % HY, z = row / HY;
     const int x = 2 * (r % HX) + ((y + z + PAR) & 1);
     // F index of the node (the F region starts one node inside the U region)
@@ -254,7 +254,7 @@ __device__ __forceinline__ void tile_colour_phase(T* su, const int8_t* sc, const
 // workgroup writes its own block of uout (a tile, or a part of one: RTile): the interior
 // nodes off the boundary band (the relaxation chunks write the band and the ghosts), or,
 // with write_all, every unknown.
-template <int D, typename T, int MODE, int SUB>
+template <int D, typename T, int MODE, int SUB, int NT = 256>
 __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   constexpr bool PROLONG = MODE == kRelaxProlong, RESTRICT = MODE == kRelaxRestrict;
   static_assert(!RESTRICT || D == 2, "the restriction is fused in 2D only");
@@ -283,10 +283,10 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   const int oz = D == 3 ? t.w * Tile<D>::Z + TZ * (q / (SUB * SUB)) : 0;
   // every global load of the thread is issued before the first is used: positions outside
   // the box read the tile's first node and are replaced by zero afterwards
-  constexpr int NU = (NUN + 255) / 256, NF = (NFN + 255) / 256, NC = (NCN + 255) / 256;
+  constexpr int NU = (NUN + NT - 1) / NT, NF = (NFN + NT - 1) / NT, NC = (NCN + NT - 1) / NT;
   // fine defect patch under the F region (restriction): fine x from 2 ox - 3 to 2 ox + 2 TX + 1
   constexpr int RX = 2 * FX + 1, RY = 2 * FY + 1, NRN = RESTRICT ? RX * RY : 1;
-  constexpr int NR = (NRN + 255) / 256;
+  constexpr int NR = (NRN + NT - 1) / NT;
   T uv[NU], fv[NF], ev[NC], rpv[NR];
   int8_t cv[NU], fc[NF], ccv[NC];
   uint8_t rcv[NF];
@@ -297,7 +297,7 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
     const int64_t cbase = (int64_t)t.x * gc.npp;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const int i = threadIdx.x + 256 * k;
+      const int i = threadIdx.x + NT * k;
       const int x = i % CX, y = (i / CX) % CY, z = i / (CX * CY);
       const int cx = ox / 2 - 1 + x, cy = oy / 2 - 1 + y, cz = D == 3 ? oz / 2 - 1 + z : 0;
       cok[k] = i < NCN && in_box(cx, cy, cz, gc.np, D);
@@ -308,7 +308,7 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   }
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
-    const int i = threadIdx.x + 256 * k;
+    const int i = threadIdx.x + NT * k;
     const int x = i % UX, y = (i / UX) % UY, z = i / (UX * UY);
     const int gx = ox + x - 2, gy = oy + y - 2, gz = D == 3 ? oz + z - 2 : 0;
     uok[k] = i < NUN && in_box(gx, gy, gz, g.np, D);
@@ -318,7 +318,7 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   }
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
-    const int i = threadIdx.x + 256 * k;
+    const int i = threadIdx.x + NT * k;
     const int x = i % FX, y = (i / FX) % FY, z = i / (FX * FY);
     const int gx = ox + x - 1, gy = oy + y - 1, gz = D == 3 ? oz + z - 1 : 0;
     fok[k] = i < NFN && in_box(gx, gy, gz, g.np, D);
@@ -333,7 +333,7 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
     const int64_t fbase = (int64_t)t.x * a.gf.npp;
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      const int i = threadIdx.x + 256 * k;
+      const int i = threadIdx.x + NT * k;
       const int fx = 2 * ox - 3 + i % RX, fy = 2 * oy - 3 + i / RX;
       const bool ok = i < NRN && in_box(fx, fy, 0, a.gf.np, 2);
       rpv[k] = a.rf[ok ? fbase + fx + a.gf.st[1] * fy : fbase];
@@ -341,7 +341,7 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   }
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
-    const int i = threadIdx.x + 256 * k;
+    const int i = threadIdx.x + NT * k;
     if (i < NUN) {
       su[i] = uok[k] ? uv[k] : (T)0;
       sc[i] = uok[k] ? cv[k] : (int8_t)0;
@@ -353,12 +353,12 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
     uint8_t* src = (uint8_t*)(sr + NRN);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      const int i = threadIdx.x + 256 * k;
+      const int i = threadIdx.x + NT * k;
       if (i < NRN) sr[i] = rpv[k];
     }
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
-      const int i = threadIdx.x + 256 * k;
+      const int i = threadIdx.x + NT * k;
       if (i < NFN) src[i] = fok[k] ? rcv[k] : kNoUnknown;
     }
     __syncthreads();
@@ -370,8 +370,8 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
       int ii[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        ii[h] = i0 + 256 * h < NFN ? i0 + 256 * h : i0;
-        c[h] = i0 + 256 * h < NFN ? src[ii[h]] : kNoUnknown;
+        ii[h] = i0 + NT * h < NFN ? i0 + NT * h : i0;
+        c[h] = i0 + NT * h < NFN ? src[ii[h]] : kNoUnknown;
         const int x = ii[h] % FX, y = ii[h] / FX;
         const T* pp = sr + (2 * x + 1) + RX * (2 * y + 1);
 #pragma unroll
@@ -379,11 +379,11 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
       }
 #pragma unroll
       for (int h = 0; h < 2; ++h)
-        if (i0 + 256 * h < NFN) sf[ii[h]] = c[h] != kNoUnknown ? restrict_box<2, T>(c[h], rr[h]) : (T)0;
+        if (i0 + NT * h < NFN) sf[ii[h]] = c[h] != kNoUnknown ? restrict_box<2, T>(c[h], rr[h]) : (T)0;
     }
     __syncthreads();  // sf is read below at positions other threads computed
     // the restricted right-hand side of the tile's unknowns, for the level's later launches
-    for (int i = threadIdx.x; i < TX * TY; i += 256) {
+    for (int i = threadIdx.x; i < TX * TY; i += NT) {
       const int x = i % TX, y = i / TX;
       const int fi = (x + 1) + FX * (y + 1);
       if (src[fi] == kNoUnknown) continue;
@@ -392,7 +392,7 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   } else {
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
-      const int i = threadIdx.x + 256 * k;
+      const int i = threadIdx.x + NT * k;
       if (i < NFN) {
         const int8_t c = fok[k] ? fc[k] : (int8_t)0;
         sf[i] = (c == 1 || c == 3) ? fv[k] : (T)0;
@@ -402,7 +402,7 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   if constexpr (PROLONG) {
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const int i = threadIdx.x + 256 * k;
+      const int i = threadIdx.x + NT * k;
       if (i < NCN) {
         sce[i] = cok[k] ? ev[k] : (T)0;
         scc[i] = cok[k] ? ccv[k] : (int8_t)0;
@@ -419,7 +419,7 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
     constexpr int NCD = 1 << D;
     constexpr int KX = UX / 2, KY = UY / 2, KZ = D == 3 ? UZ / 2 : 1;
     constexpr int FS[3] = {1, UX, UX * UY};
-    for (int cell = threadIdx.x; cell < KX * KY * KZ; cell += 256) {
+    for (int cell = threadIdx.x; cell < KX * KY * KZ; cell += NT) {
       const int cx = cell % KX, cy = (cell / KX) % KY, cz = cell / (KX * KY);
       const int li0 = cx * CS[0] + cy * CS[1] + cz * CS[2];
       const int ui0 = 2 * cx * FS[0] + 2 * cy * FS[1] + 2 * cz * FS[2];
@@ -467,19 +467,19 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   // colour, ghosts or outside nodes, which the phase leaves unchanged.
   constexpr int FXH = FX / 2, TXH = TX / 2;
   constexpr int NRED = FXH * FY * FZ, NBLK = TXH * TY * TZ;
-  tile_colour_phase<D, T, NRED, FXH, FY, 1, (D & 1)>(su, sc, sf, FX, FY, SY, SZ, a.h2, a.inv2d,
+  tile_colour_phase<D, T, NRED, FXH, FY, 1, (D & 1), NT>(su, sc, sf, FX, FY, SY, SZ, a.h2, a.inv2d,
                                                      a.skip_band);
   __syncthreads();
-  tile_colour_phase<D, T, NBLK, TXH, TY, 2, 1>(su, sc, sf, FX, FY, SY, SZ, a.h2, a.inv2d,
+  tile_colour_phase<D, T, NBLK, TXH, TY, 2, 1, NT>(su, sc, sf, FX, FY, SY, SZ, a.h2, a.inv2d,
                                                a.skip_band);
   __syncthreads();
   // the block's nodes to uout: every code and value read before the first store
-  constexpr int NST = TZ * TY * TX, KS = (NST + 255) / 256;
+  constexpr int NST = TZ * TY * TX, KS = (NST + NT - 1) / NT;
   int8_t cst[KS];
   T vst[KS];
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
-    const int i0 = threadIdx.x + 256 * k, i = i0 < NST ? i0 : 0;
+    const int i0 = threadIdx.x + NT * k, i = i0 < NST ? i0 : 0;
     const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
     const int ui = (x + 2) + SY * (y + 2) + (D == 3 ? SZ * (z + 2) : 0);
     cst[k] = i0 < NST ? sc[ui] : (int8_t)0;
@@ -487,7 +487,7 @@ __device__ void relax_tile(const RelaxArgs<T>& a, int tb, unsigned char* lds) {
   }
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
-    const int i = threadIdx.x + 256 * k;
+    const int i = threadIdx.x + NT * k;
     const int x = i % TX, y = (i / TX) % TY, z = i / (TX * TY);
     if (cst[k] == 0 || (cst[k] != 1 && !a.write_all)) continue;
     a.uout[base + (ox + x) + g.st[1] * (oy + y) + g.st[2] * (D == 3 ? oz + z : 0)] = vst[k];
@@ -773,6 +773,20 @@ template <int D, typename T>
 __global__ void __launch_bounds__(band_chunk_threads(D)) k_relax_chunks(RelaxArgs<T> a) {
   extern __shared__ __align__(16) unsigned char relax_smem[];
   relax_chunk<D, T, kRelaxPlain>(a, blockIdx.x, relax_smem);
+}
+
+// 3D levels with few tiles: the tiles and the first launch's relaxation chunks share one
+// launch of chunk-wide workgroups (workgroups [0, nchunks) the chunks, the rest one tile
+// each, relaxed by all the workgroup's threads).  There the launch does not fill the chip,
+// so the chunks' registers cost the tiles nothing, and a launch of its own is saved.
+template <typename T>
+__global__ void __launch_bounds__(band_chunk_threads(3)) k_relax_shared3(RelaxArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char relax_smem[];
+  if ((int)blockIdx.x < a.nchunks)
+    relax_chunk<3, T, kRelaxPlain>(a, blockIdx.x, relax_smem);
+  else
+    relax_tile<3, T, kRelaxPlain, 1, band_chunk_threads(3)>(a, (int)blockIdx.x - a.nchunks,
+                                                             relax_smem);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1862,6 +1876,13 @@ static void launch_relax_sub(RelaxArgs<T> a, const DevLevel& L, hipStream_t s) {
   a.nbt = a.ntiles ? tile_grid(a.ntiles * RTile<D, SUB>::N) : 0;
   const size_t chunk_lds = (size_t)(L.bc_smax + band_chunk_threads(D)) * sizeof(T);
   if constexpr (D == 3) {
+    if (MODE == kRelaxPlain && a.nchunks) {
+      // tiles and the first launch's chunks together (levels with few tiles, plain mode)
+      const size_t lds = std::max(tile_lds<D, T, kRelaxPlain, 1>(), chunk_lds);
+      hipLaunchKernelGGL((k_relax_shared3<T>), dim3(a.nchunks + a.nbt), dim3(band_chunk_threads(D)),
+                         lds, s, a);
+      return;
+    }
     // tiles and chunks in launches of their own
     if (a.nbt) {
       RelaxArgs<T> t = a;
@@ -1887,6 +1908,9 @@ static void launch_relax_sub(RelaxArgs<T> a, const DevLevel& L, hipStream_t s) {
 
 // tiles split in parts on levels with fewer than kSplitTilesBelow tiles (2D)
 constexpr int kSplitTilesBelow = 512;
+// 3D levels with at most this many tiles relax their tiles in the launch of the first
+// relaxation chunks (k_relax_shared3)
+constexpr int kShareTilesBelow3D = 2048;
 
 template <int D, typename T, int MODE>
 static void launch_relax_kernel(const RelaxArgs<T>& a, const DevLevel& L, hipStream_t s) {
@@ -1999,8 +2023,9 @@ void launch_relax(const DevLevel& L, const mg_grid& G, const T* uin, T* uout, co
   a.skip_band = G.smoother == 2 ? 1 : 0;
   // 2D: the tiles and the first launch's chunks share a launch; 3D chunks (which hold the
   // 27-point ghost rows in registers) get launches of their own, so that the tiles keep
-  // their occupancy
-  const int k0 = D == 2 ? 1 : 0;
+  // their occupancy, except on levels with few tiles (plain relaxations: 3D interpolation and
+  // restriction are launches of their own)
+  const int k0 = D == 2 || (L.nchunks && L.ntiles > 0 && L.ntiles <= kShareTilesBelow3D) ? 1 : 0;
   a.nchunks = L.nchunks && k0 == 1 ? L.sub[1] - L.sub[0] : 0;
   a.phases = L.bc_phases;
   a.hdr = L.bc_hdr;
