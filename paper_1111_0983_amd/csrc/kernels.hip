@@ -1876,7 +1876,7 @@ static void launch_relax_sub(RelaxArgs<T> a, const DevLevel& L, hipStream_t s) {
   a.nbt = a.ntiles ? tile_grid(a.ntiles * RTile<D, SUB>::N) : 0;
   const size_t chunk_lds = (size_t)(L.bc_smax + band_chunk_threads(D)) * sizeof(T);
   if constexpr (D == 3) {
-    if (MODE == kRelaxPlain && a.nchunks) {
+    if (MODE == kRelaxPlain && a.nchunks && a.nbt) {
       // tiles and the first launch's chunks together (levels with few tiles, plain mode)
       const size_t lds = std::max(tile_lds<D, T, kRelaxPlain, 1>(), chunk_lds);
       hipLaunchKernelGGL((k_relax_shared3<T>), dim3(a.nchunks + a.nbt), dim3(band_chunk_threads(D)),
