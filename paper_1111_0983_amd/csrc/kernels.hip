@@ -1909,8 +1909,11 @@ static void launch_relax_sub(RelaxArgs<T> a, const DevLevel& L, hipStream_t s) {
 // tiles split in parts on levels with fewer than kSplitTilesBelow tiles (2D)
 constexpr int kSplitTilesBelow = 512;
 // 3D levels with at most this many tiles relax their tiles in the launch of the first
-// relaxation chunks (k_relax_shared3)
-constexpr int kShareTilesBelow3D = 2048;
+// relaxation chunks (k_relax_shared3): levels whose tile launch is a single round of resident
+// workgroups (256 CUs x 7 FP32 tiles = 1792), where it costs latency rather than bandwidth
+// (tank 384^3: the 192^3 level, 1232 tiles, gains; torus 256^3: the finest level, about
+// 1900 tiles, loses when shared)
+constexpr int kShareTilesBelow3D = 1536;
 
 template <int D, typename T, int MODE>
 static void launch_relax_kernel(const RelaxArgs<T>& a, const DevLevel& L, hipStream_t s) {
