@@ -124,10 +124,13 @@ struct Ext {
 int extension(PL& F, const PL& C, const mg_grid& G, const BcPartition& part,
               std::vector<Ext>& out) {
   const int D = F.D;
-  std::vector<int64_t> rank(F.nn, -1);
-  std::vector<int64_t> nodes;
   int nnb = 1;
   for (int a = 0; a < D; ++a) nnb *= 3;
+  // the extension nodes: outside fine nodes under the coarse ghosts, each once (ids, in
+  // increasing node index); a node's rank (its position in increasing phi) and DAG level
+  // are kept per id, looked up by binary search (the fine level has far more nodes than
+  // extension nodes)
+  std::vector<int64_t> ids;
   for (int64_t X = 0; X < C.nn; ++X) {
     if (C.cls[X] != GHOST) continue;
     int jc[3];
@@ -140,18 +143,23 @@ int extension(PL& F, const PL& C, const mg_grid& G, const BcPartition& part,
       }
       if (!inbox(F, j)) continue;
       const int64_t P = iof(F, j);
-      if (F.cls[P] == OUT && rank[P] < 0) {
-        rank[P] = 0;
-        nodes.push_back(P);
-      }
+      if (F.cls[P] == OUT) ids.push_back(P);
     }
   }
+  std::sort(ids.begin(), ids.end());
+  ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+  auto slot = [&](int64_t P) -> int64_t {  // position of P in ids, -1 when absent
+    const auto it = std::lower_bound(ids.begin(), ids.end(), P);
+    return it != ids.end() && *it == P ? (int64_t)(it - ids.begin()) : -1;
+  };
+  std::vector<int64_t> nodes(ids);
   std::sort(nodes.begin(), nodes.end(), [&](int64_t a, int64_t b) {
     if (F.phi[a] != F.phi[b]) return F.phi[a] < F.phi[b];
     return a < b;
   });
-  for (size_t e = 0; e < nodes.size(); ++e) rank[nodes[e]] = (int64_t)e;
-  std::vector<int> dag(F.nn, 0);
+  std::vector<int64_t> rank(ids.size(), -1);
+  for (size_t e = 0; e < nodes.size(); ++e) rank[slot(nodes[e])] = (int64_t)e;
+  std::vector<int> dag(ids.size(), 0);
   out.clear();
   out.reserve(nodes.size());
   for (size_t e = 0; e < nodes.size(); ++e) {
@@ -170,9 +178,10 @@ int extension(PL& F, const PL& C, const mg_grid& G, const BcPartition& part,
     double n2 = 0.0;
     for (int a = 0; a < D; ++a) n2 += gr[a] * gr[a];
     const double nrm = std::sqrt(n2);
+    const int64_t sp = slot(P);
     if (!(nrm > 0.0)) {
       F.lab[P] = 1;
-      dag[P] = 1;
+      dag[sp] = 1;
       out.push_back(x);
       continue;
     }
@@ -189,7 +198,8 @@ int extension(PL& F, const PL& C, const mg_grid& G, const BcPartition& part,
         q[a] -= na > 0.0 ? 1 : -1;
         if (!inbox(F, q)) continue;
         const int64_t Q = iof(F, q);
-        const bool avail = F.cls[Q] == GHOST || (rank[Q] >= 0 && rank[Q] < (int64_t)e);
+        const int64_t sq = F.cls[Q] == OUT ? slot(Q) : -1;
+        const bool avail = F.cls[Q] == GHOST || (sq >= 0 && rank[sq] < (int64_t)e);
         if (!avail) continue;
         if (G.split && pass == 0 && F.lab[Q] != F.lab[P]) continue;
         if (pass == 0) ++nsame;
@@ -199,8 +209,8 @@ int extension(PL& F, const PL& C, const mg_grid& G, const BcPartition& part,
     }
     int lvl = 1;
     for (int a = 0; a < 3; ++a)
-      if (x.src[a] >= 0 && F.cls[x.src[a]] == OUT) lvl = std::max(lvl, dag[x.src[a]] + 1);
-    dag[P] = lvl;
+      if (x.src[a] >= 0 && F.cls[x.src[a]] == OUT) lvl = std::max(lvl, dag[slot(x.src[a])] + 1);
+    dag[sp] = lvl;
     x.dag = lvl;
     out.push_back(x);
   }
