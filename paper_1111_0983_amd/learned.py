@@ -470,7 +470,7 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--eval", type=int, default=64, help="evaluation problems (0: none)")
-    ap.add_argument("--out", default="gpurun_out/learned")
+    ap.add_argument("--out", default="learned_out")
     ap.add_argument("--init", default=None, help="start training from these weights")
     ap.add_argument("--weights", default=None, help="skip training, load these weights")
     ap.add_argument("--arch", choices=["base", "large"], default="base",
